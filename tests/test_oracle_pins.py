@@ -1,0 +1,524 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: values the
+paper states, closed forms, probability theory, brute force on tiny inputs,
+hand-worked values, published generator vectors, or finite differences.
+"""
+import itertools
+import math
+import os
+import struct
+from collections import Counter
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1907_08817_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# helpers written from definitions, independent of the oracle
+# ---------------------------------------------------------------------------
+def _f64_bits(v: float) -> int:
+    return struct.unpack("<Q", struct.pack("<d", v))[0]
+
+
+def total_order_less(a: float, b: float) -> bool:
+    """IEEE 754-2019 totalOrder(a, b) and a != b, from the standard's wording:
+    -NaN < -Inf < negative finite < -0 < +0 < positive finite < +Inf < +NaN;
+    NaNs of one sign ordered by payload (more payload = farther from zero)."""
+    ba, bb = _f64_bits(a), _f64_bits(b)
+    if ba == bb:
+        return False
+    sa, sb = ba >> 63, bb >> 63
+    na, nb = math.isnan(a), math.isnan(b)
+    if na or nb:
+        # a NaN sits at the extreme of its sign
+        rank_a = (-2 if sa else 2) if na else 0
+        rank_b = (-2 if sb else 2) if nb else 0
+        if rank_a != rank_b:
+            return rank_a < rank_b
+        pa, pb = ba & ((1 << 52) - 1), bb & ((1 << 52) - 1)
+        return pa > pb if sa else pa < pb
+    if a < b:
+        return True
+    if a > b:
+        return False
+    return sa > sb  # -0 before +0
+
+
+def brute_sort_f64(xs):
+    """Selection sort under total_order_less (quadratic, for tiny inputs)."""
+    xs = list(xs)
+    for i in range(len(xs)):
+        m = i
+        for j in range(i + 1, len(xs)):
+            if total_order_less(xs[j], xs[m]):
+                m = j
+        xs[i], xs[m] = xs[m], xs[i]
+    return xs
+
+
+def bits_of(a: np.ndarray) -> list:
+    return np.ascontiguousarray(a).view(np.uint64).tolist()
+
+
+def const_model(H: int, F: float) -> dict:
+    th = np.zeros(O.num_params(H), np.float32)
+    th[-1] = F
+    return {"H": H, "lo": 0.0, "inv_range": 1.0, "theta": th}
+
+
+def random_model(H: int, seed: int, lo=0.0, inv=1.0) -> dict:
+    rng = np.random.default_rng(seed)
+    th = rng.uniform(-1, 1, O.num_params(H)).astype(np.float32)
+    th[2 * H:2 * H + H * H] /= math.sqrt(H)
+    return {"H": H, "lo": lo, "inv_range": inv, "theta": th}
+
+
+def load_tiny():
+    d = {}
+    evals = []
+    for line in open(os.path.join(GOLDEN, "tiny_mlp.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, *v = line.split()
+        if k == "eval":
+            evals.append((float(v[0]), float(v[1])))
+        else:
+            d[k] = [float(t) for t in v]
+    th = np.array(d["w1"] + d["b1"] + d["W2"] + d["b2"] + d["w3"] + d["b3"], np.float32)
+    return {"H": 2, "lo": 0.0, "inv_range": 1.0, "theta": th}, evals
+
+
+# ---------------------------------------------------------------------------
+# final output: brute force, invariants, the worked example
+# ---------------------------------------------------------------------------
+def test_worked_example_output():
+    """Sec. 2, Example: tau = 2, eps = 2 and the stated ordered result."""
+    lines = [l.split() for l in open(os.path.join(GOLDEN, "worked_example.txt"))
+             if l.strip() and not l.startswith("#")]
+    kv = {l[0]: l[1:] for l in lines}
+    tau, eps = int(kv["tau"][0]), int(kv["eps"][0])
+    A = np.array([float(v) for v in kv["input"]])
+    expect = np.array([float(v) for v in kv["output"]])
+    for model in (const_model(8, 0.5), random_model(8, 1, lo=1.0, inv=1 / 91.0),
+                  O.fit(A, H=8, sample_frac=1.0, batch=16, steps=5, seed=3)):
+        out, st = O.nnsort(A, model, eps=eps, tau=tau)
+        assert np.array_equal(out, expect)
+        assert st["rounds"] <= eps
+
+
+def test_worked_example_conflict_rule():
+    """Sec. 2, Example: 37 and 38 share a position; 38 comes first in A, so 37
+    is the element the first-arrival rule sends to the conflict array."""
+    A = np.array([32, 60, 31, 1, 81, 6, 88, 38, 3, 59, 37, 92, 91], np.float64)
+    slots = np.arange(A.size, dtype=np.uint32)       # all distinct ...
+    slots[10] = slots[7]                            # ... except 37 -> slot of 38
+    out, st = O.nnsort(A, const_model(4, 0.0), eps=1, tau=2, slots=slots)
+    assert st["collided"] == [1]
+    assert np.array_equal(out, np.sort(A))
+
+
+MULTISETS = [
+    [1.0, 1.0, 2.0, 3.0, -0.0, 0.0, float("nan")],
+    [5.0, 5.0, 5.0, -1.0, float("inf"), -float("inf")],
+    [2.0, 1.0, 3.0, 0.5, 0.25, 4.0, 8.0],
+]
+
+
+@pytest.mark.parametrize("ms", MULTISETS)
+def test_all_permutations_tiny(ms):
+    """Every permutation of small multisets, several models, vs brute force."""
+    expect = bits_of(np.array(brute_sort_f64(ms)))
+    models = [const_model(4, 0.3), random_model(4, 5, lo=-1.0, inv=0.2),
+              random_model(8, 6, lo=0.0, inv=0.1)]
+    seen = set()
+    for perm in itertools.permutations(range(len(ms))):
+        x = np.array([ms[i] for i in perm])
+        key = tuple(bits_of(x))
+        if key in seen:
+            continue
+        seen.add(key)
+        for j, model in enumerate(models):
+            out, _ = O.nnsort(x, model, eps=1 + j, tau=1)
+            assert bits_of(out) == expect
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_vs_selection_sort(seed):
+    rng = np.random.default_rng(seed)
+    n = 400
+    x = np.round(rng.standard_normal(n) * 4, 1)      # many duplicates
+    x[rng.integers(0, n, 5)] = -0.0
+    model = O.fit(x, H=8, sample_frac=0.5, batch=256, steps=3, seed=seed)
+    out, st = O.nnsort(x, model, eps=3, tau=4)
+    assert bits_of(out) == bits_of(np.array(brute_sort_f64(x.tolist())))
+
+
+def test_edge_keys_total_order():
+    x = W.edge_keys()
+    out, st = O.nnsort(x, random_model(16, 2, lo=-3.0, inv=1 / 6.0), eps=3, tau=2)
+    assert bits_of(out) == bits_of(np.array(brute_sort_f64(x.tolist())))
+    assert bits_of(O.sort_reference(x)) == bits_of(out)
+    assert bits_of(O.sort_reference_qsort(x)) == bits_of(out)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 1024, 1025])
+def test_sizes_around_tau(n):
+    x = W.lognormal(n, seed=11)
+    model = random_model(8, 3, lo=0.0, inv=0.1)
+    out, st = O.nnsort(x, model, eps=3, tau=1024)
+    assert bits_of(out) == bits_of(np.sort(x))
+    # count(w) > tau guards every round: no round at all when n <= tau
+    assert (st["rounds"] == 0) == (n <= 1024)
+    if n <= 1024:
+        assert st["residue"] == n
+
+
+def test_invariants_u64_duplicates():
+    x = W.zipf_u64(50_000, seed=3)
+    model = O.fit(x, H=16, sample_frac=0.1, batch=1024, steps=5)
+    out, st = O.nnsort(x, model)
+    assert np.all(out[1:] >= out[:-1])
+    assert Counter(out.tolist()) == Counter(x.tolist())
+
+
+# ---------------------------------------------------------------------------
+# round counts: closed forms and an invariant computed another way
+# ---------------------------------------------------------------------------
+def test_constant_model_worst_case():
+    """All keys mapped to one position (the worst case): each round stores one
+    key, so |c_r| = n - r."""
+    x = W.uniform(5000, seed=1)
+    out, st = O.nnsort(x, const_model(8, 0.5), eps=5, tau=0)
+    assert st["collided"] == [5000 - r for r in range(1, 6)]
+    assert np.array_equal(out, np.sort(x))
+
+
+def test_perfect_rank_model_no_conflicts():
+    """f = rank/n on distinct keys, m >= 1: round(m * rank) is injective, so
+    nothing collides and the polish has nothing out of order."""
+    x = W.uniform(20_000, seed=2)
+    rank = np.empty(x.size, np.int64)
+    rank[np.argsort(x)] = np.arange(x.size)
+    slots = O.slots_from_F(rank / x.size, 1.25 * x.size)
+    out, st = O.nnsort(x, const_model(4, 0.0), slots=slots)
+    assert st["collided"] == [0] and st["extracted"] == [0]
+    assert np.array_equal(out, np.sort(x))
+
+
+def test_reversed_model_all_out_of_order():
+    """A decreasing f places o_1 in descending order: only its first entry is
+    in order, every other one must be inserted."""
+    x = W.uniform(3000, seed=4)
+    rank = np.empty(x.size, np.int64)
+    rank[np.argsort(x)] = np.arange(x.size)
+    slots = O.slots_from_F((x.size - 1 - rank) / x.size, 1.25 * x.size)
+    out, st = O.nnsort(x, const_model(4, 0.0), slots=slots, eps=1, tau=0)
+    assert st["extracted"] == [st["placed"][0] - 1]
+    assert np.array_equal(out, np.sort(x))
+
+
+def test_duplicate_groups_closed_form():
+    """A group of g equal keys shares one slot and contributes max(0, g - r)."""
+    rng = np.random.default_rng(5)
+    vals = rng.permutation(300).astype(np.float64)
+    g = rng.integers(1, 7, vals.size)
+    x = rng.permutation(np.repeat(vals, g))
+    vrank = {v: i for i, v in enumerate(np.sort(vals))}
+    slots = O.slots_from_F(np.array([vrank[v] for v in x]) / vals.size, 1.25 * vals.size)
+    for eps in (1, 2, 3, 4):
+        _, st = O.nnsort(x, const_model(4, 0.0), slots=slots, eps=eps, tau=0)
+        assert st["collided"] == [int(np.maximum(0, g - r).sum()) for r in range(1, eps + 1)]
+
+
+@pytest.mark.parametrize("name", ["uniform", "lognormal", "gauss_mix"])
+def test_count_identity_from_slot_histogram(name):
+    """|c_r| = sum_s max(0, k_s - r) where k_s counts keys per slot: a property
+    of first-arrival placement that does not depend on who wins a slot."""
+    x = W.make(name, 200_000)
+    model = O.fit(x, H=16, sample_frac=0.01, batch=4096, steps=3)
+    slots = O.predict_slots(x, model)
+    k = np.bincount(slots[slots != O.UNMAPPED].astype(np.int64))
+    _, st = O.nnsort(x, model, slots=slots, tau=0)
+    assert st["collided"] == [int(np.maximum(0, k - r).sum()) for r in range(1, 4)]
+    assert st["residue"] == st["collided"][-1]
+    assert sum(st["placed"]) + st["residue"] == x.size
+
+
+def _poisson_tail(lam: float, j: int) -> float:
+    return 1.0 - sum(math.exp(-lam) * lam ** i / math.factorial(i) for i in range(j))
+
+
+def test_exact_cdf_model_poisson_rates():
+    """With the exact population CDF as f on i.i.d. continuous data, slot counts
+    are Poisson(n/S): E|c_r|/n = 1 - (S/n) sum_{j<=r} P(K >= j)
+    (= 0.3117, 0.0727, 0.0134 at m = 1.25)."""
+    n = 1_000_000
+    x = W.uniform(n, seed=8)
+    M = 1.25 * n
+    slots = O.slots_from_F(x, M)           # F(x) = x for Uniform[0, 1)
+    _, st = O.nnsort(x, const_model(4, 0.0), slots=slots, tau=0)
+    S = O.num_slots(n, 1.25)
+    lam = n / S
+    for r in range(1, 4):
+        p = 1.0 - (S / n) * sum(_poisson_tail(lam, j) for j in range(1, r + 1))
+        got = st["collided"][r - 1] / n
+        assert abs(got - p) < 6 * math.sqrt(p * (1 - p) / n) + 1e-4, (r, got, p)
+    assert abs(p - 0.0134) < 5e-4
+
+
+# ---------------------------------------------------------------------------
+# slot rounding and sizes
+# ---------------------------------------------------------------------------
+def test_slot_rounding():
+    M = 10.0
+    assert O.slot_of(0.25, M) == 3        # 2.5 -> 3 (half away from zero)
+    assert O.slot_of(0.2499999, M) == 2
+    assert O.slot_of(-0.1, M) == 0        # clamped
+    assert O.slot_of(1.7, M) == 10        # clamped to M
+    assert O.slot_of(float("nan"), M) == O.UNMAPPED
+    assert O.num_slots(10, 1.25) == 14    # round(12.5) + 1
+    assert O.num_slots(10 ** 8, 1.25) == 125_000_001
+
+
+# ---------------------------------------------------------------------------
+# model evaluators
+# ---------------------------------------------------------------------------
+def test_tiny_network_hand_values():
+    model, evals = load_tiny()
+    for x, F in evals:
+        for form in (O.FORM_FP64, O.FORM_FP32C, O.FORM_BF16W):
+            assert O.eval_F(np.array([x]), model, form)[0] == F
+
+
+def test_bf16_rounding():
+    assert O.round_bf16(1.0) == 1.0
+    assert O.round_bf16(1.0 + 2 ** -8) == 1.0                 # tie -> even
+    assert O.round_bf16(1.0 + 3 * 2 ** -8) == 1.0 + 2 ** -6   # tie -> even (up)
+    assert O.round_bf16(1.0 + 2 ** -8 + 2 ** -20) == 1.0 + 2 ** -7
+    assert O.round_bf16(-3.0) == -3.0
+
+
+def _magnitude(model, x):
+    H = model["H"]
+    th = model["theta"].astype(np.float64)
+    w1, b1 = th[:H], th[H:2 * H]
+    W2 = th[2 * H:2 * H + H * H].reshape(H, H)
+    b2, w3, b3 = th[2 * H + H * H:3 * H + H * H], th[3 * H + H * H:4 * H + H * H], th[-1]
+    a1 = np.abs(w1)[None, :] * np.abs(x)[:, None] + np.abs(b1)[None, :]
+    a2 = np.abs(b2)[None, :] + a1 @ np.abs(W2).T
+    return np.abs(b3) + a2 @ np.abs(w3)
+
+
+@pytest.mark.parametrize("H", [32, 64])
+def test_fp32_canonical_within_error_bound(H):
+    """|F_fp32c - F_fp64| <= gamma_{H+4} * (sum of |terms|) + u|F|, the standard
+    a-priori bound for FMA chains and a compensated dot product (u = 2^-24)."""
+    u = 2.0 ** -24
+    gam = (H + 4) * u / (1 - (H + 4) * u)
+    xs = np.random.default_rng(1).random(20_000)
+    for seed in range(3):
+        model = random_model(H, seed)
+        F32 = O.eval_F(xs, model, O.FORM_FP32C)
+        F64 = O.eval_F(xs, model, O.FORM_FP64)
+        bound = gam * _magnitude(model, xs) + u * np.abs(F64)
+        assert np.all(np.abs(F32 - F64) <= bound)
+
+
+def test_fp64_evaluator_is_piecewise_linear():
+    """A 1-input ReLU network is piecewise linear: between consecutive layer-1
+    and layer-2 breakpoints F(x) is affine.  The pieces are rebuilt here from
+    the weights alone (per interval: active set, then per-unit affine maps) and
+    compared with the direct FP64 evaluation."""
+    H = 16
+    model = random_model(H, 9)
+    th = model["theta"].astype(np.float64)
+    w1, b1 = th[:H], th[H:2 * H]
+    W2 = th[2 * H:2 * H + H * H].reshape(H, H)
+    b2, w3, b3 = th[2 * H + H * H:3 * H + H * H], th[3 * H + H * H:4 * H + H * H], th[-1]
+    xs = np.sort(np.random.default_rng(2).random(4000))
+    knots1 = sorted(-b1[j] / w1[j] for j in range(H) if w1[j] != 0)
+    got = O.eval_F(xs, model, O.FORM_FP64)
+    for x, F in zip(xs, got):
+        # interval of layer-1 knots containing x -> active set -> affine z2
+        active = (w1 * x + b1) > 0
+        A = W2[:, active] @ w1[active]
+        B = W2[:, active] @ b1[active] + b2
+        z2 = A * x + B
+        pw = float(b3 + np.sum(w3[z2 > 0] * (A[z2 > 0] * x + B[z2 > 0])))
+        assert abs(pw - F) <= 1e-12 * (1 + abs(F))
+    assert len(knots1) > 0
+
+
+def test_bf16w_equals_fp64_on_bf16_weights():
+    model = random_model(32, 4)
+    th = model["theta"].copy()
+    H = 32
+    th[2 * H:2 * H + H * H] = [O.round_bf16(v) for v in th[2 * H:2 * H + H * H]]
+    m2 = dict(model, theta=th)
+    xs = np.linspace(0, 1, 1001)
+    assert np.array_equal(O.eval_F(xs, m2, O.FORM_BF16W), O.eval_F(xs, m2, O.FORM_FP64))
+    assert not np.array_equal(O.eval_F(xs, model, O.FORM_BF16W), O.eval_F(xs, model, O.FORM_FP64))
+
+
+def test_translate():
+    lo, inv = 2.0, 0.25
+    x = np.array([2.0, 6.0, 4.0, 1.0, 9.0, np.nan, np.inf, -np.inf])
+    xh, ok = O.translate(x, lo, inv)
+    assert ok.tolist() == [True] * 5 + [False] * 3
+    assert xh[:5].tolist() == [0.0, 1.0, 0.5, 0.0, 1.0]
+    u = np.array([0, 2 ** 40, 2 ** 41], np.uint64)
+    xh, ok = O.translate(u, 0.0, 2.0 ** -41)
+    assert ok.all() and xh.tolist() == [0.0, 0.5, 1.0]
+
+
+# ---------------------------------------------------------------------------
+# training: gradients, Adam, Huber, generator, init
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("loss", [0, 1])
+def test_gradient_vs_central_differences(loss):
+    H = 8
+    rng = np.random.default_rng(3)
+    th = random_model(H, 7)["theta"].astype(np.float64)
+    x = rng.random(64)
+    y = rng.random(64)
+    delta = 0.2
+    L, g = O.loss_grad(th, H, x, y, loss, delta)
+    assert abs(L - O.loss_value(th, H, x, y, loss, delta)) <= 1e-14 * max(1, L)
+    checked = 0
+    for p in range(th.size):
+        h = 1e-6 * max(1.0, abs(th[p]))
+        tp, tm = th.copy(), th.copy()
+        tp[p] += h
+        tm[p] -= h
+        Lp = O.loss_value(tp, H, x, y, loss, delta)
+        Lm = O.loss_value(tm, H, x, y, loss, delta)
+        fwd, bwd = (Lp - L) / h, (L - Lm) / h
+        if abs(fwd - bwd) > 1e-4 * max(1.0, abs(fwd)):
+            continue  # a ReLU kink or the Huber threshold lies within +-h
+        cd = (Lp - Lm) / (2 * h)
+        assert abs(cd - g[p]) <= 1e-6 * max(1.0, abs(g[p])), (p, cd, g[p])
+        checked += 1
+    assert checked > 0.8 * th.size
+
+
+def test_huber_matches_paper_equation_on_constant_model():
+    """Eq. (loss): 1/2 e^2 if |e| <= delta else delta |e| - delta^2/2, with a
+    constant model F = b3 so that e = b3 - y is known in closed form."""
+    H = 4
+    th = np.zeros(O.num_params(H))
+    th[-1] = 0.5
+    y = np.array([0.1, 0.45, 0.5, 0.9, 0.55])
+    delta = 0.1
+    e = 0.5 - y
+    expect = np.where(np.abs(e) <= delta, 0.5 * e * e, delta * np.abs(e) - 0.5 * delta ** 2).mean()
+    L, g = O.loss_grad(th, H, np.zeros(y.size), y, 1, delta)
+    assert abs(L - expect) < 1e-15
+    assert abs(g[-1] - np.clip(e, -delta, delta).mean()) < 1e-15
+
+
+def test_adam_first_step_closed_form():
+    """Adam step 1: bias-corrected m = g, v = g^2, so the update is
+    -lr * g / (|g| + eps)."""
+    th = np.array([1.0, -2.0, 3.0, 0.0])
+    g = np.array([0.5, -1e-3, 0.0, 4.0])
+    m1, m2 = np.zeros(4), np.zeros(4)
+    t0 = th.copy()
+    O.adam_step(th, g, m1, m2, 1, lr=1e-3)
+    assert np.allclose(th, t0 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+
+
+def test_philox_known_answers():
+    for line in open(os.path.join(GOLDEN, "philox_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        v = [int(t, 16) for t in line.split()]
+        assert O.philox4x32_10(v[0:4], v[4:6]).tolist() == v[6:10]
+
+
+def test_sample_and_batch_indices_in_range_and_spread():
+    idx = O.sample_indices(5, 1000, 200_000)
+    assert idx.min() >= 0 and idx.max() < 1000
+    counts = np.bincount(idx, minlength=1000)
+    assert counts.min() > 120 and counts.max() < 290   # ~200 +- 6 sigma
+    b = O.batch_indices(5, 3, 77, 10_000)
+    assert b.min() >= 0 and b.max() < 77
+    assert not np.array_equal(b, O.batch_indices(5, 4, 77, 10_000))
+
+
+def test_ramp_init_interpolates_sample_cdf():
+    """Quantile-ramp initialisation: F(q_j) = j/H at the knots."""
+    x = W.lognormal(100_000, seed=1)
+    H = 16
+    s, lo, inv, xh, y = O.fit_sample(x, 0.05, 0)
+    model = O.fit(x, H=H, sample_frac=0.05, steps=0)
+    q = np.array([xh[(j * (xh.size - 1)) // H] for j in range(H + 1)])
+    F = O.eval_F(q, model, O.FORM_FP64)
+    assert np.allclose(F, np.arange(H + 1) / H, atol=2e-3)
+    assert np.all(np.diff(O.eval_F(np.linspace(0, 1, 10001), model)) >= -1e-6)
+
+
+def test_fit_reduces_loss_from_random_init():
+    x = W.uniform(20_000, seed=3)
+    model, hist = O.fit(x, H=8, sample_frac=0.5, batch=512, steps=300, lr=1e-2, init=0,
+                        return_history=True)
+    assert hist[-1] < 0.5 * hist[0]
+
+
+def test_pos_err_perfect_and_constant():
+    x = np.sort(W.uniform(10_000, seed=6))
+    ident = {"H": 1, "lo": 0.0, "inv_range": 1.0,
+             "theta": np.array([1, 0, 1, 0, 1, 0], np.float32)}   # F(x) = x
+    assert O.pos_err(x, ident) < 0.02
+    assert abs(O.pos_err(x, const_model(1, 0.0)) - 0.5) < 1e-3
+
+
+def _h1_model(w1, b1, w2, b2, w3, b3):
+    return {"H": 1, "lo": 0.0, "inv_range": 1.0,
+            "theta": np.array([w1, b1, w2, b2, w3, b3], np.float32)}
+
+
+def test_fp32_canonical_uses_two_float_input():
+    """F = relu(2^20 (x - 1/2)) at x = 1/2 + 2^-40 is exactly 2^-20; the
+    FP32-rounded input alone would give 0."""
+    model = _h1_model(2.0 ** 20, -2.0 ** 19, 1.0, 0.0, 1.0, 0.0)
+    x = np.array([0.5 + 2.0 ** -40])
+    assert O.eval_F(x, model, O.FORM_FP32C)[0] == 2.0 ** -20
+    assert O.eval_F(x, model, O.FORM_FP64)[0] == 2.0 ** -20
+
+
+def test_fp32_canonical_compensated_output():
+    """h2 = w3 = 1 + 2^-12 and b3 = -1: F = 2^-11 + 2^-24 exactly; a plain FP32
+    dot product loses the 2^-24 (the rounding error of the product)."""
+    model = _h1_model(2.0 + 2.0 ** -11, 0.0, 1.0, 0.0, 1.0 + 2.0 ** -12, -1.0)
+    x = np.array([0.5])
+    assert O.eval_F(x, model, O.FORM_FP32C)[0] == 2.0 ** -11 + 2.0 ** -24
+    assert O.eval_F(x, model, O.FORM_FP64)[0] == 2.0 ** -11 + 2.0 ** -24
+
+
+def test_equal_entries_are_in_order():
+    """Polish: an entry equal to the running maximum is appended (in order);
+    only strictly smaller ones are inserted.  o_1 = [1, 1, 0.5] -> e_1 = 1."""
+    x = np.array([1.0, 1.0, 0.5])
+    slots = np.array([0, 1, 2], np.uint32)
+    out, st = O.nnsort(x, const_model(1, 0.0), slots=slots, eps=1, tau=0)
+    assert st["extracted"] == [1]
+    assert out.tolist() == [0.5, 1.0, 1.0]
+
+
+def test_rounds_follow_processing_order():
+    """Only the first arrival is stored, and the conflict array is reprocessed
+    in the order it was appended to.  Input (value, slot): a=(0,0), b=(10,0),
+    c=(1,0), x=(0,1), d=(5,1): round 1 stores a, x; round 2 sees b, c, d and
+    stores b and d, so o_2 = [10, 5] has one entry out of order."""
+    x = np.array([0.0, 10.0, 1.0, 0.0, 5.0])
+    slots = np.array([0, 0, 0, 1, 1], np.uint32)
+    out, st = O.nnsort(x, const_model(1, 0.0), slots=slots, eps=2, tau=0)
+    assert st["collided"] == [3, 1]
+    assert st["extracted"] == [0, 1]
+    assert out.tolist() == [0.0, 0.0, 1.0, 5.0, 10.0]
