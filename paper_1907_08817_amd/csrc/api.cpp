@@ -1,0 +1,754 @@
+// C ABI of libnnsort: argument checks, workspace planning and the order of
+// kernel launches for NN-sort (Sec. 2, Procedure NN-sort and polish; Sec. 2,
+// Training).  No device memory is allocated here: every buffer is carved out
+// of the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "nnsort_internal.h"
+
+namespace nns {
+// launchers defined in the .hip translation units
+hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+hipError_t fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
+hipError_t launch_classify(const uint32_t* d_cnt, int64_t NB, int64_t big_max, int32_t* d_bigmap,
+                           uint64_t* d_moff, int32_t* d_seglist, int32_t* d_bigbucket,
+                           uint64_t* d_counters, hipStream_t st);
+hipError_t launch_big_buckets(const int32_t* d_bigbucket, int64_t big_count, const int32_t* d_bigmap,
+                              const uint64_t* d_region_key, const uint64_t* d_region_meta,
+                              const SpillEntry* d_spill, int64_t spill_count, uint32_t* d_big_hist,
+                              uint64_t* d_G, uint64_t* d_counters, int eps, hipStream_t st);
+hipError_t launch_bucket_polish(const uint32_t* d_cnt, const uint64_t* d_moff, int64_t NB,
+                                const uint64_t* d_region_key, const uint64_t* d_region_meta, int eps,
+                                void* d_M, bool M_is_bits, bool is_f64, uint64_t* d_segmin,
+                                uint64_t* d_segmax, uint64_t* d_counters, hipStream_t st);
+hipError_t launch_boundary_plan(const void* d_M, bool M_is_bits, bool is_f64, const uint64_t* d_moff,
+                                const uint32_t* d_cnt, const int32_t* d_seglist, int64_t K,
+                                const uint64_t* d_segmin, const uint64_t* d_segmax, void* d_zones,
+                                uint64_t* d_counters, hipStream_t st);
+hipError_t launch_boundary_merge(void* d_M, bool M_is_bits, bool is_f64, const void* d_zones, int64_t K,
+                                 hipStream_t st);
+size_t zone_bytes();
+hipError_t launch_pos_err_sum(const double* d_F, int64_t n, double* d_sum, hipStream_t st);
+// fit
+hipError_t launch_sample(const void* d_in, int64_t n, bool is_f64, uint64_t seed, int64_t k, uint64_t* d_out,
+                         uint64_t* d_count, hipStream_t st);
+hipError_t launch_make_xy(const uint64_t* d_sorted, int64_t k, bool is_f64, double lo, double inv, double* d_x,
+                          float* d_y, hipStream_t st);
+hipError_t launch_init(float* d_theta, int H, int init, uint64_t seed, const double* d_x, int64_t k,
+                       hipStream_t st);
+hipError_t launch_batch(const double* d_x, const float* d_y, int64_t k, uint64_t seed, int64_t step, int64_t B,
+                        double* d_bx, float* d_by, hipStream_t st);
+size_t mlp_backward_ws_floats(int H, int64_t B);
+size_t loss_ws_floats();
+hipError_t launch_loss_grad(const float* d_F, const float* d_y, int64_t B, int loss, float delta, float* d_gF,
+                            float* d_loss, float* d_partial, hipStream_t st);
+}  // namespace nns
+
+using namespace nns;
+
+namespace {
+
+thread_local char g_last_error[256] = "";
+
+int fail_hip(hipError_t e, const char* where) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s", where, hipGetErrorString(e));
+    return NNSORT_EHIP;
+}
+
+#define NNS_HIP(call)                                   \
+    do {                                                \
+        hipError_t _e = (call);                         \
+        if (_e != hipSuccess) return fail_hip(_e, #call); \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int64_t num_slots(int64_t n, double m) {
+    double M = m * (double)n;
+    double t = std::trunc(M);
+    if (M - t >= 0.5) t += 1.0;
+    return (int64_t)t + 1;
+}
+
+bool valid_sort_params(const nnsort_sort_params* p, int64_t n) {
+    if (!p) return false;
+    if (!(p->m > 0.0) || !std::isfinite(p->m)) return false;
+    if (p->eps < 1 || p->eps > NNSORT_MAX_EPS) return false;
+    if (p->tau < 0) return false;
+    if (p->form != NNSORT_FORM_FP32 && p->form != NNSORT_FORM_BF16) return false;
+    if (p->bf16_terms < 1 || p->bf16_terms > 3) return false;
+    if (n >= (int64_t)0xFFFFFFFF) return false;
+    if (p->m * (double)n >= 4294967294.0) return false;
+    return true;
+}
+
+int model_width(int H) { return H <= 32 ? 32 : 64; }
+
+int check_model(const nnsort_model* m) {
+    if (!m) return NNSORT_EINVAL;
+    if (m->version != NNSORT_ABI_VERSION || m->hidden < 1 || m->hidden > NNSORT_MAX_HIDDEN) return NNSORT_EMODEL;
+    return NNSORT_OK;
+}
+
+// Device layout of the model, zero-padded to a width of 32 or 64.
+void to_dev_model(const nnsort_model* m, DevModel* d) {
+    std::memset(d, 0, sizeof(*d));
+    int H = m->hidden, HP = model_width(H);
+    d->H = HP;
+    d->H_true = H;
+    d->lo = m->lo;
+    d->inv_range = m->inv_range;
+    for (int j = 0; j < H; ++j) {
+        d->w1[j] = m->w1[j];
+        d->b1[j] = m->b1[j];
+        d->b2[j] = m->b2[j];
+        d->w3[j] = m->w3[j];
+        for (int k = 0; k < H; ++k) d->w2[j * HP + k] = m->w2[j * H + k];
+    }
+    d->b3 = m->b3;
+}
+
+}  // namespace
+
+namespace nns {
+
+SortPlan plan_sort(int64_t n, double m) {
+    SortPlan p{};
+    p.n = n;
+    p.S = num_slots(n, m);
+    p.NB = (p.S + kBucketSlots - 1) / kBucketSlots;
+    p.big_max = n / (kBucketCap + 1) + 1;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o += align256(bytes);
+        return at;
+    };
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    p.off_counters = take(kNumCounters * 8);
+    p.off_cnt = take((size_t)p.NB * 4);
+    p.off_region_key = take((size_t)p.NB * kBucketCap * 8);
+    p.off_region_meta = take((size_t)p.NB * kBucketCap * 8);
+    p.off_spill = take(nn * sizeof(SpillEntry));
+    p.off_bucket_info = take((size_t)p.NB * (4 + 8 + 4) + (size_t)p.big_max * 4);
+    p.off_segminmax = take((size_t)p.NB * 16 + (size_t)p.NB * zone_bytes());
+    p.off_G = take(nn * 8);
+    p.off_M = take(nn * 8);
+    p.off_big_hist = take((size_t)p.big_max * kBucketSlots * 4);
+    p.off_model = take(sizeof(DevModel));
+    p.radix_bytes = radix_ws_bytes(n);
+    p.off_radix = take(p.radix_bytes);
+    p.total = o;
+    return p;
+}
+
+}  // namespace nns
+
+namespace {
+
+struct Events {
+    hipEvent_t e[7] = {};
+    bool on = false;
+    hipStream_t st = nullptr;
+    explicit Events(bool enable, hipStream_t s) : on(enable), st(s) {
+        if (!on) return;
+        for (auto& x : e)
+            if (hipEventCreate(&x) != hipSuccess) x = nullptr;
+    }
+    void mark(int i) {
+        if (on && e[i]) (void)hipEventRecord(e[i], st);
+    }
+    double ms(int a, int b) {
+        float t = 0.0f;
+        if (!on || !e[a] || !e[b]) return 0.0;
+        if (hipEventElapsedTime(&t, e[a], e[b]) != hipSuccess) return 0.0;
+        return (double)t;
+    }
+    ~Events() {
+        if (!on) return;
+        for (auto& x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
+// Conventional sort of everything (no round runs when n <= tau).
+int plain_sort(const void* d_in, void* d_out, int64_t n, bool is_f64, void* d_ws, size_t ws_bytes,
+               hipStream_t st) {
+    int mode = is_f64 ? 1 : 2;
+    if (ws_bytes < radix_ws_bytes(n)) return NNSORT_EWORKSPACE;
+    NNS_HIP(radix_sort((const uint64_t*)d_in, (uint64_t*)d_out, n, mode, mode, d_ws, ws_bytes, st));
+    return NNSORT_OK;
+}
+
+int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void* d_in, void* d_out, int64_t n,
+              nnsort_dtype dtype, const nnsort_sort_params* prm, void* d_ws, size_t ws_bytes, nnsort_stats* stats,
+              hipStream_t st) {
+    if (n < 0 || (n > 0 && (!d_in || !d_out))) return NNSORT_EINVAL;
+    if (dtype != NNSORT_F64 && dtype != NNSORT_U64) return NNSORT_EINVAL;
+    if (!valid_sort_params(prm, n)) return NNSORT_EINVAL;
+    if (model) {
+        int rc = check_model(model);
+        if (rc) return rc;
+    }
+    if (n > 0) {
+        const char* a = (const char*)d_in;
+        const char* b = (const char*)d_out;
+        if (a < b + n * 8 && b < a + n * 8) return NNSORT_EINVAL;  // overlapping buffers
+    }
+    const bool is_f64 = dtype == NNSORT_F64;
+    const int eps = prm->eps;
+    nnsort_stats S{};
+    S.n = n;
+    S.form = prm->form;
+    Events ev(stats && prm->stats_level >= 1, st);
+    ev.mark(0);
+    if (n == 0) {
+        if (stats) *stats = S;
+        return NNSORT_OK;
+    }
+    if (n <= prm->tau) {  // count(w) > tau fails at once: conventional sort only
+        int rc = plain_sort(d_in, d_out, n, is_f64, d_ws, ws_bytes, st);
+        if (rc) return rc;
+        ev.mark(6);
+        NNS_HIP(hipStreamSynchronize(st));
+        S.rounds = 0;
+        S.residue = n;
+        S.t_total_ms = ev.ms(0, 6);
+        if (stats) *stats = S;
+        return NNSORT_OK;
+    }
+
+    SortPlan P = plan_sort(n, prm->m);
+    if (!d_ws || ws_bytes < P.total) return NNSORT_EWORKSPACE;
+    char* ws = (char*)d_ws;
+    uint64_t* counters = (uint64_t*)(ws + P.off_counters);
+    uint32_t* cnt = (uint32_t*)(ws + P.off_cnt);
+    uint64_t* rkey = (uint64_t*)(ws + P.off_region_key);
+    uint64_t* rmeta = (uint64_t*)(ws + P.off_region_meta);
+    SpillEntry* spill = (SpillEntry*)(ws + P.off_spill);
+    int32_t* bigmap = (int32_t*)(ws + P.off_bucket_info);
+    uint64_t* moff = (uint64_t*)(ws + P.off_bucket_info + align256((size_t)P.NB * 4));
+    int32_t* seglist = (int32_t*)((char*)moff + align256((size_t)P.NB * 8));
+    int32_t* bigbucket = (int32_t*)((char*)seglist + align256((size_t)P.NB * 4));
+    uint64_t* segmin = (uint64_t*)(ws + P.off_segminmax);
+    uint64_t* segmax = segmin + P.NB;
+    void* zones = (void*)(segmax + P.NB);
+    uint64_t* G = (uint64_t*)(ws + P.off_G);
+    uint64_t* Mbuf = (uint64_t*)(ws + P.off_M);
+    uint32_t* big_hist = (uint32_t*)(ws + P.off_big_hist);
+    DevModel* dmodel = (DevModel*)(ws + P.off_model);
+    void* radix_ws = ws + P.off_radix;
+    // the bucket_info carve-up must fit its reservation
+    if ((char*)(bigbucket + P.big_max) > ws + P.off_segminmax) return NNSORT_EINTERNAL;
+
+    NNS_HIP(fill_u64(counters, kNumCounters, 0, st));
+    NNS_HIP(fill_u32(cnt, P.NB, 0, st));
+    DevModel hm;
+    int HP = 32;
+    if (model) {
+        to_dev_model(model, &hm);
+        HP = hm.H;
+        NNS_HIP(hipMemcpyAsync(dmodel, &hm, sizeof(hm), hipMemcpyHostToDevice, st));
+    }
+
+    // ---- input phase + map + hand-off to slot-range buckets ----
+    InferArgs ia{};
+    ia.model = dmodel;
+    ia.in = (const uint64_t*)d_in;
+    ia.n = n;
+    ia.is_f64 = is_f64 ? 1 : 0;
+    ia.M = prm->m * (double)n;
+    ia.S = P.S;
+    ia.given_slots = given_slots;
+    ia.scatter = 1;
+    ia.cnt = cnt;
+    ia.region_key = rkey;
+    ia.region_meta = rmeta;
+    ia.spill = spill;
+    ia.counters = (unsigned long long*)counters;
+    NNS_HIP(launch_infer(ia, HP, prm->form, prm->bf16_terms, st));
+    ev.mark(1);
+    NNS_HIP(launch_classify(cnt, P.NB, P.big_max, bigmap, moff, seglist, bigbucket, counters, st));
+    uint64_t c[kNumCounters];
+    NNS_HIP(hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, st));
+    NNS_HIP(hipStreamSynchronize(st));
+    if (c[kCntBadSlot]) return NNSORT_EINVAL;
+    const int64_t big_count = (int64_t)c[kCntBigBuckets];
+    const int64_t G_size = (int64_t)(c[kCntBigKeys] + c[kCntUnmapped]);
+    const int64_t spill_count = (int64_t)c[kCntSpill];
+    if (big_count > P.big_max) return NNSORT_EINTERNAL;
+
+    // ---- slot ranges too dense for LDS, and keys without a slot: to G ----
+    if (G_size > 0)
+        NNS_HIP(launch_big_buckets(bigbucket, big_count, bigmap, rkey, rmeta, spill, spill_count, big_hist, G,
+                                   counters, eps, st));
+    ev.mark(2);
+    // ---- rounds + polish of each slot range in LDS ----
+    const bool M_is_bits = G_size == 0;
+    void* M = M_is_bits ? d_out : (void*)Mbuf;
+    const int64_t M_len = n - G_size;
+    NNS_HIP(launch_bucket_polish(cnt, moff, P.NB, rkey, rmeta, eps, M, M_is_bits, is_f64, segmin, segmax,
+                                 counters, st));
+    const int64_t K = (int64_t)c[kCntSmallBuckets];
+    NNS_HIP(launch_boundary_plan(M, M_is_bits, is_f64, moff, cnt, seglist, K, segmin, segmax, zones, counters,
+                                 st));
+    NNS_HIP(hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, st));
+    NNS_HIP(hipStreamSynchronize(st));
+    if (c[kCntFallback]) {
+        const int mode = M_is_bits ? (is_f64 ? 1 : 2) : 0;
+        if (P.radix_bytes < radix_ws_bytes(M_len)) return NNSORT_EINTERNAL;
+        NNS_HIP(radix_sort((const uint64_t*)M, (uint64_t*)M, M_len, mode, mode, radix_ws, P.radix_bytes, st));
+    } else {
+        NNS_HIP(launch_boundary_merge(M, M_is_bits, is_f64, zones, K, st));
+    }
+    ev.mark(3);
+    // ---- last conflict array (and dense ranges): conventional sort, merge ----
+    if (G_size > 0) {
+        NNS_HIP(radix_sort(G, G, G_size, 0, 0, radix_ws, P.radix_bytes, st));
+        ev.mark(4);
+        NNS_HIP(launch_merge(Mbuf, M_len, G, G_size, (uint64_t*)d_out, is_f64 ? 1 : 2, st));
+    } else {
+        ev.mark(4);
+    }
+    ev.mark(5);
+
+    // ---- statistics ----
+    NNS_HIP(hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, st));
+    NNS_HIP(hipStreamSynchronize(st));
+    // while i < eps and count(w) > tau: the rounds were computed for all eps;
+    // the procedure stops at the first round whose conflict array is <= tau.
+    int t = 1;
+    int64_t unm = (int64_t)c[kCntUnmapped];
+    while (t < eps && (int64_t)c[kCntCollided + t - 1] + unm > prm->tau) ++t;
+    S.rounds = t;
+    for (int r = 0; r < t; ++r) {
+        S.collided[r] = (int64_t)c[kCntCollided + r] + unm;
+        S.placed[r] = (int64_t)c[kCntPlaced + r];
+    }
+    S.residue = S.collided[t - 1];
+    S.unmapped = unm;
+    S.big_buckets = big_count;
+    S.big_bucket_keys = (int64_t)c[kCntBigKeys];
+    S.boundary_keys = (int64_t)c[kCntBoundary];
+    S.fallback = c[kCntFallback] ? 1 : 0;
+    if (stats && prm->stats_level >= 2 && model) {
+        double* Fbuf = (double*)rkey;  // region storage is free now
+        InferArgs pa = ia;
+        pa.in = (const uint64_t*)d_out;
+        pa.given_slots = nullptr;
+        pa.scatter = 0;
+        pa.F_out = Fbuf;
+        pa.slots_out = nullptr;
+        NNS_HIP(launch_infer(pa, HP, prm->form, prm->bf16_terms, st));
+        double* dsum = (double*)counters + kCntPosErrSum;
+        NNS_HIP(launch_pos_err_sum(Fbuf, n, dsum, st));
+        NNS_HIP(hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, st));
+        NNS_HIP(hipStreamSynchronize(st));
+        double sum;
+        std::memcpy(&sum, &c[kCntPosErrSum], 8);
+        int64_t cntm = (int64_t)c[kCntPosErrCnt];
+        S.pos_err = cntm ? sum / (double)cntm / (double)n : 0.0;
+    }
+    ev.mark(6);
+    if (ev.on) {
+        NNS_HIP(hipEventSynchronize(ev.e[6]));
+        S.t_infer_ms = ev.ms(0, 1);
+        S.t_place_ms = ev.ms(1, 2);
+        S.t_polish_ms = ev.ms(2, 3);
+        S.t_residue_ms = ev.ms(3, 4);
+        S.t_merge_ms = ev.ms(4, 5);
+        S.t_total_ms = ev.ms(0, 5);
+    }
+    if (stats) *stats = S;
+    return NNSORT_OK;
+}
+
+// ---- fit workspace ----
+struct FitPlan {
+    int64_t k, B;
+    int H;
+    size_t off_sample, off_count, off_x, off_y, off_bx, off_by, off_F, off_gF, off_saved, off_bws, off_theta,
+        off_grad, off_m1, off_m2, off_loss, off_lpart, off_radix, total;
+};
+
+int64_t sample_count(int64_t n, double frac) {
+    double v = std::floor(frac * (double)n + 0.5);
+    return v < 1.0 ? 1 : (int64_t)v;
+}
+
+FitPlan plan_fit(int64_t n, const nnsort_fit_params* fp) {
+    FitPlan p{};
+    p.k = sample_count(n, fp->sample_frac);
+    p.B = fp->batch;
+    p.H = fp->hidden;
+    int P = p.H * p.H + 4 * p.H + 1;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o += align256(bytes);
+        return at;
+    };
+    p.off_sample = take((size_t)p.k * 8);
+    p.off_count = take(64);
+    p.off_x = take((size_t)p.k * 8);
+    p.off_y = take((size_t)p.k * 4);
+    p.off_bx = take((size_t)p.B * 8);
+    p.off_by = take((size_t)p.B * 4);
+    p.off_F = take((size_t)p.B * 4);
+    p.off_gF = take((size_t)p.B * 4);
+    p.off_saved = take((size_t)p.B * 2 * p.H * 4);
+    p.off_bws = take(mlp_backward_ws_floats(p.H, p.B) * 4);
+    p.off_theta = take((size_t)P * 4);
+    p.off_grad = take((size_t)P * 4);
+    p.off_m1 = take((size_t)P * 4);
+    p.off_m2 = take((size_t)P * 4);
+    p.off_loss = take(64);
+    p.off_lpart = take(loss_ws_floats() * 4);
+    p.off_radix = take(radix_ws_bytes(p.k));
+    p.total = o;
+    return p;
+}
+
+bool valid_fit_params(const nnsort_fit_params* f) {
+    if (!f) return false;
+    if (f->hidden != 8 && f->hidden != 16 && f->hidden != 32 && f->hidden != 64) return false;
+    if (!(f->sample_frac > 0.0) || f->sample_frac > 1.0e6) return false;
+    if (f->batch < 1 || f->steps < 0) return false;
+    if (f->loss != 0 && f->loss != 1) return false;
+    if (f->init != 0 && f->init != 1) return false;
+    if (!std::isfinite(f->lr)) return false;
+    return true;
+}
+
+int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit_params* fp, nnsort_model* out,
+             void* d_ws, size_t ws_bytes, hipStream_t st, float* loss_history, int history_len) {
+    if (n < 1 || !d_keys || !out || !valid_fit_params(fp)) return NNSORT_EINVAL;
+    if (dtype != NNSORT_F64 && dtype != NNSORT_U64) return NNSORT_EINVAL;
+    if (n >= (int64_t)0xFFFFFFFF) return NNSORT_EINVAL;
+    FitPlan P = plan_fit(n, fp);
+    if (!d_ws || ws_bytes < P.total) return NNSORT_EWORKSPACE;
+    const bool is_f64 = dtype == NNSORT_F64;
+    char* ws = (char*)d_ws;
+    uint64_t* sample = (uint64_t*)(ws + P.off_sample);
+    uint64_t* count = (uint64_t*)(ws + P.off_count);
+    double* x = (double*)(ws + P.off_x);
+    float* y = (float*)(ws + P.off_y);
+    double* bx = (double*)(ws + P.off_bx);
+    float* by = (float*)(ws + P.off_by);
+    float* F = (float*)(ws + P.off_F);
+    float* gF = (float*)(ws + P.off_gF);
+    float* saved = (float*)(ws + P.off_saved);
+    float* bws = (float*)(ws + P.off_bws);
+    float* theta = (float*)(ws + P.off_theta);
+    float* grad = (float*)(ws + P.off_grad);
+    float* m1 = (float*)(ws + P.off_m1);
+    float* m2 = (float*)(ws + P.off_m2);
+    float* dloss = (float*)(ws + P.off_loss);
+    float* lpart = (float*)(ws + P.off_lpart);
+    void* rws = ws + P.off_radix;
+    const int H = fp->hidden;
+    const int Pn = H * H + 4 * H + 1;
+
+    NNS_HIP(fill_u64(count, 1, 0, st));
+    NNS_HIP(launch_sample(d_keys, n, is_f64, fp->seed, P.k, sample, count, st));
+    uint64_t k2 = 0;
+    NNS_HIP(hipMemcpyAsync(&k2, count, 8, hipMemcpyDeviceToHost, st));
+    NNS_HIP(hipStreamSynchronize(st));
+    nnsort_model M{};
+    M.version = NNSORT_ABI_VERSION;
+    M.hidden = H;
+    if (k2 == 0) {  // no finite key: a constant model sends every key to slot 0
+        *out = M;
+        return NNSORT_OK;
+    }
+    NNS_HIP(radix_sort(sample, sample, (int64_t)k2, 0, 0, rws, radix_ws_bytes(P.k), st));
+    uint64_t ends[2];
+    NNS_HIP(hipMemcpyAsync(&ends[0], sample, 8, hipMemcpyDeviceToHost, st));
+    NNS_HIP(hipMemcpyAsync(&ends[1], sample + (k2 - 1), 8, hipMemcpyDeviceToHost, st));
+    NNS_HIP(hipStreamSynchronize(st));
+    auto value_of = [&](uint64_t okey) {
+        if (!is_f64) return (double)okey;
+        uint64_t b = (okey >> 63) ? (okey & 0x7FFFFFFFFFFFFFFFull) : ~okey;
+        double d;
+        std::memcpy(&d, &b, 8);
+        return d;
+    };
+    double lo = value_of(ends[0]), hi = value_of(ends[1]);
+    double inv = hi > lo ? 1.0 / (hi - lo) : 0.0;
+    NNS_HIP(launch_make_xy(sample, (int64_t)k2, is_f64, lo, inv, x, y, st));
+    NNS_HIP(launch_init(theta, H, fp->init, fp->seed, x, (int64_t)k2, st));
+    NNS_HIP(hipMemsetAsync(m1, 0, (size_t)Pn * 4, st));
+    NNS_HIP(hipMemsetAsync(m2, 0, (size_t)Pn * 4, st));
+    for (int t = 1; t <= fp->steps; ++t) {
+        NNS_HIP(launch_batch(x, y, (int64_t)k2, fp->seed, t, P.B, bx, by, st));
+        NNS_HIP(launch_mlp_forward(H, theta, bx, P.B, F, saved, st));
+        NNS_HIP(launch_loss_grad(F, by, P.B, fp->loss, fp->huber_delta, gF, dloss, lpart, st));
+        if (loss_history && t - 1 < history_len)
+            NNS_HIP(hipMemcpyAsync(loss_history + (t - 1), dloss, 4, hipMemcpyDeviceToHost, st));
+        NNS_HIP(launch_mlp_backward(H, theta, bx, P.B, saved, gF, grad, bws, st));
+        NNS_HIP(launch_adam(theta, grad, m1, m2, Pn, t, fp->lr, 0.9f, 0.999f, 1e-8f, st));
+    }
+    std::vector<float> th((size_t)Pn);
+    NNS_HIP(hipMemcpyAsync(th.data(), theta, (size_t)Pn * 4, hipMemcpyDeviceToHost, st));
+    NNS_HIP(hipStreamSynchronize(st));
+    M.lo = lo;
+    M.inv_range = inv;
+    for (int j = 0; j < H; ++j) {
+        M.w1[j] = th[j];
+        M.b1[j] = th[H + j];
+        M.b2[j] = th[2 * H + H * H + j];
+        M.w3[j] = th[3 * H + H * H + j];
+    }
+    for (int e = 0; e < H * H; ++e) M.w2[e] = th[2 * H + e];
+    M.b3 = th[4 * H + H * H];
+    *out = M;
+    return NNSORT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void nnsort_default_params(nnsort_sort_params* sp, nnsort_fit_params* fp) {
+    if (sp) {
+        std::memset(sp, 0, sizeof(*sp));
+        sp->m = 1.25;
+        sp->eps = 3;
+        sp->form = NNSORT_FORM_FP32;
+        sp->tau = 1024;
+        sp->bf16_terms = 3;
+        sp->stats_level = 1;
+    }
+    if (fp) {
+        std::memset(fp, 0, sizeof(*fp));
+        fp->hidden = 32;
+        fp->batch = 65536;
+        fp->sample_frac = 0.01;
+        fp->steps = 200;
+        fp->lr = 1e-7f;
+        fp->seed = 0;
+        fp->loss = 0;
+        fp->huber_delta = 1.0f;
+        fp->init = 1;
+    }
+}
+
+int nnsort_workspace_size(int64_t n, nnsort_dtype dtype, const nnsort_sort_params* sp,
+                          const nnsort_fit_params* fp, size_t* bytes) {
+    if (!bytes || n < 0 || !sp) return NNSORT_EINVAL;
+    if (dtype != NNSORT_F64 && dtype != NNSORT_U64) return NNSORT_EINVAL;
+    if (!valid_sort_params(sp, n)) return NNSORT_EINVAL;
+    size_t need = align256(radix_ws_bytes(n));
+    if (n > sp->tau) {
+        SortPlan P = plan_sort(n, sp->m);
+        need = P.total > need ? P.total : need;
+    }
+    need = need > align256(sizeof(DevModel)) ? need : align256(sizeof(DevModel));
+    if (fp) {
+        if (!valid_fit_params(fp)) return NNSORT_EINVAL;
+        FitPlan F = plan_fit(n > 0 ? n : 1, fp);
+        need = F.total > need ? F.total : need;
+    }
+    *bytes = need;
+    return NNSORT_OK;
+}
+
+int nnsort_fit(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit_params* params,
+               nnsort_model* out, void* d_ws, size_t ws_bytes, void* stream) {
+    return fit_impl(d_keys, n, dtype, params, out, d_ws, ws_bytes, (hipStream_t)stream, nullptr, 0);
+}
+
+int nnsort_fit_history(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit_params* params,
+                       nnsort_model* out, void* d_ws, size_t ws_bytes, float* loss_history, int history_len,
+                       void* stream) {
+    return fit_impl(d_keys, n, dtype, params, out, d_ws, ws_bytes, (hipStream_t)stream, loss_history,
+                    history_len);
+}
+
+int nnsort_sort_with_model(const nnsort_model* model, const void* d_in, void* d_out, int64_t n,
+                           nnsort_dtype dtype, const nnsort_sort_params* params, void* d_ws, size_t ws_bytes,
+                           nnsort_stats* stats, void* stream) {
+    if (!model) return NNSORT_EINVAL;
+    return sort_impl(model, nullptr, d_in, d_out, n, dtype, params, d_ws, ws_bytes, stats, (hipStream_t)stream);
+}
+
+int nnsort_sort_with_slots(const uint32_t* d_slots, const void* d_in, void* d_out, int64_t n, nnsort_dtype dtype,
+                           const nnsort_sort_params* params, void* d_ws, size_t ws_bytes, nnsort_stats* stats,
+                           void* stream) {
+    if (n > 0 && !d_slots) return NNSORT_EINVAL;
+    return sort_impl(nullptr, d_slots, d_in, d_out, n, dtype, params, d_ws, ws_bytes, stats, (hipStream_t)stream);
+}
+
+int nnsort_sort(const void* d_in, void* d_out, int64_t n, nnsort_dtype dtype, const nnsort_fit_params* fp,
+                const nnsort_sort_params* sp, void* d_ws, size_t ws_bytes, nnsort_model* model_out,
+                nnsort_stats* stats, void* stream) {
+    if (n < 0 || !fp || !sp) return NNSORT_EINVAL;
+    if (n == 0) {
+        if (stats) std::memset(stats, 0, sizeof(*stats));
+        return NNSORT_OK;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    Events ev(stats != nullptr, st);
+    ev.mark(0);
+    nnsort_model m;
+    int rc = fit_impl(d_in, n, dtype, fp, &m, d_ws, ws_bytes, st, nullptr, 0);
+    if (rc) return rc;
+    ev.mark(1);
+    rc = sort_impl(&m, nullptr, d_in, d_out, n, dtype, sp, d_ws, ws_bytes, stats, st);
+    if (rc) return rc;
+    ev.mark(2);
+    if (model_out) *model_out = m;
+    if (stats && ev.on) {
+        NNS_HIP(hipEventSynchronize(ev.e[2]));
+        stats->t_total_ms = ev.ms(0, 2);
+    }
+    return NNSORT_OK;
+}
+
+size_t nnsort_model_device_bytes(void) { return align256(sizeof(DevModel)); }
+
+int nnsort_predict(const nnsort_model* model, const void* d_in, int64_t n, nnsort_dtype dtype,
+                   const nnsort_sort_params* params, uint32_t* d_slots, double* d_F, void* d_ws, size_t ws_bytes,
+                   void* stream) {
+    int rc = check_model(model);
+    if (rc) return rc;
+    if (n < 0 || (n > 0 && !d_in) || !valid_sort_params(params, n)) return NNSORT_EINVAL;
+    if (dtype != NNSORT_F64 && dtype != NNSORT_U64) return NNSORT_EINVAL;
+    if (!d_ws || ws_bytes < sizeof(DevModel)) return NNSORT_EWORKSPACE;
+    if (n == 0) return NNSORT_OK;
+    hipStream_t st = (hipStream_t)stream;
+    DevModel hm;
+    to_dev_model(model, &hm);
+    NNS_HIP(hipMemcpyAsync(d_ws, &hm, sizeof(hm), hipMemcpyHostToDevice, st));
+    InferArgs ia{};
+    ia.model = (const DevModel*)d_ws;
+    ia.in = (const uint64_t*)d_in;
+    ia.n = n;
+    ia.is_f64 = dtype == NNSORT_F64;
+    ia.M = params->m * (double)n;
+    ia.S = num_slots(n, params->m);
+    ia.slots_out = d_slots;
+    ia.F_out = d_F;
+    ia.scatter = 0;
+    NNS_HIP(launch_infer(ia, hm.H, params->form, params->bf16_terms, st));
+    NNS_HIP(hipStreamSynchronize(st));
+    return NNSORT_OK;
+}
+
+size_t nnsort_radix_workspace_size(int64_t n) { return radix_ws_bytes(n); }
+
+int nnsort_radix_sort(const void* d_in, void* d_out, int64_t n, nnsort_dtype dtype, void* d_ws, size_t ws_bytes,
+                      void* stream) {
+    if (n < 0 || (n > 0 && (!d_in || !d_out))) return NNSORT_EINVAL;
+    if (dtype != NNSORT_F64 && dtype != NNSORT_U64) return NNSORT_EINVAL;
+    if (n >= (int64_t)0xFFFFFFFF) return NNSORT_EINVAL;
+    if (n == 0) return NNSORT_OK;
+    if (!d_ws || ws_bytes < radix_ws_bytes(n)) return NNSORT_EWORKSPACE;
+    int mode = dtype == NNSORT_F64 ? 1 : 2;
+    NNS_HIP(radix_sort((const uint64_t*)d_in, (uint64_t*)d_out, n, mode, mode, d_ws, ws_bytes, (hipStream_t)stream));
+    return NNSORT_OK;
+}
+
+size_t nnsort_mlp_saved_floats(int hidden, int64_t batch) { return (size_t)batch * 2 * hidden; }
+size_t nnsort_mlp_backward_ws_floats(int hidden, int64_t batch) { return mlp_backward_ws_floats(hidden, batch); }
+
+static bool fit_width(int H) { return H == 8 || H == 16 || H == 32 || H == 64; }
+
+int nnsort_mlp_forward(int hidden, const float* d_theta, const double* d_x, int64_t batch, float* d_F,
+                       float* d_saved, void* stream) {
+    if (!fit_width(hidden) || batch < 0 || (batch > 0 && (!d_theta || !d_x || !d_F))) return NNSORT_EINVAL;
+    if (batch == 0) return NNSORT_OK;
+    NNS_HIP(launch_mlp_forward(hidden, d_theta, d_x, batch, d_F, d_saved, (hipStream_t)stream));
+    return NNSORT_OK;
+}
+
+int nnsort_mlp_backward(int hidden, const float* d_theta, const double* d_x, int64_t batch, const float* d_saved,
+                        const float* d_gF, float* d_gtheta, float* d_ws, void* stream) {
+    if (!fit_width(hidden) || batch < 1 || !d_theta || !d_x || !d_saved || !d_gF || !d_gtheta || !d_ws)
+        return NNSORT_EINVAL;
+    NNS_HIP(launch_mlp_backward(hidden, d_theta, d_x, batch, d_saved, d_gF, d_gtheta, d_ws, (hipStream_t)stream));
+    return NNSORT_OK;
+}
+
+size_t nnsort_loss_ws_floats(void) { return loss_ws_floats(); }
+
+int nnsort_loss_grad(const float* d_F, const float* d_y, int64_t batch, int loss, float delta, float* d_gF,
+                        float* d_loss, float* d_ws, void* stream) {
+    if (batch < 1 || !d_F || !d_y || !d_gF || !d_loss || !d_ws || (loss != 0 && loss != 1)) return NNSORT_EINVAL;
+    NNS_HIP(launch_loss_grad(d_F, d_y, batch, loss, delta, d_gF, d_loss, d_ws, (hipStream_t)stream));
+    return NNSORT_OK;
+}
+
+int nnsort_adam_step(float* d_theta, const float* d_g, float* d_m1, float* d_m2, int64_t count, int64_t t,
+                     float lr, float beta1, float beta2, float eps, void* stream) {
+    if (count < 0 || t < 1 || (count > 0 && (!d_theta || !d_g || !d_m1 || !d_m2))) return NNSORT_EINVAL;
+    if (count == 0) return NNSORT_OK;
+    NNS_HIP(launch_adam(d_theta, d_g, d_m1, d_m2, count, t, lr, beta1, beta2, eps, (hipStream_t)stream));
+    return NNSORT_OK;
+}
+
+int nnsort_model_save(const nnsort_model* m, const char* path) {
+    int rc = check_model(m);
+    if (rc) return rc;
+    if (!path) return NNSORT_EINVAL;
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return NNSORT_EIO;
+    const char magic[4] = {'N', 'N', 'S', 'M'};
+    int32_t hdr[2] = {m->version, m->hidden};
+    double aff[2] = {m->lo, m->inv_range};
+    int H = m->hidden;
+    bool ok = std::fwrite(magic, 1, 4, f) == 4 && std::fwrite(hdr, 4, 2, f) == 2 && std::fwrite(aff, 8, 2, f) == 2 &&
+              std::fwrite(m->w1, 4, H, f) == (size_t)H && std::fwrite(m->b1, 4, H, f) == (size_t)H &&
+              std::fwrite(m->w2, 4, (size_t)H * H, f) == (size_t)H * H && std::fwrite(m->b2, 4, H, f) == (size_t)H &&
+              std::fwrite(m->w3, 4, H, f) == (size_t)H && std::fwrite(&m->b3, 4, 1, f) == 1;
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? NNSORT_OK : NNSORT_EIO;
+}
+
+int nnsort_model_load(nnsort_model* m, const char* path) {
+    if (!m || !path) return NNSORT_EINVAL;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return NNSORT_EIO;
+    nnsort_model t{};
+    char magic[4];
+    int32_t hdr[2];
+    double aff[2];
+    int rc = NNSORT_OK;
+    if (std::fread(magic, 1, 4, f) != 4 || std::memcmp(magic, "NNSM", 4) != 0 || std::fread(hdr, 4, 2, f) != 2 ||
+        hdr[0] != NNSORT_ABI_VERSION || hdr[1] < 1 || hdr[1] > NNSORT_MAX_HIDDEN || std::fread(aff, 8, 2, f) != 2) {
+        rc = NNSORT_EMODEL;
+    } else {
+        int H = hdr[1];
+        t.version = hdr[0];
+        t.hidden = H;
+        t.lo = aff[0];
+        t.inv_range = aff[1];
+        bool ok = std::fread(t.w1, 4, H, f) == (size_t)H && std::fread(t.b1, 4, H, f) == (size_t)H &&
+                  std::fread(t.w2, 4, (size_t)H * H, f) == (size_t)H * H && std::fread(t.b2, 4, H, f) == (size_t)H &&
+                  std::fread(t.w3, 4, H, f) == (size_t)H && std::fread(&t.b3, 4, 1, f) == 1;
+        if (!ok) rc = NNSORT_EMODEL;
+    }
+    std::fclose(f);
+    if (rc == NNSORT_OK) *m = t;
+    return rc;
+}
+
+const char* nnsort_strerror(int status) {
+    switch (status) {
+    case NNSORT_OK: return "ok";
+    case NNSORT_EINVAL: return "invalid argument";
+    case NNSORT_EWORKSPACE: return "workspace too small";
+    case NNSORT_EHIP: return g_last_error[0] ? g_last_error : "HIP runtime error";
+    case NNSORT_EMODEL: return "malformed model";
+    case NNSORT_EIO: return "model file I/O error";
+    case NNSORT_EINTERNAL: return "internal consistency check failed";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,583 @@
+// Sorting and polish phases on slot-range buckets (Sec. 2, Procedure NN-sort
+// and polish).
+//
+// Every round of the sorting phase stores, for each slot, the first key (in
+// processing order) that maps to it; the rest go to the conflict array and are
+// mapped again.  Since f is fixed, a key keeps its slot in every round, so a
+// slot's keys never interact with another slot's: the rounds of the keys of
+// one slot range can run on their own.  k_bucket_polish runs all rounds of one
+// range in LDS (first arrival = smallest input index, decided with LDS
+// atomic-min), compacts each o_r in slot order followed by the range's part of
+// the last conflict array, and then sorts that sequence in LDS (per-thread
+// sorting network, then merge-path merges) -- the polish of the range.
+// Adjacent ranges can overlap in key order where f is not monotone or jitters;
+// k_boundary_* repairs each such overlap with an in-place merge, and reports a
+// fallback when the overlap is not confined to neighbours.
+#include "nnsort_internal.h"
+
+namespace nns {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+__global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+static int blocks_for(int64_t n, int threads, int cap) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, 256, 8192)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+hipError_t fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(n, 256, 8192)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ uint64_t load_key(const void* M, bool M_is_bits, bool is_f64, int64_t i) {
+    uint64_t v = ((const uint64_t*)M)[i];
+    return M_is_bits ? order_key(v, is_f64) : v;
+}
+__device__ __forceinline__ void store_key(void* M, bool M_is_bits, bool is_f64, int64_t i, uint64_t k) {
+    ((uint64_t*)M)[i] = M_is_bits ? order_key_inverse(k, is_f64) : k;
+}
+
+// ---------------------------------------------------------------------------
+// classify: small / big buckets, offsets of small segments, segment list
+// ---------------------------------------------------------------------------
+// Single workgroup; each thread owns a contiguous chunk of buckets.
+// bucket_info layout (int64 each): bigmap[NB] (id of big bucket or -1),
+// moff[NB] (offset of the segment in M), seglist[NB] (non-empty small buckets
+// in order), bigbucket[big_max] (bucket of big id).
+__global__ void __launch_bounds__(1024) k_classify(const uint32_t* __restrict__ cnt, int64_t NB,
+                                                   int64_t big_max, int32_t* bigmap, uint64_t* moff,
+                                                   int32_t* seglist, int32_t* bigbucket,
+                                                   unsigned long long* counters) {
+    __shared__ unsigned long long s_small[1024], s_big[1024], s_seg[1024], s_bigkeys[1024];
+    int t = threadIdx.x;
+    int64_t chunk = (NB + 1023) / 1024;
+    int64_t b0 = t * chunk, b1 = b0 + chunk < NB ? b0 + chunk : NB;
+    unsigned long long small = 0, big = 0, seg = 0, bigkeys = 0;
+    for (int64_t b = b0; b < b1; ++b) {
+        uint32_t c = cnt[b];
+        if (c > kBucketCap) {
+            ++big;
+            bigkeys += c;
+        } else {
+            small += c;
+            seg += c ? 1 : 0;
+        }
+    }
+    s_small[t] = small;
+    s_big[t] = big;
+    s_seg[t] = seg;
+    s_bigkeys[t] = bigkeys;
+    __syncthreads();
+    // inclusive Hillis-Steele scans over 1024 entries
+    for (int off = 1; off < 1024; off <<= 1) {
+        unsigned long long a = t >= off ? s_small[t - off] : 0;
+        unsigned long long c = t >= off ? s_big[t - off] : 0;
+        unsigned long long d = t >= off ? s_seg[t - off] : 0;
+        unsigned long long e = t >= off ? s_bigkeys[t - off] : 0;
+        __syncthreads();
+        s_small[t] += a;
+        s_big[t] += c;
+        s_seg[t] += d;
+        s_bigkeys[t] += e;
+        __syncthreads();
+    }
+    unsigned long long po = s_small[t] - small, pb = s_big[t] - big, ps = s_seg[t] - seg;
+    for (int64_t b = b0; b < b1; ++b) {
+        uint32_t c = cnt[b];
+        if (c > kBucketCap) {
+            bigmap[b] = (int32_t)pb;
+            if ((int64_t)pb < big_max) bigbucket[pb] = (int32_t)b;
+            ++pb;
+            moff[b] = po;
+        } else {
+            bigmap[b] = -1;
+            moff[b] = po;
+            po += c;
+            if (c) seglist[ps++] = (int32_t)b;
+        }
+    }
+    if (t == 1023) {
+        counters[kCntBigBuckets] = s_big[1023];
+        counters[kCntBigKeys] = s_bigkeys[1023];
+        counters[kCntSmallBuckets] = s_seg[1023];
+    }
+}
+
+hipError_t launch_classify(const uint32_t* d_cnt, int64_t NB, int64_t big_max, int32_t* d_bigmap,
+                           uint64_t* d_moff, int32_t* d_seglist, int32_t* d_bigbucket,
+                           uint64_t* d_counters, hipStream_t st) {
+    hipLaunchKernelGGL(k_classify, dim3(1), dim3(1024), 0, st, d_cnt, NB, big_max, d_bigmap, d_moff,
+                       d_seglist, d_bigbucket, (unsigned long long*)d_counters);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// big buckets: slot multiplicities (for the round counts) and gather to G
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void g_append(bool want, uint64_t okey, uint64_t* G,
+                                         unsigned long long* counter) {
+    unsigned long long mask = __ballot(want);
+    if (!mask) return;
+    int leader = __ffsll((long long)mask) - 1;
+    unsigned long long base = 0;
+    if ((int)__lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader);
+    if (want) G[base + __popcll(mask & ((1ull << __lane_id()) - 1ull))] = okey;
+}
+
+// Region entries of big buckets: thread per (big id, entry).
+__global__ void __launch_bounds__(256) k_big_region(const int32_t* __restrict__ bigbucket, int64_t big_count,
+                                                    const uint64_t* __restrict__ rkey,
+                                                    const uint64_t* __restrict__ rmeta, uint32_t* hist,
+                                                    uint64_t* G, unsigned long long* counters) {
+    int64_t total = big_count * (int64_t)kBucketCap;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
+        int64_t i = base + threadIdx.x;
+        bool act = i < total;
+        uint64_t okey = 0;
+        if (act) {
+            int64_t id = i / kBucketCap;
+            int64_t e = (int64_t)bigbucket[id] * kBucketCap + (i % kBucketCap);
+            okey = rkey[e];
+            uint32_t lsl = (uint32_t)(rmeta[e] & (kBucketSlots - 1));
+            atomicAdd(&hist[id * kBucketSlots + lsl], 1u);
+        }
+        g_append(act, okey, G, &counters[kCntGlobal]);
+    }
+}
+
+// Spill entries: overflow of big buckets, and keys without a slot.
+__global__ void __launch_bounds__(256) k_big_spill(const SpillEntry* __restrict__ spill, int64_t count,
+                                                   const int32_t* __restrict__ bigmap, uint32_t* hist,
+                                                   uint64_t* G, unsigned long long* counters) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < count; base += stride) {
+        int64_t i = base + threadIdx.x;
+        bool act = i < count;
+        uint64_t okey = 0;
+        if (act) {
+            SpillEntry e = spill[i];
+            okey = e.okey;
+            if (e.slot != kUnmapped) {
+                int32_t id = bigmap[e.slot >> kLogBucketSlots];
+                if (id >= 0) atomicAdd(&hist[(int64_t)id * kBucketSlots + (e.slot & (kBucketSlots - 1))], 1u);
+                else atomicAdd(&counters[kCntBadSlot], 1ull);  // cannot happen: spill implies big
+            }
+        }
+        g_append(act, okey, G, &counters[kCntGlobal]);
+    }
+}
+
+// Round counts of big buckets from slot multiplicities k_s: round r stores
+// min(k_s, r) - min(k_s, r - 1) keys of slot s and leaves max(0, k_s - r).
+__global__ void __launch_bounds__(256) k_big_counts(const uint32_t* __restrict__ hist, int64_t total, int eps,
+                                                    unsigned long long* counters) {
+    __shared__ unsigned long long s_col[NNSORT_MAX_EPS], s_pl[NNSORT_MAX_EPS];
+    if (threadIdx.x < NNSORT_MAX_EPS) {
+        s_col[threadIdx.x] = 0;
+        s_pl[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    unsigned long long col[NNSORT_MAX_EPS] = {0}, pl[NNSORT_MAX_EPS] = {0};
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        uint32_t k = hist[i];
+        for (int r = 1; r <= eps; ++r) {
+            col[r - 1] += k > (uint32_t)r ? k - r : 0;
+            pl[r - 1] += k >= (uint32_t)r ? 1 : 0;
+        }
+    }
+    for (int r = 0; r < eps; ++r) {
+        atomicAdd(&s_col[r], col[r]);
+        atomicAdd(&s_pl[r], pl[r]);
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)eps) {
+        atomicAdd(&counters[kCntCollided + threadIdx.x], s_col[threadIdx.x]);
+        atomicAdd(&counters[kCntPlaced + threadIdx.x], s_pl[threadIdx.x]);
+    }
+}
+
+hipError_t launch_big_buckets(const int32_t* d_bigbucket, int64_t big_count, const int32_t* d_bigmap,
+                              const uint64_t* d_region_key, const uint64_t* d_region_meta,
+                              const SpillEntry* d_spill, int64_t spill_count, uint32_t* d_big_hist,
+                              uint64_t* d_G, uint64_t* d_counters, int eps, hipStream_t st) {
+    unsigned long long* c = (unsigned long long*)d_counters;
+    hipError_t e = fill_u32(d_big_hist, big_count * (int64_t)kBucketSlots, 0u, st);
+    if (e != hipSuccess) return e;
+    if (big_count > 0) {
+        hipLaunchKernelGGL(k_big_region, dim3(blocks_for(big_count * kBucketCap, 256, 16384)), dim3(256), 0,
+                           st, d_bigbucket, big_count, d_region_key, d_region_meta, d_big_hist, d_G, c);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (spill_count > 0) {
+        hipLaunchKernelGGL(k_big_spill, dim3(blocks_for(spill_count, 256, 16384)), dim3(256), 0, st,
+                           d_spill, spill_count, d_bigmap, d_big_hist, d_G, c);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (big_count > 0) {
+        hipLaunchKernelGGL(k_big_counts, dim3(blocks_for(big_count * kBucketSlots, 256, 2048)), dim3(256),
+                           0, st, d_big_hist, big_count * (int64_t)kBucketSlots, eps, c);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// per-bucket rounds + polish in LDS
+// ---------------------------------------------------------------------------
+constexpr int kItems = kItemsPerThread;  // keys per thread (16)
+
+__device__ __forceinline__ void cswap(uint64_t& a, uint64_t& b) {
+    uint64_t lo = a < b ? a : b;
+    uint64_t hi = a < b ? b : a;
+    a = lo;
+    b = hi;
+}
+
+// Bitonic sorting network over 16 registers (ascending).
+__device__ __forceinline__ void sort16(uint64_t (&v)[kItems]) {
+#pragma unroll
+    for (int k = 2; k <= kItems; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < kItems; ++i) {
+                int l = i ^ j;
+                if (l > i) {
+                    if ((i & k) == 0) cswap(v[i], v[l]);
+                    else cswap(v[l], v[i]);
+                }
+            }
+        }
+    }
+}
+
+// Merge-path split: number of elements taken from a (length na) among the
+// first `diag` outputs of merge(a, b); ties go to a first (stable).
+__device__ __forceinline__ int merge_split(const uint64_t* a, int na, const uint64_t* b, int nb, int diag) {
+    int lo = diag > nb ? diag - nb : 0;
+    int hi = diag < na ? diag : na;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        // take a[mid] before b[diag - 1 - mid] iff a[mid] <= b[diag - 1 - mid]
+        if (a[mid] <= b[diag - 1 - mid]) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+struct BucketSmem {
+    uint64_t bufA[kBucketCap];
+    uint64_t bufB[kBucketCap];
+    uint32_t owner[kBucketSlots];
+    uint32_t bitmap[NNSORT_MAX_EPS][kBucketSlots / 32];
+    uint32_t woff[NNSORT_MAX_EPS][kBucketSlots / 32];
+    uint32_t placed[NNSORT_MAX_EPS + 1];
+    uint32_t resid_cursor;
+};
+
+__global__ void __launch_bounds__(kBucketThreads) k_bucket_polish(
+    const uint32_t* __restrict__ cnt_arr, const uint64_t* __restrict__ moff,
+    const uint64_t* __restrict__ rkey, const uint64_t* __restrict__ rmeta, int eps, void* M,
+    int M_is_bits, int is_f64, uint64_t* segmin, uint64_t* segmax, unsigned long long* counters) {
+    __shared__ BucketSmem sm;
+    const int tid = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const uint32_t cnt = cnt_arr[b];
+    if (cnt == 0 || cnt > kBucketCap) return;  // empty, or handled by the big-bucket path
+    const size_t rbase = (size_t)b * kBucketCap;
+
+    uint64_t key[kItems];
+    uint32_t idx[kItems];
+    uint32_t lsl[kItems];
+    uint8_t rnd[kItems];  // round that stored the key (0 = still in conflict array)
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        uint32_t e = tid + k * kBucketThreads;
+        rnd[k] = 0;
+        if (e < cnt) {
+            key[k] = rkey[rbase + e];
+            uint64_t m = rmeta[rbase + e];
+            idx[k] = (uint32_t)(m >> 32);
+            lsl[k] = (uint32_t)(m & (kBucketSlots - 1));
+        } else {
+            key[k] = 0;
+            idx[k] = 0;
+            lsl[k] = 0;
+        }
+    }
+    if (tid <= NNSORT_MAX_EPS) sm.placed[tid] = 0;
+    if (tid == 0) sm.resid_cursor = 0;
+    for (int i = tid; i < NNSORT_MAX_EPS * (int)(kBucketSlots / 32); i += kBucketThreads)
+        (&sm.bitmap[0][0])[i] = 0;
+
+    // ---- rounds: first arrival (smallest input index) per slot ----
+    for (int r = 1; r <= eps; ++r) {
+        for (int i = tid; i < (int)kBucketSlots; i += kBucketThreads) sm.owner[i] = kUnmapped;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            uint32_t e = tid + k * kBucketThreads;
+            if (e < cnt && rnd[k] == 0) atomicMin(&sm.owner[lsl[k]], idx[k]);
+        }
+        __syncthreads();
+        uint32_t mine = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            uint32_t e = tid + k * kBucketThreads;
+            if (e < cnt && rnd[k] == 0 && sm.owner[lsl[k]] == idx[k]) {
+                rnd[k] = (uint8_t)r;
+                atomicOr(&sm.bitmap[r - 1][lsl[k] >> 5], 1u << (lsl[k] & 31));
+                ++mine;
+            }
+        }
+        if (mine) atomicAdd(&sm.placed[r - 1], mine);
+        __syncthreads();
+    }
+
+    // ---- counts: |c_r| of this range and the stored keys per round ----
+    if (tid == 0) {
+        uint32_t left = cnt;
+        for (int r = 0; r < eps; ++r) {
+            left -= sm.placed[r];
+            atomicAdd(&counters[kCntCollided + r], (unsigned long long)left);
+            atomicAdd(&counters[kCntPlaced + r], (unsigned long long)sm.placed[r]);
+        }
+    }
+    // exclusive popcount prefix of each round's occupancy bitmap (wave 0)
+    if (tid < 64) {
+        for (int r = 0; r < eps; ++r) {
+            uint32_t c = __popc(sm.bitmap[r][tid]);
+            uint32_t incl = c;
+            for (int off = 1; off < 64; off <<= 1) {
+                uint32_t y = __shfl_up(incl, off);
+                if (tid >= off) incl += y;
+            }
+            sm.woff[r][tid] = incl - c;
+        }
+    }
+    __syncthreads();
+
+    // ---- compaction: o_1 | o_2 | ... | o_eps (each in slot order) | rest ----
+    uint32_t rbase_pos[NNSORT_MAX_EPS + 1];
+    {
+        uint32_t acc = 0;
+        for (int r = 0; r < eps; ++r) {
+            rbase_pos[r] = acc;
+            acc += sm.placed[r];
+        }
+        rbase_pos[eps] = acc;
+    }
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        uint32_t e = tid + k * kBucketThreads;
+        if (e >= cnt) continue;
+        uint32_t pos;
+        if (rnd[k]) {
+            int r = rnd[k] - 1;
+            uint32_t w = lsl[k] >> 5;
+            uint32_t below = sm.bitmap[r][w] & ((1u << (lsl[k] & 31)) - 1u);
+            pos = rbase_pos[r] + sm.woff[r][w] + __popc(below);
+        } else {
+            pos = rbase_pos[eps] + atomicAdd(&sm.resid_cursor, 1u);
+        }
+        sm.bufA[pos] = key[k];
+    }
+    __syncthreads();
+
+    // ---- polish: sort the compacted sequence (runs of 16, then merges) ----
+    int npad = kItems;
+    while (npad < (int)cnt) npad <<= 1;
+    const int nthr = npad / kItems;
+    uint64_t* src = sm.bufA;
+    uint64_t* dst = sm.bufB;
+    if (tid < nthr) {
+        uint64_t v[kItems];
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            int p = tid * kItems + k;
+            v[k] = p < (int)cnt ? src[p] : ~0ull;
+        }
+        sort16(v);
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) src[tid * kItems + k] = v[k];
+    }
+    __syncthreads();
+    for (int w = kItems; w < npad; w <<= 1) {
+        if (tid < nthr) {
+            int out0 = tid * kItems;
+            int pair = out0 / (2 * w);
+            int d = out0 - pair * 2 * w;
+            const uint64_t* a = src + pair * 2 * w;
+            const uint64_t* bb = a + w;
+            int ia = merge_split(a, w, bb, w, d);
+            int ib = d - ia;
+            uint64_t* o = dst + out0;
+#pragma unroll
+            for (int k = 0; k < kItems; ++k) {
+                bool takeA = ib >= w || (ia < w && a[ia] <= bb[ib]);
+                o[k] = takeA ? a[ia] : bb[ib];
+                ia += takeA ? 1 : 0;
+                ib += takeA ? 0 : 1;
+            }
+        }
+        __syncthreads();
+        uint64_t* t = src;
+        src = dst;
+        dst = t;
+    }
+
+    // ---- write the range's sorted keys to its segment of M ----
+    const uint64_t off = moff[b];
+    for (uint32_t i = tid; i < cnt; i += kBucketThreads) store_key(M, M_is_bits, is_f64, off + i, src[i]);
+    if (tid == 0) {
+        segmin[b] = src[0];
+        segmax[b] = src[cnt - 1];
+    }
+}
+
+hipError_t launch_bucket_polish(const uint32_t* d_cnt, const uint64_t* d_moff, int64_t NB,
+                                const uint64_t* d_region_key, const uint64_t* d_region_meta, int eps,
+                                void* d_M, bool M_is_bits, bool is_f64, uint64_t* d_segmin,
+                                uint64_t* d_segmax, uint64_t* d_counters, hipStream_t st) {
+    if (NB <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bucket_polish, dim3((unsigned)NB), dim3(kBucketThreads), 0, st, d_cnt, d_moff,
+                       d_region_key, d_region_meta, eps, d_M, M_is_bits ? 1 : 0, is_f64 ? 1 : 0, d_segmin,
+                       d_segmax, (unsigned long long*)d_counters);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// boundary fix-up between consecutive segments of M
+// ---------------------------------------------------------------------------
+constexpr int kZoneMax = 4096;  // keys a single boundary repair may hold in LDS
+
+// zone[k] for the boundary between segment k and k+1: {start, tail, head}.
+struct Zone {
+    uint64_t start;
+    uint32_t tail;
+    uint32_t head;
+};
+
+// One thread per segment k: checks that overlaps involve neighbours only
+// (max of segment k-1 <= min of segment k+1) and sizes the zone between k and
+// k+1 by binary search in both sorted segments.
+__global__ void __launch_bounds__(256) k_boundary_plan(const void* M, int M_is_bits, int is_f64,
+                                                       const uint64_t* __restrict__ moff,
+                                                       const uint32_t* __restrict__ cnt,
+                                                       const int32_t* __restrict__ seglist, int64_t K,
+                                                       const uint64_t* __restrict__ segmin,
+                                                       const uint64_t* __restrict__ segmax, Zone* zones,
+                                                       unsigned long long* counters) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    int32_t b = seglist[k];
+    if (k > 0 && k + 1 < K) {
+        if (segmax[seglist[k - 1]] > segmin[seglist[k + 1]]) atomicAdd(&counters[kCntFallback], 1ull);
+    }
+    Zone z{0, 0, 0};
+    if (k + 1 < K) {
+        int32_t b2 = seglist[k + 1];
+        uint64_t mx = segmax[b], mn = segmin[b2];
+        if (mx > mn) {
+            // tail: keys of segment k greater than min of k+1
+            int64_t s0 = moff[b], n0 = cnt[b];
+            int64_t lo = 0, hi = n0;
+            while (lo < hi) {
+                int64_t mid = (lo + hi) >> 1;
+                if (load_key(M, M_is_bits, is_f64, s0 + mid) > mn) hi = mid;
+                else lo = mid + 1;
+            }
+            uint32_t tail = (uint32_t)(n0 - lo);
+            // head: keys of segment k+1 less than max of k
+            int64_t s1 = moff[b2], n1 = cnt[b2];
+            lo = 0;
+            hi = n1;
+            while (lo < hi) {
+                int64_t mid = (lo + hi) >> 1;
+                if (load_key(M, M_is_bits, is_f64, s1 + mid) < mx) lo = mid + 1;
+                else hi = mid;
+            }
+            uint32_t head = (uint32_t)lo;
+            z.start = (uint64_t)(s0 + n0 - tail);
+            z.tail = tail;
+            z.head = head;
+            atomicAdd(&counters[kCntBoundary], (unsigned long long)(tail + head));
+            if (tail + head > (uint32_t)kZoneMax) atomicAdd(&counters[kCntFallback], 1ull);
+        }
+    }
+    zones[k] = z;
+}
+
+// One workgroup per boundary: merge tail and head (adjacent in M) in place.
+__global__ void __launch_bounds__(256) k_boundary_merge(void* M, int M_is_bits, int is_f64,
+                                                        const Zone* __restrict__ zones, int64_t K) {
+    __shared__ uint64_t buf[kZoneMax];
+    int64_t k = blockIdx.x;
+    if (k >= K) return;
+    Zone z = zones[k];
+    int total = (int)(z.tail + z.head);
+    if (z.tail == 0 || z.head == 0 || total > kZoneMax) return;
+    for (int i = threadIdx.x; i < total; i += blockDim.x) buf[i] = load_key(M, M_is_bits, is_f64, z.start + i);
+    __syncthreads();
+    const uint64_t* a = buf;
+    const uint64_t* b = buf + z.tail;
+    int na = z.tail, nb = z.head;
+    int per = (total + blockDim.x - 1) / blockDim.x;
+    int d0 = threadIdx.x * per;
+    if (d0 < total) {
+        int ia = merge_split(a, na, b, nb, d0);
+        int ib = d0 - ia;
+        int d1 = d0 + per < total ? d0 + per : total;
+        for (int d = d0; d < d1; ++d) {
+            bool takeA = ib >= nb || (ia < na && a[ia] <= b[ib]);
+            uint64_t v = takeA ? a[ia] : b[ib];
+            ia += takeA ? 1 : 0;
+            ib += takeA ? 0 : 1;
+            store_key(M, M_is_bits, is_f64, z.start + d, v);
+        }
+    }
+}
+
+hipError_t launch_boundary_plan(const void* d_M, bool M_is_bits, bool is_f64, const uint64_t* d_moff,
+                                const uint32_t* d_cnt, const int32_t* d_seglist, int64_t K,
+                                const uint64_t* d_segmin, const uint64_t* d_segmax, void* d_zones,
+                                uint64_t* d_counters, hipStream_t st) {
+    if (K <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_boundary_plan, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, d_M,
+                       M_is_bits ? 1 : 0, is_f64 ? 1 : 0, d_moff, d_cnt, d_seglist, K, d_segmin,
+                       d_segmax, (Zone*)d_zones, (unsigned long long*)d_counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_boundary_merge(void* d_M, bool M_is_bits, bool is_f64, const void* d_zones, int64_t K,
+                                 hipStream_t st) {
+    if (K <= 1) return hipSuccess;
+    hipLaunchKernelGGL(k_boundary_merge, dim3((unsigned)(K - 1)), dim3(256), 0, st, d_M, M_is_bits ? 1 : 0,
+                       is_f64 ? 1 : 0, (const Zone*)d_zones, K - 1);
+    return hipGetLastError();
+}
+
+size_t zone_bytes() { return sizeof(Zone); }
+
+}  // namespace nns

@@ -1,0 +1,449 @@
+// On-device fit of the CDF model (Sec. 2, Training; Sec. 4.1, Training
+// details: a regression network trained with Adam, here on the normalised rank
+// of a random sample of the keys).
+//
+// Random numbers come from Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC
+// 2011) keyed by the seed: stream 1 draws the sample, stream 2 the uniform
+// initial weights, stream 3 the batches.  The forward pass uses the FP32
+// form's operation order; the backward pass is hand-written: per-sample
+// deltas, then batch reductions in fixed blocks summed in a fixed order, so a
+// gradient does not depend on scheduling.  This translation unit is compiled
+// with -ffp-contract=off.
+#include "nnsort_internal.h"
+
+namespace nns {
+
+// ---- Philox4x32-10 ----
+__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
+        uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+__device__ __forceinline__ uint64_t rand64(uint64_t seed, uint32_t stream, uint64_t a, uint32_t b) {
+    uint32_t c[4] = {(uint32_t)a, (uint32_t)(a >> 32), b, stream};
+    philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    return (uint64_t)c[0] | ((uint64_t)c[1] << 32);
+}
+
+constexpr uint32_t kStreamSample = 1, kStreamInit = 2, kStreamBatch = 3;
+
+// Sample k keys with replacement; keep the finite ones (order keys) in G.
+__global__ void __launch_bounds__(256) k_sample(const uint64_t* __restrict__ in, int64_t n, int is_f64,
+                                                uint64_t seed, int64_t k, uint64_t* out,
+                                                unsigned long long* count) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < k; base += stride) {
+        int64_t j = base + threadIdx.x;
+        bool ok = false;
+        uint64_t okey = 0;
+        if (j < k) {
+            uint64_t r = rand64(seed, kStreamSample, (uint64_t)j, 0);
+            uint64_t bits = in[r % (uint64_t)n];
+            ok = !is_f64 || (bits & 0x7FF0000000000000ull) != 0x7FF0000000000000ull;
+            okey = order_key(bits, is_f64);
+        }
+        unsigned long long mask = __ballot(ok);
+        if (mask) {
+            int leader = __ffsll((long long)mask) - 1;
+            unsigned long long b0 = 0;
+            if ((int)__lane_id() == leader) b0 = atomicAdd(count, (unsigned long long)__popcll(mask));
+            b0 = __shfl(b0, leader);
+            if (ok) out[b0 + __popcll(mask & ((1ull << __lane_id()) - 1ull))] = okey;
+        }
+    }
+}
+
+// Training inputs: x_j = clamp((key_j - lo) * inv, 0, 1), y_j = (j + 0.5)/k.
+__global__ void __launch_bounds__(256) k_make_xy(const uint64_t* __restrict__ sorted_okeys, int64_t k,
+                                                 int is_f64, double lo, double inv, double* x, float* y) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= k) return;
+    uint64_t bits = order_key_inverse(sorted_okeys[j], is_f64);
+    double v = is_f64 ? __longlong_as_double((long long)bits) : __ull2double_rn(bits);
+    double t = (v - lo) * inv;
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    x[j] = t;
+    y[j] = (float)(((double)j + 0.5) / (double)k);
+}
+
+// Initial weights (packed theta of width H).
+__global__ void k_init(float* theta, int H, int init, uint64_t seed, const double* __restrict__ x, int64_t k) {
+    int P = H * H + 4 * H + 1;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        double v = 0.0;
+        if (init == 1) {
+            // quantile ramps: u_j = relu(s_j (x - q_j)), v_i = relu(1 - u_i), F = 1 - mean v
+            if (p < H) {
+                int j = p;
+                double q0 = x[(int64_t)j * (k - 1) / H], q1 = x[(int64_t)(j + 1) * (k - 1) / H];
+                double w = q1 - q0;
+                w = w > 0x1p-40 ? w : 0x1p-40;
+                v = 1.0 / w;
+            } else if (p < 2 * H) {
+                int j = p - H;
+                double q0 = x[(int64_t)j * (k - 1) / H], q1 = x[(int64_t)(j + 1) * (k - 1) / H];
+                double w = q1 - q0;
+                w = w > 0x1p-40 ? w : 0x1p-40;
+                double s = 1.0 / w;
+                v = -s * q0;
+            } else if (p < 2 * H + H * H) {
+                int e = p - 2 * H;
+                v = (e / H == e % H) ? -1.0 : 0.0;
+            } else if (p < 3 * H + H * H) {
+                v = 1.0;
+            } else if (p < 4 * H + H * H) {
+                v = -1.0 / H;
+            } else {
+                v = 1.0;
+            }
+        } else {
+            double bound = p < 2 * H ? 1.0 : 1.0 / sqrt((double)H);
+            uint64_t r = rand64(seed, kStreamInit, (uint64_t)p, 0);
+            double u = (double)(uint32_t)(r >> 40) * (1.0 / 16777216.0);
+            v = bound * (2.0 * u - 1.0);
+        }
+        theta[p] = (float)v;
+    }
+}
+
+// Gather a batch: bx[b] = x[idx], by[b] = y[idx], idx = Philox(step, b) mod k.
+__global__ void __launch_bounds__(256) k_batch(const double* __restrict__ x, const float* __restrict__ y,
+                                               int64_t k, uint64_t seed, int64_t step, int64_t B,
+                                               double* bx, float* by) {
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    uint64_t j = rand64(seed, kStreamBatch, (uint64_t)b, (uint32_t)step) % (uint64_t)k;
+    bx[b] = x[j];
+    by[b] = y[j];
+}
+
+// ---- forward (FP32 form order), saving h1 and h2 ----
+__device__ __forceinline__ float two_sum_f(float a, float b, float& err) {
+    float s = a + b;
+    float bb = s - a;
+    err = (a - (s - bb)) + (b - bb);
+    return s;
+}
+
+template <int H>
+__global__ void __launch_bounds__(256) k_fwd(const float* __restrict__ th, const double* __restrict__ x,
+                                             int64_t B, float* F, float* saved) {
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const float* w1 = th;
+    const float* b1 = th + H;
+    const float* W2 = th + 2 * H;
+    const float* b2 = th + 2 * H + H * H;
+    const float* w3 = th + 3 * H + H * H;
+    double xv = x[b];
+    float xh = (float)xv;
+    float xl = (float)(xv - (double)xh);
+    float h1[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        float z = __builtin_fmaf(w1[j], xh, b1[j]);
+        z = __builtin_fmaf(w1[j], xl, z);
+        h1[j] = z > 0.0f ? z : 0.0f;
+    }
+    float p = th[4 * H + H * H], s = 0.0f;
+    float* sh1 = saved ? saved + b * (2 * H) : nullptr;
+    for (int i = 0; i < H; ++i) {
+        float z = b2[i];
+#pragma unroll
+        for (int j = 0; j < H; ++j) z = __builtin_fmaf(W2[i * H + j], h1[j], z);
+        float h2 = z > 0.0f ? z : 0.0f;
+        if (sh1) sh1[H + i] = h2;
+        float pr = w3[i] * h2;
+        float r = __builtin_fmaf(w3[i], h2, -pr);
+        float q;
+        p = two_sum_f(p, pr, q);
+        s = s + (q + r);
+    }
+    if (sh1) {
+#pragma unroll
+        for (int j = 0; j < H; ++j) sh1[j] = h1[j];
+    }
+    F[b] = p + s;
+}
+
+// ---- loss and dL/dF ----
+constexpr int kLossBlocks = 256;
+__global__ void __launch_bounds__(256) k_loss(const float* __restrict__ F, const float* __restrict__ y, int64_t B,
+                                              int loss, float delta, float* gF, float* partial) {
+    __shared__ float s[256];
+    float acc = 0.0f;
+    float invB = 1.0f / (float)B;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < B; b += (int64_t)gridDim.x * blockDim.x) {
+        float e = F[b] - y[b];
+        float g, l;
+        if (loss == 1) {
+            if (fabsf(e) <= delta) {
+                l = 0.5f * e * e;
+                g = e;
+            } else {
+                l = delta * fabsf(e) - 0.5f * delta * delta;
+                g = e > 0.0f ? delta : -delta;
+            }
+        } else {
+            l = e * e;
+            g = 2.0f * e;
+        }
+        gF[b] = g * invB;
+        acc += l;
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < (unsigned)off) s[threadIdx.x] += s[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+}
+
+__global__ void k_loss_final(const float* __restrict__ partial, int nb, int64_t B, float* loss_out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        float s = 0.0f;
+        for (int i = 0; i < nb; ++i) s += partial[i];
+        loss_out[0] = s / (float)B;
+    }
+}
+
+// ---- backward ----
+// Per sample: dz2_i = g w3_i [h2_i > 0]; dz1_j = [h1_j > 0] sum_i dz2_i W2_ij.
+// Writes d = (dz1[H], dz2[H]) per sample next to the saved (h1, h2).
+template <int H>
+__global__ void __launch_bounds__(256) k_bwd_sample(const float* __restrict__ th, int64_t B,
+                                                    const float* __restrict__ saved,
+                                                    const float* __restrict__ gF, float* d) {
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const float* W2 = th + 2 * H;
+    const float* w3 = th + 3 * H + H * H;
+    const float* h = saved + b * (2 * H);
+    float g = gF[b];
+    float dz2[H];
+#pragma unroll
+    for (int i = 0; i < H; ++i) dz2[i] = h[H + i] > 0.0f ? g * w3[i] : 0.0f;
+    float* o = d + b * (2 * H);
+    for (int j = 0; j < H; ++j) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int i = 0; i < H; ++i) acc = __builtin_fmaf(dz2[i], W2[i * H + j], acc);
+        o[j] = h[j] > 0.0f ? acc : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < H; ++i) o[H + i] = dz2[i];
+}
+
+// Batch reductions: block c sums samples [c*chunk, (c+1)*chunk) into its row
+// of `part` (P floats): dW2_ij = sum dz2_i h1_j, dw3_i = sum g h2_i,
+// db2 = sum dz2, dw1_j = sum dz1_j x, db1 = sum dz1, db3 = sum g.
+constexpr int kRedChunk = 512;
+constexpr int kRedSub = 32;
+template <int H>
+__global__ void __launch_bounds__(256) k_bwd_reduce(const double* __restrict__ x, int64_t B,
+                                                    const float* __restrict__ saved, const float* __restrict__ d,
+                                                    const float* __restrict__ gF, float* part) {
+    constexpr int P = H * H + 4 * H + 1;
+    constexpr int PER = (H * H + 255) / 256;
+    __shared__ float sh1[kRedSub][H];
+    __shared__ float sdz2[kRedSub][H];
+    __shared__ float sx[kRedSub], sg[kRedSub];
+    const int tid = threadIdx.x;
+    float acc[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) acc[q] = 0.0f;
+    float accv = 0.0f;   // one of the 4H vector gradients per thread (tid < 4H)
+    float accb3 = 0.0f;  // db3, thread 0
+    const int64_t c0 = (int64_t)blockIdx.x * kRedChunk;
+    for (int64_t s0 = c0; s0 < c0 + kRedChunk && s0 < B; s0 += kRedSub) {
+        for (int e = tid; e < kRedSub * H; e += 256) {
+            int r = e / H, c = e % H;
+            int64_t b = s0 + r;
+            sh1[r][c] = b < B ? saved[b * (2 * H) + c] : 0.0f;
+            sdz2[r][c] = b < B ? d[b * (2 * H) + H + c] : 0.0f;
+        }
+        if (tid < kRedSub) {
+            int64_t b = s0 + tid;
+            sx[tid] = b < B ? (float)x[b] : 0.0f;
+            sg[tid] = b < B ? gF[b] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            int e = tid + q * 256;
+            if (e < H * H) {
+                int i = e / H, j = e % H;
+                float a = acc[q];
+                for (int r = 0; r < kRedSub; ++r) a = __builtin_fmaf(sdz2[r][i], sh1[r][j], a);
+                acc[q] = a;
+            }
+        }
+        if (tid == 0)
+            for (int r = 0; r < kRedSub; ++r) accb3 += sg[r];
+        if (tid < 4 * H) {
+            for (int r = 0; r < kRedSub; ++r) {
+                int64_t b = s0 + r;
+                if (b >= B) break;
+                float v;
+                if (tid < H) {  // dw1_j = dz1_j x
+                    v = d[b * (2 * H) + tid] * sx[r];
+                } else if (tid < 2 * H) {  // db1_j = dz1_j
+                    v = d[b * (2 * H) + tid - H];
+                } else if (tid < 3 * H) {  // db2_i = dz2_i
+                    v = sdz2[r][tid - 2 * H];
+                } else {  // dw3_i = g h2_i
+                    v = sg[r] * saved[b * (2 * H) + H + (tid - 3 * H)];
+                }
+                accv += v;
+            }
+        }
+        __syncthreads();
+    }
+    float* row = part + (int64_t)blockIdx.x * P;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        int e = tid + q * 256;
+        if (e < H * H) row[2 * H + e] = acc[q];
+    }
+    if (tid < 4 * H) {
+        int p;
+        if (tid < 2 * H) p = tid;                                 // w1, b1
+        else if (tid < 3 * H) p = 2 * H + H * H + (tid - 2 * H);  // b2
+        else p = 3 * H + H * H + (tid - 3 * H);                   // w3
+        row[p] = accv;
+    }
+    if (tid == 0) row[4 * H + H * H] = accb3;
+}
+
+__global__ void __launch_bounds__(256) k_sum_rows(const float* __restrict__ part, int rows, int P, float* out) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    float s = 0.0f;
+    for (int r = 0; r < rows; ++r) s += part[(int64_t)r * P + p];
+    out[p] = s;
+}
+
+__global__ void __launch_bounds__(256) k_adam(float* th, const float* __restrict__ g, float* m1, float* m2,
+                                              int64_t count, float b1, float b2, float c1, float c2, float lr,
+                                              float eps) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= count) return;
+    float gv = g[p];
+    float m = b1 * m1[p] + (1.0f - b1) * gv;
+    float v = b2 * m2[p] + (1.0f - b2) * gv * gv;
+    m1[p] = m;
+    m2[p] = v;
+    float mh = m / c1, vh = v / c2;
+    th[p] = th[p] - lr * mh / (sqrtf(vh) + eps);
+}
+
+// ---- launchers ----
+static unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t launch_sample(const void* d_in, int64_t n, bool is_f64, uint64_t seed, int64_t k, uint64_t* d_out,
+                         uint64_t* d_count, hipStream_t st) {
+    unsigned g = nblk(k, 256);
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_sample, dim3(g), dim3(256), 0, st, (const uint64_t*)d_in, n, is_f64 ? 1 : 0, seed, k,
+                       d_out, (unsigned long long*)d_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_make_xy(const uint64_t* d_sorted, int64_t k, bool is_f64, double lo, double inv, double* d_x,
+                          float* d_y, hipStream_t st) {
+    hipLaunchKernelGGL(k_make_xy, dim3(nblk(k, 256)), dim3(256), 0, st, d_sorted, k, is_f64 ? 1 : 0, lo, inv,
+                       d_x, d_y);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(float* d_theta, int H, int init, uint64_t seed, const double* d_x, int64_t k,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_init, dim3(nblk(H * H + 4 * H + 1, 256)), dim3(256), 0, st, d_theta, H, init, seed,
+                       d_x, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const double* d_x, const float* d_y, int64_t k, uint64_t seed, int64_t step, int64_t B,
+                        double* d_bx, float* d_by, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch, dim3(nblk(B, 256)), dim3(256), 0, st, d_x, d_y, k, seed, step, B, d_bx, d_by);
+    return hipGetLastError();
+}
+
+template <int H>
+static hipError_t fwd_h(const float* th, const double* x, int64_t B, float* F, float* saved, hipStream_t st) {
+    hipLaunchKernelGGL(k_fwd<H>, dim3(nblk(B, 256)), dim3(256), 0, st, th, x, B, F, saved);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(int H, const float* d_theta, const double* d_x, int64_t B, float* d_F,
+                              float* d_saved, hipStream_t st) {
+    switch (H) {
+    case 8: return fwd_h<8>(d_theta, d_x, B, d_F, d_saved, st);
+    case 16: return fwd_h<16>(d_theta, d_x, B, d_F, d_saved, st);
+    case 32: return fwd_h<32>(d_theta, d_x, B, d_F, d_saved, st);
+    case 64: return fwd_h<64>(d_theta, d_x, B, d_F, d_saved, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+size_t mlp_backward_ws_floats(int H, int64_t B) {
+    int64_t rows = (B + kRedChunk - 1) / kRedChunk;
+    return (size_t)B * 2 * H + (size_t)rows * (H * H + 4 * H + 1);
+}
+
+template <int H>
+static hipError_t bwd_h(const float* th, const double* x, int64_t B, const float* saved, const float* gF,
+                        float* gtheta, float* ws, hipStream_t st) {
+    constexpr int P = H * H + 4 * H + 1;
+    float* d = ws;
+    float* part = ws + (size_t)B * 2 * H;
+    int rows = (int)((B + kRedChunk - 1) / kRedChunk);
+    hipLaunchKernelGGL(k_bwd_sample<H>, dim3(nblk(B, 256)), dim3(256), 0, st, th, B, saved, gF, d);
+    hipLaunchKernelGGL(k_bwd_reduce<H>, dim3(rows), dim3(256), 0, st, x, B, saved, d, gF, part);
+    hipLaunchKernelGGL(k_sum_rows, dim3(nblk(P, 256)), dim3(256), 0, st, part, rows, P, gtheta);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_backward(int H, const float* d_theta, const double* d_x, int64_t B, const float* d_saved,
+                               const float* d_gF, float* d_gtheta, float* d_ws, hipStream_t st) {
+    switch (H) {
+    case 8: return bwd_h<8>(d_theta, d_x, B, d_saved, d_gF, d_gtheta, d_ws, st);
+    case 16: return bwd_h<16>(d_theta, d_x, B, d_saved, d_gF, d_gtheta, d_ws, st);
+    case 32: return bwd_h<32>(d_theta, d_x, B, d_saved, d_gF, d_gtheta, d_ws, st);
+    case 64: return bwd_h<64>(d_theta, d_x, B, d_saved, d_gF, d_gtheta, d_ws, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+size_t loss_ws_floats() { return kLossBlocks; }
+
+hipError_t launch_loss_grad(const float* d_F, const float* d_y, int64_t B, int loss, float delta, float* d_gF,
+                            float* d_loss, float* d_partial, hipStream_t st) {
+    hipLaunchKernelGGL(k_loss, dim3(kLossBlocks), dim3(256), 0, st, d_F, d_y, B, loss, delta, d_gF, d_partial);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, d_partial, kLossBlocks, B, d_loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* d_theta, const float* d_g, float* d_m1, float* d_m2, int64_t count, int64_t t,
+                       float lr, float b1, float b2, float eps, hipStream_t st) {
+    float c1 = (float)(1.0 - pow((double)b1, (double)t));
+    float c2 = (float)(1.0 - pow((double)b2, (double)t));
+    hipLaunchKernelGGL(k_adam, dim3(nblk(count, 256)), dim3(256), 0, st, d_theta, d_g, d_m1, d_m2, count, b1, b2,
+                       c1, c2, lr, eps);
+    return hipGetLastError();
+}
+
+}  // namespace nns

@@ -1,0 +1,183 @@
+// BF16 form of the model map: the hidden-to-hidden layer on the matrix cores
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation), the rest on the vector ALU.
+//
+// One wave maps 32 keys per tile.  Keys are the N dimension of the product
+// Z2^T[H x 32] = W2[H x H] * H1^T[H x 32]: lane l holds key j = l % 32 and lane
+// half g = l / 32, so both layers' data of a key stays in the two lanes that
+// own it and no transpose is needed:
+//  - layer 1 (VALU, FP32 form order with the two-float input): lane (j, g)
+//    computes hidden-1 units 16 s + 8 g + t (k-step s, t = 0..7), which is
+//    exactly its slice of the B operand of k-step s;
+//  - each activation is split exactly into up to three bfloat16 terms
+//    (truncation: h = hi + mid + lo, 8 significant bits each), one MFMA per
+//    term, so the product is formed from a 24-bit input (the bf16x3 scheme of
+//    Henry, Tang and Heinecke, 2019) while W2 itself is rounded to bfloat16;
+//  - the accumulators start at b2; lane (j, g) ends with hidden-2 units
+//    32 rb + 8 (v / 4) + 4 g + v % 4 (v = 0..15) of its key;
+//  - layer 3: relu, then a Kahan-compensated FP32 sum per lane, the two halves
+//    combined as (sum - correction) in FP64 so that F keeps a resolution finer
+//    than one slot at n = 1e9.
+// Compiled with -ffp-contract=off.
+#include "infer_common.h"
+
+namespace nns {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t bf16_rne_bits(float v) {
+    uint32_t u = __float_as_uint(v);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+// Upper halves of two floats packed as (lo16 = x, hi16 = y).
+__device__ __forceinline__ uint32_t pack_hi(float x, float y) {
+    return __builtin_amdgcn_perm(__float_as_uint(y), __float_as_uint(x), 0x07060302u);
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+template <int H, int T>
+__global__ void __launch_bounds__(256) k_infer_bf16(InferArgs a) {
+    constexpr int RB = H / 32;  // 32-row blocks of hidden-2 units
+    constexpr int KS = H / 16;  // k-steps of 16 hidden-1 units
+    const DevModel* __restrict__ m = a.model;
+    __shared__ float s_w1[64], s_b1[64];
+    for (int i = threadIdx.x; i < H; i += blockDim.x) {
+        s_w1[i] = m->w1[i];
+        s_b1[i] = m->b1[i];
+    }
+    __syncthreads();
+    const int lane = __lane_id();
+    const int j = lane & 31;
+    const int g = lane >> 5;
+
+    // A operands: W2 rows 32 rb + j, columns 16 s + 8 g + t, rounded to bf16.
+    u32x4 A[RB][KS];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const float* row = m->w2 + (32 * rb + j) * H + 16 * s + 8 * g;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                A[rb][s][q] = bf16_rne_bits(row[2 * q]) | (bf16_rne_bits(row[2 * q + 1]) << 16);
+        }
+    float b2r[RB][16], w3r[RB][16];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            int u = 32 * rb + 8 * (v >> 2) + 4 * g + (v & 3);
+            b2r[rb][v] = m->b2[u];
+            w3r[rb][v] = m->w3[u];
+        }
+    const float b3 = m->b3;
+    const double lo = m->lo, inv = m->inv_range;
+
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t ntiles = (a.n + 31) >> 5;
+    for (int64_t tile = wave; tile < ntiles; tile += nwaves) {
+        const int64_t i = tile * 32 + j;
+        const bool active = i < a.n;
+        const uint64_t bits = active ? a.in[i] : 0;
+        const uint64_t okey = order_key(bits, a.is_f64);
+        double x = 0.0;
+        const bool mapped = active && translate_key(bits, a.is_f64, lo, inv, &x);
+        const float xh = (float)x;
+        const float xl = (float)(x - (double)xh);
+
+        floatx16 acc[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[rb][v] = b2r[rb][v];
+
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            float h[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int u = 16 * s + 8 * g + t;
+                float z = __builtin_fmaf(s_w1[u], xh, s_b1[u]);
+                z = __builtin_fmaf(s_w1[u], xl, z);
+                h[t] = z > 0.0f ? z : 0.0f;
+            }
+            u32x4 B0, B1, B2;
+            float r1[8], r2[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                float hi = __uint_as_float(__float_as_uint(h[t]) & 0xFFFF0000u);
+                r1[t] = h[t] - hi;
+                if (T >= 3) {
+                    float mid = __uint_as_float(__float_as_uint(r1[t]) & 0xFFFF0000u);
+                    r2[t] = r1[t] - mid;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                B0[q] = pack_hi(h[2 * q], h[2 * q + 1]);
+                if (T >= 2) B1[q] = pack_hi(r1[2 * q], r1[2 * q + 1]);
+                if (T >= 3) B2[q] = pack_hi(r2[2 * q], r2[2 * q + 1]);
+            }
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const bf16x8 av = as_bf16x8(A[rb][s]);
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, as_bf16x8(B0), acc[rb], 0, 0, 0);
+                if (T >= 2)
+                    acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, as_bf16x8(B1), acc[rb], 0, 0, 0);
+                if (T >= 3)
+                    acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, as_bf16x8(B2), acc[rb], 0, 0, 0);
+            }
+        }
+
+        // layer 3: Kahan-compensated sum of w3 * relu(z2) over this lane's units
+        float sum = g == 0 ? b3 : 0.0f, c = 0.0f;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                float h2 = acc[rb][v] > 0.0f ? acc[rb][v] : 0.0f;
+                float y = w3r[rb][v] * h2 - c;
+                float t = sum + y;
+                c = (t - sum) - y;
+                sum = t;
+            }
+        const float osum = __shfl_xor(sum, 32);
+        const float oc = __shfl_xor(c, 32);
+        const double F = ((double)sum - (double)c) + ((double)osum - (double)oc);
+        const uint32_t slot = mapped ? slot_of(F, a.M) : kUnmapped;
+        const bool mine = active && g == 0;
+        if (mine) {
+            if (a.slots_out) a.slots_out[i] = slot;
+            if (a.F_out) a.F_out[i] = mapped ? F : __longlong_as_double(0x7FF8000000000000ll);
+        }
+        place_key(a, i, mine, okey, slot);
+    }
+}
+
+hipError_t launch_bf16_infer(const InferArgs& a, int H, int bf16_terms, hipStream_t st) {
+    int64_t tiles = (a.n + 31) / 32;
+    int64_t blocks = (tiles + 3) / 4;
+    if (blocks > 256 * 16) blocks = 256 * 16;
+    if (blocks < 1) blocks = 1;
+    dim3 grid((unsigned)blocks), block(256);
+#define NNS_BF16_CASE(HH, TT)                                                     \
+    if (H == HH && bf16_terms == TT) {                                           \
+        hipLaunchKernelGGL((k_infer_bf16<HH, TT>), grid, block, 0, st, a);       \
+        return hipGetLastError();                                                \
+    }
+    NNS_BF16_CASE(32, 1)
+    NNS_BF16_CASE(32, 2)
+    NNS_BF16_CASE(32, 3)
+    NNS_BF16_CASE(64, 1)
+    NNS_BF16_CASE(64, 2)
+    NNS_BF16_CASE(64, 3)
+#undef NNS_BF16_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace nns

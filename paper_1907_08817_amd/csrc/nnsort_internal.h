@@ -1,0 +1,131 @@
+// Internal declarations shared by the HIP translation units of libnnsort.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/nnsort.h"
+
+namespace nns {
+
+constexpr uint32_t kUnmapped = 0xFFFFFFFFu;
+
+// Slot-range buckets: the sorting phase's slot array o_i is cut into ranges of
+// kBucketSlots consecutive slots; the keys predicted into one range are
+// gathered into a fixed-capacity region of kBucketCap entries so that one
+// workgroup can run every round and the polish of that range in LDS.
+constexpr int kLogBucketSlots = 11;
+constexpr uint32_t kBucketSlots = 1u << kLogBucketSlots;
+constexpr uint32_t kBucketCap = 4096;
+constexpr int kBucketThreads = 256;
+constexpr int kItemsPerThread = kBucketCap / kBucketThreads;  // 16
+
+// Counters kept in the workspace (uint64 each).
+enum Counter : int {
+    kCntSpill = 0,        // entries in the spill list
+    kCntUnmapped = 1,     // keys with no slot
+    kCntCollided = 2,     // [2, 2 + 8): |c_r| for r = 1..8 (all buckets)
+    kCntPlaced = 10,      // [10, 18): keys stored in o_r
+    kCntBigKeys = 18,     // keys of big buckets
+    kCntBigBuckets = 19,
+    kCntGlobal = 20,      // entries in the global residue list G
+    kCntBoundary = 21,    // keys inside boundary fix-up zones
+    kCntFallback = 22,    // nonzero: tile fix-up needs the full-sort fallback
+    kCntBadSlot = 23,     // caller-given slot out of range
+    kCntSmallBuckets = 24,
+    kCntPosErrSum = 25,   // double bits: sum |F n - p|
+    kCntPosErrCnt = 26,
+    kNumCounters = 32
+};
+
+// A spill entry: a key whose bucket region was full, or that has no slot.
+struct SpillEntry {
+    uint64_t okey;
+    uint32_t idx;
+    uint32_t slot;
+};
+
+// IEEE 754-2019 totalOrder as an unsigned 64-bit key (identity for uint64).
+__device__ __forceinline__ uint64_t order_key(uint64_t bits, bool is_f64) {
+    if (!is_f64) return bits;
+    return (bits >> 63) ? ~bits : (bits | 0x8000000000000000ull);
+}
+__device__ __forceinline__ uint64_t order_key_inverse(uint64_t key, bool is_f64) {
+    if (!is_f64) return key;
+    return (key >> 63) ? (key & 0x7FFFFFFFFFFFFFFFull) : ~key;
+}
+
+// Device copy of the model in the FP32 layout the kernels read, padded to a
+// multiple of 32 hidden units with zero weights.
+struct DevModel {
+    int H;       // padded width (32 or 64)
+    int H_true;  // width of the caller's model
+    double lo;
+    double inv_range;
+    float w1[64];
+    float b1[64];
+    float w2[64 * 64];  // [i * H + j]
+    float b2[64];
+    float w3[64];
+    float b3;
+};
+
+// Workspace carve-up for a sort of n keys.
+struct SortPlan {
+    int64_t n;
+    int64_t S;         // slots
+    int64_t NB;        // buckets
+    int64_t big_max;   // capacity for big buckets' slot histograms
+    size_t off_counters, off_cnt, off_region_key, off_region_meta, off_spill, off_bucket_info,
+        off_segminmax, off_G, off_radix, off_M, off_big_hist, off_model, off_bigmap, total;
+    size_t radix_bytes;
+};
+
+SortPlan plan_sort(int64_t n, double m);
+size_t radix_ws_bytes(int64_t n);
+
+// ---- launchers (each returns hipError_t of its launch) ----
+struct InferArgs {
+    const DevModel* model;
+    const uint64_t* in;
+    int64_t n;
+    int is_f64;
+    double M;
+    int64_t S;
+    const uint32_t* given_slots;  // non-null: use these slots, no inference
+    uint32_t* slots_out;          // optional per-key slot
+    double* F_out;                // optional per-key F
+    int scatter;                  // 1: hand keys to bucket regions / spill
+    uint32_t* cnt;
+    uint64_t* region_key;
+    uint64_t* region_meta;
+    SpillEntry* spill;
+    unsigned long long* counters;
+};
+
+// H is the padded model width (32 or 64).
+hipError_t launch_infer(const InferArgs& a, int H, int form, int bf16_terms, hipStream_t st);
+
+// Radix sort of 64-bit keys: in_mode/out_mode 0 = order keys, 1 = f64 bits,
+// 2 = u64 bits (converted on load / store).
+hipError_t radix_sort(const uint64_t* d_in, uint64_t* d_out, int64_t n, int in_mode, int out_mode,
+                      void* d_ws, size_t ws_bytes, hipStream_t st);
+
+// Merge two ascending order-key arrays into bits (out_mode as above).
+hipError_t launch_merge(const uint64_t* d_a, int64_t na, const uint64_t* d_b, int64_t nb,
+                        uint64_t* d_out, int out_mode, hipStream_t st);
+
+// Copy with conversion between order keys and bits.
+hipError_t launch_convert(const uint64_t* d_in, uint64_t* d_out, int64_t n, int in_mode, int out_mode,
+                          hipStream_t st);
+
+// Fit.
+hipError_t launch_mlp_forward(int H, const float* d_theta, const double* d_x, int64_t B, float* d_F,
+                              float* d_saved, hipStream_t st);
+hipError_t launch_mlp_backward(int H, const float* d_theta, const double* d_x, int64_t B,
+                               const float* d_saved, const float* d_gF, float* d_gtheta, float* d_ws,
+                               hipStream_t st);
+hipError_t launch_adam(float* d_theta, const float* d_g, float* d_m1, float* d_m2, int64_t count,
+                       int64_t t, float lr, float b1, float b2, float eps, hipStream_t st);
+
+}  // namespace nns

@@ -1,0 +1,351 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Sorted output: bit-exact.  Round counts |c_r| and stored keys per round: equal
+(they depend only on the slots, and the FP32 form's slots are reproduced bit
+for bit).  BF16 form: its slots are checked against an a-priori error bound
+around the oracle's FP64 evaluation of the bf16-rounded model, and its round
+counts against the slot-histogram identity.  Every input is seeded synthetic
+data; models come from the oracle's fit or from closed forms.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1907_08817_amd as nn
+from paper_1907_08817_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def to_dev(x: np.ndarray):
+    if x.dtype == np.float64:
+        return torch.from_numpy(x.copy()).to(DEV)
+    return torch.from_numpy(x.view(np.int64).copy()).to(DEV)
+
+
+def to_host(t, like_dtype) -> np.ndarray:
+    a = t.cpu().numpy()
+    return a.view(np.uint64) if np.dtype(like_dtype) == np.uint64 else a
+
+
+def bits(a: np.ndarray) -> np.ndarray:
+    return np.ascontiguousarray(a).view(np.uint64)
+
+
+def assert_same_bits(got: np.ndarray, expect: np.ndarray):
+    g, e = bits(got), bits(expect)
+    assert g.shape == e.shape
+    bad = np.nonzero(g != e)[0]
+    assert bad.size == 0, f"{bad.size} mismatches, first at {bad[:5]}"
+
+
+def random_model(H, seed, lo=0.0, inv=1.0):
+    rng = np.random.default_rng(seed)
+    th = rng.uniform(-1, 1, O.num_params(H)).astype(np.float32)
+    th[2 * H:2 * H + H * H] /= math.sqrt(H)
+    return {"H": H, "lo": lo, "inv_range": inv, "theta": th}
+
+
+def gpu_sort(x, model, **kw):
+    sp = nn.sort_params(stats_level=2, **kw)
+    out, st = nn.nnsort_sort_with_model(nn.model_from_dict(model), to_dev(x), sp=sp)
+    torch.cuda.synchronize()
+    return to_host(out, x.dtype), st
+
+
+# ---------------------------------------------------------------------------
+# FP32 form: slots reproduced bit for bit
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,n,H", [("uniform", 1_000_000, 32), ("lognormal", 300_001, 32),
+                                      ("gauss_mix", 200_003, 64), ("zipf_u64", 100_000, 64)])
+def test_fp32_slots_bit_exact(name, n, H):
+    x = W.make(name, n)
+    model = O.fit(x, H=H, sample_frac=0.01, batch=4096, steps=5)
+    slots, F = nn.nnsort_predict(nn.model_from_dict(model), to_dev(x), nn.sort_params())
+    s_gpu = slots.cpu().numpy().astype(np.uint32)
+    s_orc = O.predict_slots(x, model, form=O.FORM_FP32C)
+    assert np.array_equal(s_gpu, s_orc), np.count_nonzero(s_gpu != s_orc)
+    xh, ok = O.translate(x, model["lo"], model["inv_range"])
+    F_orc = O.eval_F(xh, model, O.FORM_FP32C)
+    assert np.array_equal(F.cpu().numpy()[ok], F_orc[ok])
+
+
+def test_fp32_slots_random_weights_and_edge_keys():
+    x = np.concatenate([W.edge_keys(), W.gauss_mix(5000, seed=9) * 1e-3])
+    for H, seed in ((32, 1), (64, 2), (20, 3)):
+        model = random_model(H, seed, lo=-2.0, inv=0.25)
+        slots, _ = nn.nnsort_predict(nn.model_from_dict(model), to_dev(x), nn.sort_params())
+        assert np.array_equal(slots.cpu().numpy().astype(np.uint32), O.predict_slots(x, model))
+
+
+# ---------------------------------------------------------------------------
+# full procedure, FP32 form
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,n,H", [("uniform", 1_000_000, 32), ("lognormal", 500_000, 32),
+                                      ("gauss_mix", 300_000, 64), ("zipf_u64", 300_000, 64),
+                                      ("piecewise_uniform", 400_000, 32)])
+def test_sort_matches_oracle(name, n, H):
+    x = W.make(name, n)
+    model = O.fit(x, H=H, sample_frac=0.01, batch=4096, steps=5)
+    out, st = gpu_sort(x, model)
+    ref, ost = O.nnsort(x, model)
+    assert_same_bits(out, ref)
+    assert st["rounds"] == ost["rounds"]
+    assert st["collided"] == ost["collided"]
+    assert st["placed"] == ost["placed"]
+    assert st["residue"] == ost["residue"]
+    if st["fallback"] == 0:
+        assert st["boundary_keys"] < n
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 100, 1024, 1025, 2049, 4097, 65_537, 131_071])
+def test_sort_ragged_sizes(n):
+    x = W.lognormal(n, seed=n)
+    model = O.fit(x, H=32, sample_frac=0.5, batch=256, steps=2) if n else random_model(32, 0)
+    out, st = gpu_sort(x, model)
+    ref, ost = O.nnsort(x, model)
+    assert_same_bits(out, ref)
+    assert st["rounds"] == ost["rounds"] and st["collided"] == ost["collided"]
+
+
+def test_sort_edge_keys_and_tau_zero():
+    x = np.concatenate([W.edge_keys(seed=s) for s in range(20)])
+    model = random_model(32, 4, lo=-3.0, inv=1 / 6.0)
+    for eps, tau in ((1, 0), (3, 0), (8, 10)):
+        out, st = gpu_sort(x, model, eps=eps, tau=tau)
+        ref, ost = O.nnsort(x, model, eps=eps, tau=tau)
+        assert_same_bits(out, ref)
+        assert st["collided"] == ost["collided"] and st["unmapped"] > 0
+
+
+# ---------------------------------------------------------------------------
+# closed-form slots through nnsort_sort_with_slots
+# ---------------------------------------------------------------------------
+def gpu_sort_slots(x, slots, **kw):
+    sp = nn.sort_params(**kw)
+    out, st = nn.nnsort_sort_with_slots(torch.from_numpy(slots.astype(np.int64)).to(DEV), to_dev(x), sp=sp)
+    torch.cuda.synchronize()
+    return to_host(out, x.dtype), st
+
+
+def test_constant_slot_worst_case():
+    """Every key in one slot: the densest range goes through the radix path
+    and each round stores one key (|c_r| = n - r)."""
+    x = W.uniform(300_000, seed=1)
+    slots = np.full(x.size, 12345, np.uint32)
+    out, st = gpu_sort_slots(x, slots, eps=5, tau=0)
+    assert_same_bits(out, np.sort(x))
+    assert st["collided"] == [x.size - r for r in range(1, 6)]
+    assert st["big_buckets"] == 1
+
+
+def test_perfect_rank_and_reversed_slots():
+    x = W.uniform(400_000, seed=2)
+    rank = np.empty(x.size, np.int64)
+    rank[np.argsort(x)] = np.arange(x.size)
+    for F in (rank / x.size, (x.size - 1 - rank) / x.size):
+        slots = O.slots_from_F(F, 1.25 * x.size)
+        out, st = gpu_sort_slots(x, slots, tau=0)
+        ref, ost = O.nnsort(x, {"H": 1, "lo": 0, "inv_range": 1, "theta": np.zeros(6, np.float32)}, slots=slots,
+                            tau=0)
+        assert_same_bits(out, ref)
+        assert st["collided"] == ost["collided"] == [0, 0, 0]
+
+
+def test_duplicate_groups_closed_form():
+    rng = np.random.default_rng(5)
+    vals = rng.permutation(40_000).astype(np.float64)
+    g = rng.integers(1, 9, vals.size)
+    x = rng.permutation(np.repeat(vals, g))
+    vrank = np.searchsorted(np.sort(vals), x)
+    slots = O.slots_from_F(vrank / vals.size, 1.25 * x.size)
+    out, st = gpu_sort_slots(x, slots, eps=4, tau=0)
+    assert_same_bits(out, np.sort(x))
+    k = np.bincount(slots.astype(np.int64))
+    assert st["collided"] == [int(np.maximum(0, k - r).sum()) for r in range(1, 5)]
+
+
+def test_bad_slot_rejected():
+    x = W.uniform(5000, seed=3)
+    slots = np.zeros(x.size, np.uint32)
+    slots[7] = 10 ** 6   # beyond S
+    with pytest.raises(nn.NNSortError):
+        gpu_sort_slots(x, slots, tau=0)
+
+
+# ---------------------------------------------------------------------------
+# BF16 form
+# ---------------------------------------------------------------------------
+def _mag_bf16(model, x):
+    H = model["H"]
+    th = model["theta"].astype(np.float64)
+    w1, b1 = th[:H], th[H:2 * H]
+    W2 = np.array([O.round_bf16(v) for v in th[2 * H:2 * H + H * H]]).reshape(H, H)
+    b2, w3, b3 = th[2 * H + H * H:3 * H + H * H], th[3 * H + H * H:4 * H + H * H], th[-1]
+    a1 = np.abs(w1)[None, :] * np.abs(x)[:, None] + np.abs(b1)[None, :]
+    a2 = np.abs(b2)[None, :] + a1 @ np.abs(W2).T
+    return np.abs(b3) + a2 @ np.abs(w3)
+
+
+@pytest.mark.parametrize("H", [32, 64])
+def test_bf16_F_within_bound(H):
+    """F of the BF16 form vs the FP64 evaluation of the same model with W2
+    rounded to bf16: the three-term split is exact, so the difference is FP32
+    accumulation only, |dF| <= 2 gamma_{3H+8} * (sum of |terms|)."""
+    x = W.gauss_mix(100_000, seed=4)
+    model = O.fit(x, H=H, sample_frac=0.05, batch=4096, steps=3)
+    sp = nn.sort_params(form=nn.FORM_BF16, bf16_terms=3)
+    _, F = nn.nnsort_predict(nn.model_from_dict(model), to_dev(x), sp)
+    xh, ok = O.translate(x, model["lo"], model["inv_range"])
+    ref = O.eval_F(xh, model, O.FORM_BF16W)
+    u = 2.0 ** -24
+    k = 3 * H + 8
+    bound = 2 * k * u / (1 - k * u) * _mag_bf16(model, xh)
+    d = np.abs(F.cpu().numpy() - ref)
+    assert np.all(d[ok] <= bound[ok] + 1e-300), float(np.max(d[ok] / bound[ok]))
+
+
+@pytest.mark.parametrize("terms", [1, 2, 3])
+def test_bf16_sort_exact_and_counts(terms):
+    x = W.gauss_mix(400_000, seed=6)
+    model = O.fit(x, H=64, sample_frac=0.01, batch=4096, steps=3)
+    m = nn.model_from_dict(model)
+    sp = nn.sort_params(form=nn.FORM_BF16, bf16_terms=terms, tau=0, stats_level=1)
+    xd = to_dev(x)
+    out, st = nn.nnsort_sort_with_model(m, xd, sp=sp)
+    assert_same_bits(to_host(out, x.dtype), O.sort_reference(x))
+    slots, _ = nn.nnsort_predict(m, xd, sp)
+    s = slots.cpu().numpy().astype(np.int64)
+    k = np.bincount(s[s != 0xFFFFFFFF])
+    assert st["collided"] == [int(np.maximum(0, k - r).sum()) for r in range(1, 4)]
+
+
+# ---------------------------------------------------------------------------
+# determinism, radix sort, fit, gradients, errors
+# ---------------------------------------------------------------------------
+def test_repeat_runs_identical():
+    x = W.lognormal(600_000, seed=12)
+    model = O.fit(x, H=32, sample_frac=0.01, batch=4096, steps=3)
+    a, sa = gpu_sort(x, model)
+    b, sb = gpu_sort(x, model)
+    assert_same_bits(a, b)
+    for k in ("collided", "placed", "residue", "boundary_keys"):
+        assert sa[k] == sb[k]
+
+
+@pytest.mark.parametrize("name,n", [("uniform", 1), ("lognormal", 4095), ("gauss_mix", 4097),
+                                    ("zipf_u64", 1_000_003), ("uniform", 2_000_000)])
+def test_radix_sort(name, n):
+    x = W.make(name, n)
+    out = nn.nnsort_radix_sort(to_dev(x))
+    assert_same_bits(to_host(out, x.dtype), O.sort_reference(x))
+
+
+def test_radix_sort_edge_keys():
+    x = np.concatenate([W.edge_keys(seed=s) for s in range(50)])
+    out = nn.nnsort_radix_sort(to_dev(x))
+    assert_same_bits(to_host(out, x.dtype), O.sort_reference(x))
+
+
+@pytest.mark.parametrize("init,H", [(1, 32), (0, 16), (1, 64)])
+def test_fit_init_matches_oracle(init, H):
+    """Same Philox sample and initialisation: identical weights at step 0."""
+    x = W.lognormal(200_000, seed=5)
+    fp = nn.fit_params(hidden=H, sample_frac=0.05, steps=0, init=init, seed=77)
+    m = nn.nnsort_fit(to_dev(x), fp)
+    got = nn.model_to_dict(m)
+    ref = O.fit(x, H=H, sample_frac=0.05, steps=0, init=init, seed=77)
+    assert got["lo"] == ref["lo"] and got["inv_range"] == ref["inv_range"]
+    assert np.array_equal(got["theta"], ref["theta"])
+
+
+def test_fit_loss_tracks_oracle():
+    x = W.uniform(100_000, seed=8)
+    fp = nn.fit_params(hidden=16, sample_frac=0.2, batch=2048, steps=30, init=0, lr=1e-2, seed=3)
+    m, hist = nn.nnsort_fit(to_dev(x), fp, history=True)
+    ref, rhist = O.fit(x, H=16, sample_frac=0.2, batch=2048, steps=30, init=0, lr=1e-2, seed=3,
+                       return_history=True)
+    assert abs(hist[0] - rhist[0]) <= 1e-5 * max(1.0, rhist[0])
+    assert hist[-1] < 0.5 * hist[0]
+    assert abs(hist[-1] - rhist[-1]) <= 0.05 * rhist[-1] + 1e-6
+
+
+@pytest.mark.parametrize("H,loss", [(8, 0), (32, 0), (64, 0), (32, 1)])
+def test_gradient_vs_fp64_reference(H, loss):
+    rng = np.random.default_rng(H)
+    model = random_model(H, 10 + H)
+    th = torch.from_numpy(model["theta"]).to(DEV)
+    B = 3000
+    x = rng.random(B)
+    y = rng.random(B)
+    xd = torch.from_numpy(x).to(DEV)
+    yd = torch.from_numpy(y.astype(np.float32)).to(DEV)
+    saved = torch.empty(B * 2 * H, dtype=torch.float32, device=DEV)
+    F = nn.nnsort_mlp_forward(H, th, xd, saved)
+    L, gF = nn.nnsort_loss_grad(F, yd, loss=loss, delta=0.3)
+    g = nn.nnsort_mlp_backward(H, th, xd, saved, gF).cpu().numpy().astype(np.float64)
+    Lr, gr = O.loss_grad(model["theta"].astype(np.float64), H, x, y.astype(np.float32).astype(np.float64), loss,
+                         0.3)
+    assert abs(float(L.item()) - Lr) <= 1e-5 * max(1.0, Lr)
+    assert np.linalg.norm(g - gr) <= 1e-4 * np.linalg.norm(gr)
+
+
+def test_gradient_vs_finite_differences_through_autograd():
+    """torch.autograd through NNSortMLPFn; compared with central differences of
+    the FP64 loss of the oracle on parameters away from ReLU kinks."""
+    H = 16
+    rng = np.random.default_rng(1)
+    model = random_model(H, 31)
+    x = rng.random(512)
+    y = rng.random(512)
+    th = torch.from_numpy(model["theta"]).to(DEV).requires_grad_(True)
+    F = nn.mlp(torch.from_numpy(x).to(DEV), th, H)
+    L = ((F.double() - torch.from_numpy(y).to(DEV)) ** 2).mean()
+    L.backward()
+    g = th.grad.cpu().numpy().astype(np.float64)
+    t64 = model["theta"].astype(np.float64)
+    checked = 0
+    for p in range(t64.size):
+        h = 1e-6 * max(1.0, abs(t64[p]))
+        tp, tm = t64.copy(), t64.copy()
+        tp[p] += h
+        tm[p] -= h
+        L0 = O.loss_value(t64, H, x, y)
+        Lp, Lm = O.loss_value(tp, H, x, y), O.loss_value(tm, H, x, y)
+        if abs((Lp - L0) - (L0 - Lm)) > 1e-4 * max(abs(Lp - L0), 1e-12):
+            continue
+        cd = (Lp - Lm) / (2 * h)
+        assert abs(cd - g[p]) <= 1e-4 * max(1e-3, abs(cd)) + 1e-6, (p, cd, g[p])
+        checked += 1
+    assert checked > 0.7 * t64.size
+
+
+def test_adam_step_matches_oracle():
+    rng = np.random.default_rng(2)
+    P = 1000
+    th = rng.standard_normal(P).astype(np.float32)
+    g = rng.standard_normal(P).astype(np.float32)
+    d = {k: torch.from_numpy(v.copy()).to(DEV) for k, v in (("th", th), ("g", g))}
+    m1 = torch.zeros(P, dtype=torch.float32, device=DEV)
+    m2 = torch.zeros(P, dtype=torch.float32, device=DEV)
+    t64, m64, v64 = th.astype(np.float64), np.zeros(P), np.zeros(P)
+    for t in range(1, 4):
+        nn.nnsort_adam_step(d["th"], d["g"], m1, m2, t, lr=1e-3)
+        O.adam_step(t64, g.astype(np.float64), m64, v64, t, lr=1e-3)
+    assert np.allclose(d["th"].cpu().numpy(), t64, rtol=0, atol=1e-6)
+
+
+def test_errors_reported():
+    x = to_dev(W.uniform(5000, seed=1))
+    m = nn.model_from_dict(random_model(32, 1))
+    with pytest.raises(nn.NNSortError):
+        nn.nnsort_sort_with_model(m, x, out=x)            # in place is rejected
+    with pytest.raises(nn.NNSortError):
+        nn.nnsort_sort_with_model(m, x, ws=nn.alloc_workspace(1024))
+    with pytest.raises(nn.NNSortError):
+        nn.nnsort_sort_with_model(m, x, sp=nn.sort_params(eps=9))

@@ -1,0 +1,109 @@
+"""CPU-side checks of libnnsort: it loads, exports every entry point that
+include/nnsort.h declares, and its host-only paths (parameters, workspace
+sizes, argument checks that return before any device work, model files)
+behave as documented.  No kernel runs here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1907_08817_amd as nn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "nnsort.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nnsort_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = nn._lib()
+    names = header_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_layouts_match_header_sizes():
+    # sizes implied by the header's field lists (natural alignment, x86-64)
+    assert ctypes.sizeof(nn.SortParams) == 32
+    assert ctypes.sizeof(nn.FitParams) == 48
+    assert ctypes.sizeof(nn.Model) == 8 + 16 + 4 * (64 * 4 + 64 * 64 + 1 + 3)
+    assert ctypes.sizeof(nn.Stats) == 8 + 8 + 16 * 8 + 5 * 8 + 8 + 8 + 6 * 8
+
+
+def test_default_params():
+    sp, fp = nn.default_params()
+    assert (sp.m, sp.eps, sp.tau, sp.form, sp.bf16_terms) == (1.25, 3, 1024, nn.FORM_FP32, 3)
+    assert (fp.hidden, fp.batch, fp.steps, fp.init, fp.loss) == (32, 65536, 200, 1, 0)
+    assert abs(fp.sample_frac - 0.01) < 1e-15
+
+
+def test_workspace_size_grows_and_validates():
+    sp, fp = nn.default_params()
+    a = nn.workspace_size(10 ** 6, nn.F64, sp)
+    b = nn.workspace_size(10 ** 7, nn.F64, sp)
+    assert 0 < a < b
+    assert nn.workspace_size(100, nn.F64, sp) > 0          # n <= tau: radix scratch only
+    assert nn.workspace_size(10 ** 6, nn.F64, sp, fp) >= a
+    bad = nn.sort_params(eps=0)
+    with pytest.raises(nn.NNSortError):
+        nn.workspace_size(10, nn.F64, bad)
+    with pytest.raises(nn.NNSortError):
+        nn.workspace_size(10, nn.F64, nn.sort_params(m=-1.0))
+    with pytest.raises(nn.NNSortError):
+        nn.workspace_size(10, nn.F64, nn.sort_params(form=7))
+    with pytest.raises(nn.NNSortError):
+        nn.workspace_size(2 ** 32, nn.F64, sp)               # beyond 32-bit indices
+    with pytest.raises(nn.NNSortError):
+        nn.workspace_size(10, nn.F64, sp, nn.fit_params(hidden=12))
+
+
+def test_argument_checks_before_device_work():
+    L = nn._lib()
+    sp, fp = nn.default_params()
+    m = nn.Model()
+    # null model / wrong version / width
+    p = ctypes.c_void_p(0x100000)
+    q = ctypes.c_void_p(0x900000)
+    assert L.nnsort_sort_with_model(None, None, None, 0, 0, ctypes.byref(sp), None, 0, None, None) == -1
+    assert L.nnsort_sort_with_model(ctypes.byref(m), p, q, 10, 0, ctypes.byref(sp), None, 0, None,
+                                    None) == -4
+    m.version, m.hidden = 1, 16
+    # null pointers with n > 0
+    assert L.nnsort_sort_with_model(ctypes.byref(m), None, None, 10, 0, ctypes.byref(sp), None, 0, None,
+                                    None) == -1
+    # overlapping input and output
+    assert L.nnsort_sort_with_model(ctypes.byref(m), p, ctypes.c_void_p(0x100008), 10, 0, ctypes.byref(sp), None,
+                                    0, None, None) == -1
+    # workspace too small (checked before any launch)
+    assert L.nnsort_sort_with_model(ctypes.byref(m), p, q, 5000, 0, ctypes.byref(sp), q, 16, None, None) == -2
+    # fit: bad hidden width
+    bad = nn.fit_params(hidden=5)
+    assert L.nnsort_fit(p, 10, 0, ctypes.byref(bad), ctypes.byref(m), q, 1 << 20, None) == -1
+    assert L.nnsort_radix_sort(p, q, -1, 0, None, 0, None) == -1
+    assert L.nnsort_mlp_forward(24, p, p, 4, p, None, None) == -1
+    assert L.nnsort_adam_step(p, p, p, p, 4, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert "invalid" in L.nnsort_strerror(-1).decode()
+
+
+def test_model_file_round_trip(tmp_path):
+    rng = np.random.default_rng(0)
+    H = 24
+    d = {"H": H, "lo": -3.5, "inv_range": 0.125,
+         "theta": rng.standard_normal(H * H + 4 * H + 1).astype(np.float32)}
+    m = nn.model_from_dict(d)
+    path = str(tmp_path / "m.nnsm")
+    nn.model_save(m, path)
+    back = nn.model_to_dict(nn.model_load(path))
+    assert back["H"] == H and back["lo"] == -3.5 and back["inv_range"] == 0.125
+    assert np.array_equal(back["theta"], d["theta"])
+    open(path, "r+b").write(b"XXXX")
+    with pytest.raises(nn.NNSortError):
+        nn.model_load(path)
+    with pytest.raises(nn.NNSortError):
+        nn.model_load(str(tmp_path / "missing"))
