@@ -1,0 +1,239 @@
+"""Benchmark: sorted Gkeys/s of NN-sort on one MI355X.
+
+Workload (default): 1e8 float64 keys from a skewed mixture of 8 Gaussians
+(weights Dirichlet(0.3), means U[-1e6, 1e6], sigma log-uniform in [1, 1e4])
+with 1% duplicated keys; model 1 -> 64 -> 64 -> 1 fitted on the device from a
+1% sample (200 Adam steps, done once before timing, as the paper excludes
+training from the sort time); inference in the BF16 form (hidden layer on
+bf16 matrix cores, FP32 accumulation).  A step is one full sort of the
+resident keys: map, rounds, polish, residue sort and merge.
+
+Beside the headline it reports the FP32 form on the same weights, a full-n
+GPU radix sort, the fit time, and the CPU oracle on a bounded sample of the
+same workload.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+BF16_PEAK_TFLOPS = 2500.0      # dense bf16 MFMA
+FP32_VALU_PEAK_TFLOPS = 157.3  # vector FP32
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="gauss_mix_1e8_bf16_h64")
+    ap.add_argument("--n", type=int, default=0, help="override the key count (testing only)")
+    ap.add_argument("--bf16-terms", type=int, default=3)
+    ap.add_argument("--no-context", action="store_true", help="skip FP32/radix/CPU context legs")
+    ap.add_argument("--cpu-sample", type=int, default=4_000_000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (for counter calibration)")
+    return ap.parse_args()
+
+
+def src_sha(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def load_traffic(kernel: str, sha: str):
+    """Measured HBM bytes per launch of `kernel` from the committed counter
+    summary, or None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    e = d.get(kernel)
+    if not e or e.get("source_sha256") != sha:
+        return None
+    return e.get("bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sharded path is not built",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1907_08817_amd as nn
+    from paper_1907_08817_amd import workloads as W
+
+    name, n_cfg, H, form, frac = W.CONFIGS[args.workload]
+    n = args.n or n_cfg
+    t0 = time.time()
+    x = W.make(name, n)
+    gen_s = time.time() - t0
+    dev = torch.device("cuda:0")
+    keys = torch.from_numpy(x if x.dtype == np.float64 else x.view(np.int64)).to(dev)
+    out = torch.empty_like(keys)
+    dt = nn.F64 if x.dtype == np.float64 else nn.U64
+
+    form_code = nn.FORM_BF16 if form == "bf16" else nn.FORM_FP32
+    sp = nn.sort_params(form=form_code, bf16_terms=args.bf16_terms, stats_level=1)
+    fp = nn.fit_params(hidden=H, sample_frac=frac)
+    ws = nn.alloc_workspace(nn.workspace_size(n, dt, sp, fp), dev)
+
+    # device fit (once; excluded from the sort time, reported separately)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    model = nn.nnsort_fit(keys, fp, ws=ws)
+    torch.cuda.synchronize()
+    fit_ms = (time.perf_counter() - t0) * 1e3
+
+    def run_sort(params):
+        return nn.nnsort_sort_with_model(model, keys, out=out, sp=params, ws=ws)
+
+    for _ in range(args.warmup):
+        run_sort(sp)
+    torch.cuda.synchronize()
+    infer_ms, stats = [], None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, stats = run_sort(sp)
+        infer_ms.append(stats["t_infer_ms"])
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    value = n / (ms_per_step * 1e-3) / 1e9
+
+    # correctness spot check of the timed output (non-decreasing order keys)
+    o = out.view(torch.int64)
+    top = torch.tensor(-(2 ** 63), dtype=torch.int64, device=dev)
+    if dt == nn.F64:
+        k = torch.where(o < 0, (~o) ^ top, o)  # totalOrder key with its top bit flipped (signed order)
+    else:
+        k = o ^ top
+    sorted_ok = bool((k[1:] >= k[:-1]).all().item())
+
+    # roofline of the dominant kernel: the model map (inference + hand-off)
+    k1_ms = float(np.mean(infer_ms))
+    flop_per_key = 2 * (2 * H + H * H)
+    achieved_tflops = flop_per_key * n / (k1_ms * 1e-3) / 1e12
+    kname = f"k_infer_bf16<{64 if H > 32 else 32},{args.bf16_terms}>" if form == "bf16" else \
+        f"k_infer_fp32<{64 if H > 32 else 32}>"
+    ksha = src_sha(["paper_1907_08817_amd/csrc/infer_bf16.hip" if form == "bf16" else
+                    "paper_1907_08817_amd/csrc/infer.hip", "paper_1907_08817_amd/csrc/infer_common.h"])
+    traffic = load_traffic(kname, ksha)
+    peak = BF16_PEAK_TFLOPS if form == "bf16" else FP32_VALU_PEAK_TFLOPS
+    roofline = {"bound": "mfma" if form == "bf16" else "alu", "kernel": kname,
+                "achieved": round(achieved_tflops, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved_tflops / peak, 5), "traffic": traffic,
+                "flop_per_key": flop_per_key, "keys_per_launch": n, "avg_launch_ms": round(k1_ms, 4)}
+
+    # whole-sort algorithmic HBM bytes: keys read, placed keys written/read,
+    # conflict (key, slot) pairs written/read, residue radix passes, output
+    c = stats["collided"]
+    ct = stats["residue"]
+    placed = n - ct
+    alg_bytes = 8 * n + 16 * placed + 24 * sum(c) + 16 * 8 * ct + 8 * ct + 8 * n
+    e2e = {"alg_bytes_per_key": round(alg_bytes / n, 2),
+           "achieved_GBs": round(alg_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+           "frac_of_8TBs": round(alg_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    context = {}
+    if not args.no_context:
+        # FP32 form on the same weights
+        sp32 = nn.sort_params(form=nn.FORM_FP32, stats_level=1)
+        run_sort(sp32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = max(2, args.steps // 3)
+        for _ in range(reps):
+            _, st32 = run_sort(sp32)
+        torch.cuda.synchronize()
+        fp32_ms = (time.perf_counter() - t0) * 1e3 / reps
+        context["fp32_form_gkeys"] = round(n / (fp32_ms * 1e-3) / 1e9, 3)
+        context["fp32_form_ms"] = round(fp32_ms, 3)
+        context["fp32_infer_ms"] = round(st32["t_infer_ms"], 3)
+        context["bf16_vs_fp32"] = round(fp32_ms / ms_per_step, 3)
+        # full-n GPU LSD radix sort
+        rws = nn.alloc_workspace(nn._lib().nnsort_radix_workspace_size(n), dev)
+        nn.nnsort_radix_sort(keys, out=out, ws=rws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            nn.nnsort_radix_sort(keys, out=out, ws=rws)
+        torch.cuda.synchronize()
+        rad_ms = (time.perf_counter() - t0) * 1e3 / reps
+        context["radix_gkeys"] = round(n / (rad_ms * 1e-3) / 1e9, 3)
+        del rws
+    if args.copy_calibration:
+        a = torch.empty(n, dtype=torch.float64, device=dev)
+        a.copy_(keys)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_context and args.cpu_sample > 0:
+        import oracle
+        m = min(args.cpu_sample, n)
+        xs = x[:m]
+        mdict = nn.model_to_dict(model)
+        formc = oracle.FORM_BF16W if form == "bf16" else oracle.FORM_FP32C
+        t0 = time.perf_counter()
+        oracle.nnsort(xs, mdict, form=formc)
+        cpu_s = time.perf_counter() - t0
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cpu = {"value": round(m / cpu_s / 1e9, 6), "unit": "Gkeys/s", "cores": cores, "kind": "oracle",
+               "sample": f"first {m} keys of the same workload, same model, FP64 bf16-W2 evaluator; "
+                         f"{cpu_s:.1f} s"}
+
+    res = {
+        "metric": "sorted Gkeys/s at 1e8 f64 keys, BF16-MFMA vs FP32 NN-sort; % HBM roofline",
+        "value": round(value, 4),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16" if form == "bf16" else "fp32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "distribution": name, "n": n,
+                   "keys": "f64" if dt == nn.F64 else "u64", "hidden": H,
+                   "form": f"bf16x{args.bf16_terms}" if form == "bf16" else "fp32",
+                   "m": 1.25, "eps": 3, "tau": 1024, "fit": f"device, {frac:g} sample, 200 Adam steps, "
+                                                          "outside the timed region"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "sorted_ok": sorted_ok,
+        "fit_ms": round(fit_ms, 2),
+        "value_with_fit": round(n / ((ms_per_step + fit_ms) * 1e-3) / 1e9, 4),
+        "e2e_hbm": e2e,
+        "rounds": stats["rounds"],
+        "collided_frac": [round(v / n, 5) for v in c],
+        "residue_frac": round(ct / n, 5),
+        "boundary_keys": stats["boundary_keys"],
+        "fallback": stats["fallback"],
+        "big_bucket_keys": stats["big_bucket_keys"],
+        "phase_ms": {k: round(stats[k], 3) for k in ("t_infer_ms", "t_place_ms", "t_polish_ms",
+                                                       "t_residue_ms", "t_merge_ms", "t_total_ms")},
+        "context": context,
+        "datagen_s": round(gen_s, 1),
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -88,8 +88,10 @@ typedef struct {
  *  lr           Adam learning rate (beta1 0.9, beta2 0.999, eps 1e-8).
  *  seed         seed of the Philox4x32-10 streams (sample, init, batches).
  *  loss         0: mean squared error; 1: Huber with threshold huber_delta.
- *  init         0: uniform(+-1/sqrt(fan_in)); 1: quantile ramps (the
- *               piecewise-linear interpolant of the sample CDF). */
+ *  init         0: uniform(+-1/sqrt(fan_in)); 1 and 2: ramps forming the
+ *               piecewise-linear interpolant of the sample CDF through H+1
+ *               knots, placed by greedy maximum-deviation splitting (1) or at
+ *               the quantiles j/H (2). */
 typedef struct {
     int32_t hidden;
     int32_t batch;

@@ -310,16 +310,60 @@ def fit_sample(x: np.ndarray, sample_frac: float, seed: int):
     return s, lo, inv, xh, y
 
 
+def greedy_knot_indices(xs: np.ndarray, H: int) -> np.ndarray:
+    """Knots of the piecewise-linear interpolant of the sample CDF by greedy
+    splitting: starting from one piece over the sorted sample xs (ranks
+    y_j = (j + 0.5)/k), repeatedly split the piece whose points deviate most
+    (in rank) from the chord between its ends, at the point of largest
+    deviation, until H pieces.  Ties: the piece with the smaller start, then
+    the smaller point index.  A piece with fewer than 3 points, zero width, or
+    no point farther than one rank step (1/k) from the chord is never split.  Returns H + 1 sorted sample indices (the last repeated
+    if fewer than H pieces arise)."""
+    k = xs.size
+    y = (np.arange(k, dtype=np.float64) + 0.5) / k
+
+    def dev(a, b):
+        if b - a < 2 or xs[b] == xs[a]:
+            return 0.0, -1
+        j = np.arange(a + 1, b)
+        lin = y[a] + (y[b] - y[a]) * (xs[j] - xs[a]) / (xs[b] - xs[a])
+        d = np.abs(y[j] - lin)
+        m = int(np.argmax(d))   # first maximum
+        if not d[m] > 1.0 / k:
+            return 0.0, -1
+        return float(d[m]), int(j[m])
+
+    pieces = {0: (k - 1,) + dev(0, k - 1)}    # start -> (end, deviation, split point)
+    while len(pieces) < H:
+        best = None
+        for a in sorted(pieces):
+            b, d, j = pieces[a]
+            if j >= 0 and d > 0 and (best is None or d > pieces[best][1]):
+                best = a
+        if best is None:
+            break
+        b, d, j = pieces[best]
+        pieces[best] = (j,) + dev(best, j)
+        pieces[j] = (b,) + dev(j, b)
+    idx = sorted(pieces) + [k - 1]
+    while len(idx) < H + 1:
+        idx.append(k - 1)
+    return np.array(idx, np.int64)
+
+
 def init_theta(H: int, init: int, seed: int, xhat_sorted: np.ndarray) -> np.ndarray:
     """Initial weights (float64 holding float32-rounded values).
 
-    init 1 (quantile ramps): knot q_j at the sample quantile j/H, width
-    d_j = q_{j+1} - q_j (at least RAMP_MIN_WIDTH), slope s_j = 1/d_j; hidden-1
-    unit j is u_j = relu(s_j (x - q_j)), hidden-2 unit i is v_i = relu(1 - u_i),
-    F = 1 - mean_i v_i: the piecewise-linear interpolant of the sample CDF
-    through (q_j, j/H).  Slopes sit in layer 1 so that an Adam step (whose size
-    is about lr whatever the parameter's scale) moves a knot by about
-    lr * d_j rather than by lr.
+    init 1 and 2 (ramps): the piecewise-linear interpolant of the sample CDF
+    through knots (q_i, F_i), i = 0..H (q_i = sample value at knot index
+    idx_i, F_i = (idx_i + 0.5)/k), written as a network: hidden-1 unit i is
+    u_i = relu(s_i (x - q_i)) with s_i = 1/max(q_{i+1} - q_i, RAMP_MIN_WIDTH),
+    hidden-2 unit i is v_i = relu(1 - u_i) (a ramp from 1 down to 0 across
+    piece i), and F = F_H - sum_i (F_{i+1} - F_i) v_i.  Slopes sit in layer 1 so
+    that an Adam step (about lr whatever a parameter's scale) moves a knot by
+    about lr times the piece width.  init 1 places the knots by greedy
+    maximum-deviation splitting (greedy_knot_indices), init 2 at the quantiles
+    j/H.
     init 0: uniform(+-1/sqrt(fan_in)) from Philox."""
     P = num_params(H)
     th = np.zeros(P, np.float64)
@@ -327,11 +371,16 @@ def init_theta(H: int, init: int, seed: int, xhat_sorted: np.ndarray) -> np.ndar
     W2 = slice(2 * H, 2 * H + H * H)
     b2 = slice(2 * H + H * H, 3 * H + H * H)
     w3 = slice(3 * H + H * H, 4 * H + H * H)
-    if init == 1:
+    if init in (1, 2):
         k = xhat_sorted.size
         if k == 0:
             return th.astype(np.float32).astype(np.float64)
-        q = np.array([xhat_sorted[(j * (k - 1)) // H] for j in range(H + 1)], np.float64)
+        if init == 1:
+            idx = greedy_knot_indices(xhat_sorted, H)
+        else:
+            idx = np.array([(j * (k - 1)) // H for j in range(H + 1)], np.int64)
+        q = xhat_sorted[idx]
+        Fk = (idx.astype(np.float64) + 0.5) / k
         width = np.maximum(q[1:] - q[:-1], RAMP_MIN_WIDTH)
         s = 1.0 / width
         th[w1] = s
@@ -340,8 +389,8 @@ def init_theta(H: int, init: int, seed: int, xhat_sorted: np.ndarray) -> np.ndar
         np.fill_diagonal(Wm, -1.0)
         th[W2] = Wm.ravel()
         th[b2] = 1.0
-        th[w3] = -1.0 / H
-        th[P - 1] = 1.0
+        th[w3] = -(Fk[1:] - Fk[:-1])
+        th[P - 1] = Fk[H]
     else:
         bound2 = 1.0 / math.sqrt(H)
         for p in range(P):
@@ -354,9 +403,12 @@ def fit(x: np.ndarray, H: int = 32, sample_frac: float = 0.01, batch: int = 6553
         steps: int = 200, lr: float = 1e-7, seed: int = 0, init: int = 1, loss: int = 0,
         delta: float = 1.0, return_history: bool = False):
     """CPU FP64 fit of the CDF model: Adam on MSE (loss 0) or the paper's Huber
-    loss (loss 1) to the normalised rank of a random sample."""
+    loss (loss 1) to the normalised rank of a random sample.  Returns the
+    parameters with the lowest batch loss seen (a step's loss is measured
+    before its update; the initial parameters if no step improved)."""
     s, lo, inv, xh, y = fit_sample(x, sample_frac, seed)
     th = init_theta(H, init, seed, xh)
+    best, best_loss = th.copy(), math.inf
     m1 = np.zeros_like(th)
     m2 = np.zeros_like(th)
     hist = []
@@ -367,8 +419,10 @@ def fit(x: np.ndarray, H: int = 32, sample_frac: float = 0.01, batch: int = 6553
         bi = batch_indices(seed, t, k2, batch)
         L, g = loss_grad(th, H, xh[bi], y[bi], loss, delta)
         hist.append(L)
+        if L < best_loss:
+            best, best_loss = th.copy(), L
         adam_step(th, g, m1, m2, t, lr)
-    model = {"H": H, "lo": lo, "inv_range": inv, "theta": th.astype(np.float32)}
+    model = {"H": H, "lo": lo, "inv_range": inv, "theta": best.astype(np.float32)}
     if return_history:
         return model, hist
     return model

@@ -19,13 +19,12 @@ hipError_t launch_classify(const uint32_t* d_cnt, int64_t NB, int64_t big_max, i
                            uint64_t* d_moff, int32_t* d_seglist, int32_t* d_bigbucket,
                            uint64_t* d_counters, hipStream_t st);
 hipError_t launch_big_buckets(const int32_t* d_bigbucket, int64_t big_count, const int32_t* d_bigmap,
-                              const uint64_t* d_region_key, const uint64_t* d_region_meta,
+                              const RegionEntry* d_region,
                               const SpillEntry* d_spill, int64_t spill_count, uint32_t* d_big_hist,
                               uint64_t* d_G, uint64_t* d_counters, int eps, hipStream_t st);
 hipError_t launch_bucket_polish(const uint32_t* d_cnt, const uint64_t* d_moff, int64_t NB,
-                                const uint64_t* d_region_key, const uint64_t* d_region_meta, int eps,
-                                void* d_M, bool M_is_bits, bool is_f64, uint64_t* d_segmin,
-                                uint64_t* d_segmax, uint64_t* d_counters, hipStream_t st);
+                                const RegionEntry* d_region, int eps, void* d_M, bool M_is_bits, bool is_f64,
+                                uint64_t* d_segmin, uint64_t* d_segmax, uint64_t* d_counters, hipStream_t st);
 hipError_t launch_boundary_plan(const void* d_M, bool M_is_bits, bool is_f64, const uint64_t* d_moff,
                                 const uint32_t* d_cnt, const int32_t* d_seglist, int64_t K,
                                 const uint64_t* d_segmin, const uint64_t* d_segmax, void* d_zones,
@@ -40,13 +39,15 @@ hipError_t launch_sample(const void* d_in, int64_t n, bool is_f64, uint64_t seed
 hipError_t launch_make_xy(const uint64_t* d_sorted, int64_t k, bool is_f64, double lo, double inv, double* d_x,
                           float* d_y, hipStream_t st);
 hipError_t launch_init(float* d_theta, int H, int init, uint64_t seed, const double* d_x, int64_t k,
-                       hipStream_t st);
+                       int64_t* d_knots, hipStream_t st);
 hipError_t launch_batch(const double* d_x, const float* d_y, int64_t k, uint64_t seed, int64_t step, int64_t B,
                         double* d_bx, float* d_by, hipStream_t st);
 size_t mlp_backward_ws_floats(int H, int64_t B);
 size_t loss_ws_floats();
 hipError_t launch_loss_grad(const float* d_F, const float* d_y, int64_t B, int loss, float delta, float* d_gF,
                             float* d_loss, float* d_partial, hipStream_t st);
+hipError_t launch_keep_best(const float* d_theta, float* d_best, int P, const float* d_loss, float* d_best_loss,
+                            hipStream_t st);
 }  // namespace nns
 
 using namespace nns;
@@ -132,10 +133,10 @@ SortPlan plan_sort(int64_t n, double m) {
     size_t nn = (size_t)(n > 0 ? n : 1);
     p.off_counters = take(kNumCounters * 8);
     p.off_cnt = take((size_t)p.NB * 4);
-    p.off_region_key = take((size_t)p.NB * kBucketCap * 8);
-    p.off_region_meta = take((size_t)p.NB * kBucketCap * 8);
+    p.off_region = take((size_t)p.NB * kBucketCap * sizeof(RegionEntry));
     p.off_spill = take(nn * sizeof(SpillEntry));
-    p.off_bucket_info = take((size_t)p.NB * (4 + 8 + 4) + (size_t)p.big_max * 4);
+    p.off_bucket_info = take(align256((size_t)p.NB * 4) + align256((size_t)p.NB * 8) +
+                             align256((size_t)p.NB * 4) + (size_t)p.big_max * 4);
     p.off_segminmax = take((size_t)p.NB * 16 + (size_t)p.NB * zone_bytes());
     p.off_G = take(nn * 8);
     p.off_M = take(nn * 8);
@@ -152,7 +153,7 @@ SortPlan plan_sort(int64_t n, double m) {
 namespace {
 
 struct Events {
-    hipEvent_t e[7] = {};
+    hipEvent_t e[8] = {};
     bool on = false;
     hipStream_t st = nullptr;
     explicit Events(bool enable, hipStream_t s) : on(enable), st(s) {
@@ -228,8 +229,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     char* ws = (char*)d_ws;
     uint64_t* counters = (uint64_t*)(ws + P.off_counters);
     uint32_t* cnt = (uint32_t*)(ws + P.off_cnt);
-    uint64_t* rkey = (uint64_t*)(ws + P.off_region_key);
-    uint64_t* rmeta = (uint64_t*)(ws + P.off_region_meta);
+    RegionEntry* region = (RegionEntry*)(ws + P.off_region);
     SpillEntry* spill = (SpillEntry*)(ws + P.off_spill);
     int32_t* bigmap = (int32_t*)(ws + P.off_bucket_info);
     uint64_t* moff = (uint64_t*)(ws + P.off_bucket_info + align256((size_t)P.NB * 4));
@@ -267,10 +267,10 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     ia.given_slots = given_slots;
     ia.scatter = 1;
     ia.cnt = cnt;
-    ia.region_key = rkey;
-    ia.region_meta = rmeta;
+    ia.region = region;
     ia.spill = spill;
     ia.counters = (unsigned long long*)counters;
+    ev.mark(7);
     NNS_HIP(launch_infer(ia, HP, prm->form, prm->bf16_terms, st));
     ev.mark(1);
     NNS_HIP(launch_classify(cnt, P.NB, P.big_max, bigmap, moff, seglist, bigbucket, counters, st));
@@ -279,26 +279,29 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     NNS_HIP(hipStreamSynchronize(st));
     if (c[kCntBadSlot]) return NNSORT_EINVAL;
     const int64_t big_count = (int64_t)c[kCntBigBuckets];
-    const int64_t G_size = (int64_t)(c[kCntBigKeys] + c[kCntUnmapped]);
+    // G: the region entries of dense ranges plus every spilled key (overflow
+    // of dense ranges and keys without a slot)
+    const int64_t G_size = (int64_t)(c[kCntBigKeys] + c[kCntSpill]);
     const int64_t spill_count = (int64_t)c[kCntSpill];
     if (big_count > P.big_max) return NNSORT_EINTERNAL;
 
     // ---- slot ranges too dense for LDS, and keys without a slot: to G ----
     if (G_size > 0)
-        NNS_HIP(launch_big_buckets(bigbucket, big_count, bigmap, rkey, rmeta, spill, spill_count, big_hist, G,
+        NNS_HIP(launch_big_buckets(bigbucket, big_count, bigmap, region, spill, spill_count, big_hist, G,
                                    counters, eps, st));
     ev.mark(2);
     // ---- rounds + polish of each slot range in LDS ----
     const bool M_is_bits = G_size == 0;
     void* M = M_is_bits ? d_out : (void*)Mbuf;
     const int64_t M_len = n - G_size;
-    NNS_HIP(launch_bucket_polish(cnt, moff, P.NB, rkey, rmeta, eps, M, M_is_bits, is_f64, segmin, segmax,
+    NNS_HIP(launch_bucket_polish(cnt, moff, P.NB, region, eps, M, M_is_bits, is_f64, segmin, segmax,
                                  counters, st));
     const int64_t K = (int64_t)c[kCntSmallBuckets];
     NNS_HIP(launch_boundary_plan(M, M_is_bits, is_f64, moff, cnt, seglist, K, segmin, segmax, zones, counters,
                                  st));
     NNS_HIP(hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, st));
     NNS_HIP(hipStreamSynchronize(st));
+    if ((int64_t)c[kCntGlobal] != G_size) return NNSORT_EINTERNAL;  // every dense/spilled key reached G
     if (c[kCntFallback]) {
         const int mode = M_is_bits ? (is_f64 ? 1 : 2) : 0;
         if (P.radix_bytes < radix_ws_bytes(M_len)) return NNSORT_EINTERNAL;
@@ -333,11 +336,11 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     S.residue = S.collided[t - 1];
     S.unmapped = unm;
     S.big_buckets = big_count;
-    S.big_bucket_keys = (int64_t)c[kCntBigKeys];
+    S.big_bucket_keys = (int64_t)(c[kCntBigKeys] + c[kCntSpill] - c[kCntUnmapped]);
     S.boundary_keys = (int64_t)c[kCntBoundary];
     S.fallback = c[kCntFallback] ? 1 : 0;
     if (stats && prm->stats_level >= 2 && model) {
-        double* Fbuf = (double*)rkey;  // region storage is free now
+        double* Fbuf = (double*)region;  // region storage is free now
         InferArgs pa = ia;
         pa.in = (const uint64_t*)d_out;
         pa.given_slots = nullptr;
@@ -357,7 +360,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     ev.mark(6);
     if (ev.on) {
         NNS_HIP(hipEventSynchronize(ev.e[6]));
-        S.t_infer_ms = ev.ms(0, 1);
+        S.t_infer_ms = ev.ms(7, 1);  // the map kernel alone
         S.t_place_ms = ev.ms(1, 2);
         S.t_polish_ms = ev.ms(2, 3);
         S.t_residue_ms = ev.ms(3, 4);
@@ -372,7 +375,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
 struct FitPlan {
     int64_t k, B;
     int H;
-    size_t off_sample, off_count, off_x, off_y, off_bx, off_by, off_F, off_gF, off_saved, off_bws, off_theta,
+    size_t off_best, off_knots, off_sample, off_count, off_x, off_y, off_bx, off_by, off_F, off_gF, off_saved, off_bws, off_theta,
         off_grad, off_m1, off_m2, off_loss, off_lpart, off_radix, total;
 };
 
@@ -409,6 +412,8 @@ FitPlan plan_fit(int64_t n, const nnsort_fit_params* fp) {
     p.off_m2 = take((size_t)P * 4);
     p.off_loss = take(64);
     p.off_lpart = take(loss_ws_floats() * 4);
+    p.off_knots = take((NNSORT_MAX_HIDDEN + 1) * 8);
+    p.off_best = take((size_t)(P + 64) * 4);
     p.off_radix = take(radix_ws_bytes(p.k));
     p.total = o;
     return p;
@@ -420,7 +425,7 @@ bool valid_fit_params(const nnsort_fit_params* f) {
     if (!(f->sample_frac > 0.0) || f->sample_frac > 1.0e6) return false;
     if (f->batch < 1 || f->steps < 0) return false;
     if (f->loss != 0 && f->loss != 1) return false;
-    if (f->init != 0 && f->init != 1) return false;
+    if (f->init < 0 || f->init > 2) return false;
     if (!std::isfinite(f->lr)) return false;
     return true;
 }
@@ -450,9 +455,12 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
     float* m2 = (float*)(ws + P.off_m2);
     float* dloss = (float*)(ws + P.off_loss);
     float* lpart = (float*)(ws + P.off_lpart);
+    int64_t* knots = (int64_t*)(ws + P.off_knots);
     void* rws = ws + P.off_radix;
     const int H = fp->hidden;
     const int Pn = H * H + 4 * H + 1;
+    float* best = (float*)(ws + P.off_best);
+    float* best_loss = best + Pn;
 
     NNS_HIP(fill_u64(count, 1, 0, st));
     NNS_HIP(launch_sample(d_keys, n, is_f64, fp->seed, P.k, sample, count, st));
@@ -481,20 +489,25 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
     double lo = value_of(ends[0]), hi = value_of(ends[1]);
     double inv = hi > lo ? 1.0 / (hi - lo) : 0.0;
     NNS_HIP(launch_make_xy(sample, (int64_t)k2, is_f64, lo, inv, x, y, st));
-    NNS_HIP(launch_init(theta, H, fp->init, fp->seed, x, (int64_t)k2, st));
+    NNS_HIP(launch_init(theta, H, fp->init, fp->seed, x, (int64_t)k2, knots, st));
     NNS_HIP(hipMemsetAsync(m1, 0, (size_t)Pn * 4, st));
     NNS_HIP(hipMemsetAsync(m2, 0, (size_t)Pn * 4, st));
+    NNS_HIP(hipMemcpyAsync(best, theta, (size_t)Pn * 4, hipMemcpyDeviceToDevice, st));
+    NNS_HIP(fill_u32((uint32_t*)best_loss, 1, 0x7F800000u, st));  // +inf
     for (int t = 1; t <= fp->steps; ++t) {
         NNS_HIP(launch_batch(x, y, (int64_t)k2, fp->seed, t, P.B, bx, by, st));
         NNS_HIP(launch_mlp_forward(H, theta, bx, P.B, F, saved, st));
         NNS_HIP(launch_loss_grad(F, by, P.B, fp->loss, fp->huber_delta, gF, dloss, lpart, st));
+        NNS_HIP(launch_keep_best(theta, best, Pn, dloss, best_loss, st));
         if (loss_history && t - 1 < history_len)
             NNS_HIP(hipMemcpyAsync(loss_history + (t - 1), dloss, 4, hipMemcpyDeviceToHost, st));
         NNS_HIP(launch_mlp_backward(H, theta, bx, P.B, saved, gF, grad, bws, st));
         NNS_HIP(launch_adam(theta, grad, m1, m2, Pn, t, fp->lr, 0.9f, 0.999f, 1e-8f, st));
     }
     std::vector<float> th((size_t)Pn);
-    NNS_HIP(hipMemcpyAsync(th.data(), theta, (size_t)Pn * 4, hipMemcpyDeviceToHost, st));
+    // the parameters with the lowest batch loss seen (the initial ones if no
+    // step improved on them)
+    NNS_HIP(hipMemcpyAsync(th.data(), best, (size_t)Pn * 4, hipMemcpyDeviceToHost, st));
     NNS_HIP(hipStreamSynchronize(st));
     M.lo = lo;
     M.inv_range = inv;

@@ -7,9 +7,10 @@
 // slot's keys never interact with another slot's: the rounds of the keys of
 // one slot range can run on their own.  k_bucket_polish runs all rounds of one
 // range in LDS (first arrival = smallest input index, decided with LDS
-// atomic-min), compacts each o_r in slot order followed by the range's part of
-// the last conflict array, and then sorts that sequence in LDS (per-thread
-// sorting network, then merge-path merges) -- the polish of the range.
+// atomic-min), lays the arrays o_r out slot by slot (o_1, o_2, ... then the
+// range's part of the last conflict array), and polishes that nearly sorted
+// sequence in LDS: sorting networks on 8-key tiles, then merges of
+// neighbouring tiles only while a tile boundary is out of order.
 // Adjacent ranges can overlap in key order where f is not monotone or jitters;
 // k_boundary_* repairs each such overlap with an in-place merge, and reports a
 // fallback when the overlap is not confined to neighbours.
@@ -75,7 +76,7 @@ __global__ void __launch_bounds__(1024) k_classify(const uint32_t* __restrict__ 
         uint32_t c = cnt[b];
         if (c > kBucketCap) {
             ++big;
-            bigkeys += c;
+            bigkeys += kBucketCap;
         } else {
             small += c;
             seg += c ? 1 : 0;
@@ -145,8 +146,7 @@ __device__ __forceinline__ void g_append(bool want, uint64_t okey, uint64_t* G,
 
 // Region entries of big buckets: thread per (big id, entry).
 __global__ void __launch_bounds__(256) k_big_region(const int32_t* __restrict__ bigbucket, int64_t big_count,
-                                                    const uint64_t* __restrict__ rkey,
-                                                    const uint64_t* __restrict__ rmeta, uint32_t* hist,
+                                                    const RegionEntry* __restrict__ region, uint32_t* hist,
                                                     uint64_t* G, unsigned long long* counters) {
     int64_t total = big_count * (int64_t)kBucketCap;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -157,32 +157,53 @@ __global__ void __launch_bounds__(256) k_big_region(const int32_t* __restrict__ 
         if (act) {
             int64_t id = i / kBucketCap;
             int64_t e = (int64_t)bigbucket[id] * kBucketCap + (i % kBucketCap);
-            okey = rkey[e];
-            uint32_t lsl = (uint32_t)(rmeta[e] & (kBucketSlots - 1));
+            RegionEntry r = region[e];
+            okey = r.okey;
+            uint32_t lsl = (uint32_t)(r.meta & (kBucketSlots - 1));
             atomicAdd(&hist[id * kBucketSlots + lsl], 1u);
         }
         g_append(act, okey, G, &counters[kCntGlobal]);
     }
 }
 
-// Spill entries: overflow of big buckets, and keys without a slot.
+// Spill entries: overflow of big buckets, and keys without a slot.  Spilled
+// keys crowd into few slots, so a wave adds its lanes' slot counts with one
+// atomic per distinct slot (up to 8 distinct slots, then one per lane).
 __global__ void __launch_bounds__(256) k_big_spill(const SpillEntry* __restrict__ spill, int64_t count,
                                                    const int32_t* __restrict__ bigmap, uint32_t* hist,
                                                    uint64_t* G, unsigned long long* counters) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const unsigned lane = __lane_id();
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < count; base += stride) {
         int64_t i = base + threadIdx.x;
         bool act = i < count;
         uint64_t okey = 0;
+        bool pending = false;
+        uint32_t hidx = 0;
         if (act) {
             SpillEntry e = spill[i];
             okey = e.okey;
             if (e.slot != kUnmapped) {
                 int32_t id = bigmap[e.slot >> kLogBucketSlots];
-                if (id >= 0) atomicAdd(&hist[(int64_t)id * kBucketSlots + (e.slot & (kBucketSlots - 1))], 1u);
-                else atomicAdd(&counters[kCntBadSlot], 1ull);  // cannot happen: spill implies big
+                if (id >= 0) {
+                    pending = true;
+                    hidx = (uint32_t)id * kBucketSlots + (e.slot & (kBucketSlots - 1));
+                } else {
+                    atomicAdd(&counters[kCntBadSlot], 1ull);  // cannot happen: spill implies big
+                }
             }
         }
+        for (int it = 0; it < 8; ++it) {
+            unsigned long long mask = __ballot(pending);
+            if (!mask) break;
+            int leader = __ffsll((long long)mask) - 1;
+            uint32_t target = __shfl(hidx, leader);
+            bool same = pending && hidx == target;
+            unsigned long long sm_ = __ballot(same);
+            if (lane == (unsigned)leader) atomicAdd(&hist[target], (uint32_t)__popcll(sm_));
+            if (same) pending = false;
+        }
+        if (pending) atomicAdd(&hist[hidx], 1u);
         g_append(act, okey, G, &counters[kCntGlobal]);
     }
 }
@@ -218,7 +239,7 @@ __global__ void __launch_bounds__(256) k_big_counts(const uint32_t* __restrict__
 }
 
 hipError_t launch_big_buckets(const int32_t* d_bigbucket, int64_t big_count, const int32_t* d_bigmap,
-                              const uint64_t* d_region_key, const uint64_t* d_region_meta,
+                              const RegionEntry* d_region,
                               const SpillEntry* d_spill, int64_t spill_count, uint32_t* d_big_hist,
                               uint64_t* d_G, uint64_t* d_counters, int eps, hipStream_t st) {
     unsigned long long* c = (unsigned long long*)d_counters;
@@ -226,7 +247,7 @@ hipError_t launch_big_buckets(const int32_t* d_bigbucket, int64_t big_count, con
     if (e != hipSuccess) return e;
     if (big_count > 0) {
         hipLaunchKernelGGL(k_big_region, dim3(blocks_for(big_count * kBucketCap, 256, 16384)), dim3(256), 0,
-                           st, d_bigbucket, big_count, d_region_key, d_region_meta, d_big_hist, d_G, c);
+                           st, d_bigbucket, big_count, d_region, d_big_hist, d_G, c);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (spill_count > 0) {
@@ -245,7 +266,9 @@ hipError_t launch_big_buckets(const int32_t* d_bigbucket, int64_t big_count, con
 // ---------------------------------------------------------------------------
 // per-bucket rounds + polish in LDS
 // ---------------------------------------------------------------------------
-constexpr int kItems = kItemsPerThread;  // keys per thread (16)
+constexpr int kItems = kItemsPerThread;  // region entries per thread (16)
+constexpr int kTile = 8;                 // keys per polish tile
+constexpr int kMaxTileRounds = 8;        // odd-even tile rounds before the bitonic fallback
 
 __device__ __forceinline__ void cswap(uint64_t& a, uint64_t& b) {
     uint64_t lo = a < b ? a : b;
@@ -254,22 +277,30 @@ __device__ __forceinline__ void cswap(uint64_t& a, uint64_t& b) {
     b = hi;
 }
 
-// Bitonic sorting network over 16 registers (ascending).
-__device__ __forceinline__ void sort16(uint64_t (&v)[kItems]) {
+// Batcher's odd-even merge sort network for 8 keys (19 comparators).
+__device__ __forceinline__ void sort8(uint64_t (&v)[8]) {
+    cswap(v[0], v[1]); cswap(v[2], v[3]); cswap(v[4], v[5]); cswap(v[6], v[7]);
+    cswap(v[0], v[2]); cswap(v[1], v[3]); cswap(v[4], v[6]); cswap(v[5], v[7]);
+    cswap(v[1], v[2]); cswap(v[5], v[6]);
+    cswap(v[0], v[4]); cswap(v[1], v[5]); cswap(v[2], v[6]); cswap(v[3], v[7]);
+    cswap(v[2], v[4]); cswap(v[3], v[5]);
+    cswap(v[1], v[2]); cswap(v[3], v[4]); cswap(v[5], v[6]);
+}
+
+// Merge two ascending 8-key runs: reverse the second (a bitonic sequence of
+// 16) and apply the half-cleaners at distances 8, 4, 2, 1.
+__device__ __forceinline__ void merge16(uint64_t (&v)[16]) {
 #pragma unroll
-    for (int k = 2; k <= kItems; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-#pragma unroll
-            for (int i = 0; i < kItems; ++i) {
-                int l = i ^ j;
-                if (l > i) {
-                    if ((i & k) == 0) cswap(v[i], v[l]);
-                    else cswap(v[l], v[i]);
-                }
-            }
-        }
+    for (int i = 0; i < 4; ++i) {
+        uint64_t t = v[8 + i];
+        v[8 + i] = v[15 - i];
+        v[15 - i] = t;
     }
+#pragma unroll
+    for (int d = 8; d > 0; d >>= 1)
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if ((i & d) == 0) cswap(v[i], v[i | d]);
 }
 
 // Merge-path split: number of elements taken from a (length na) among the
@@ -279,7 +310,6 @@ __device__ __forceinline__ int merge_split(const uint64_t* a, int na, const uint
     int hi = diag < na ? diag : na;
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
-        // take a[mid] before b[diag - 1 - mid] iff a[mid] <= b[diag - 1 - mid]
         if (a[mid] <= b[diag - 1 - mid]) lo = mid + 1;
         else hi = mid;
     }
@@ -287,25 +317,36 @@ __device__ __forceinline__ int merge_split(const uint64_t* a, int na, const uint
 }
 
 struct BucketSmem {
-    uint64_t bufA[kBucketCap];
-    uint64_t bufB[kBucketCap];
-    uint32_t owner[kBucketSlots];
-    uint32_t bitmap[NNSORT_MAX_EPS][kBucketSlots / 32];
-    uint32_t woff[NNSORT_MAX_EPS][kBucketSlots / 32];
-    uint32_t placed[NNSORT_MAX_EPS + 1];
-    uint32_t resid_cursor;
+    uint64_t keys[kBucketCap];
+    uint32_t owner[kBucketSlots];  // rounds: first arrival per slot; then residue cursors
+    uint32_t off[kBucketSlots];    // keys per slot, then their exclusive prefix
+    uint32_t wsum[kBucketThreads];
+    unsigned long long red[2 * NNSORT_MAX_EPS];
+    int flag;
 };
 
+// One workgroup per slot range.  Steps, all in LDS:
+//  1. slot multiplicities k_s and the rounds: in round r each slot keeps the
+//     unplaced key with the smallest input index (its r-th arrival);
+//  2. round counts from k_s: round r stores #{s : k_s >= r} keys and leaves
+//     sum_s max(0, k_s - r) in the conflict array;
+//  3. compaction, slot-major: slot s's keys at offset(s), ordered o_1, o_2, ...,
+//     o_eps, then the slot's share of the last conflict array -- the arrays
+//     o_r interleaved slot by slot, which a near-monotone f leaves nearly
+//     sorted;
+//  4. polish: 8-key tiles sorted by a network, then odd-even merges of
+//     neighbouring tiles while any tile boundary is out of order (keys only
+//     move as far as f misplaced them); a bitonic sort if that does not settle.
 __global__ void __launch_bounds__(kBucketThreads) k_bucket_polish(
     const uint32_t* __restrict__ cnt_arr, const uint64_t* __restrict__ moff,
-    const uint64_t* __restrict__ rkey, const uint64_t* __restrict__ rmeta, int eps, void* M,
-    int M_is_bits, int is_f64, uint64_t* segmin, uint64_t* segmax, unsigned long long* counters) {
+    const RegionEntry* __restrict__ region, int eps, void* M, int M_is_bits, int is_f64, uint64_t* segmin,
+    uint64_t* segmax, unsigned long long* counters) {
     __shared__ BucketSmem sm;
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
     const uint32_t cnt = cnt_arr[b];
-    if (cnt == 0 || cnt > kBucketCap) return;  // empty, or handled by the big-bucket path
-    const size_t rbase = (size_t)b * kBucketCap;
+    if (cnt == 0 || cnt > kBucketCap) return;  // empty, or handled by the dense-range path
+    const RegionEntry* reg = region + (size_t)b * kBucketCap;
 
     uint64_t key[kItems];
     uint32_t idx[kItems];
@@ -315,155 +356,169 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket_polish(
     for (int k = 0; k < kItems; ++k) {
         uint32_t e = tid + k * kBucketThreads;
         rnd[k] = 0;
+        key[k] = 0;
+        idx[k] = 0;
+        lsl[k] = 0;
         if (e < cnt) {
-            key[k] = rkey[rbase + e];
-            uint64_t m = rmeta[rbase + e];
-            idx[k] = (uint32_t)(m >> 32);
-            lsl[k] = (uint32_t)(m & (kBucketSlots - 1));
-        } else {
-            key[k] = 0;
-            idx[k] = 0;
-            lsl[k] = 0;
+            RegionEntry r = reg[e];
+            key[k] = r.okey;
+            idx[k] = (uint32_t)(r.meta >> 32);
+            lsl[k] = (uint32_t)(r.meta & (kBucketSlots - 1));
         }
     }
-    if (tid <= NNSORT_MAX_EPS) sm.placed[tid] = 0;
-    if (tid == 0) sm.resid_cursor = 0;
-    for (int i = tid; i < NNSORT_MAX_EPS * (int)(kBucketSlots / 32); i += kBucketThreads)
-        (&sm.bitmap[0][0])[i] = 0;
+    for (int i = tid; i < (int)kBucketSlots; i += kBucketThreads) sm.off[i] = 0;
+    if (tid < 2 * NNSORT_MAX_EPS) sm.red[tid] = 0;
+    if (tid == 0) sm.flag = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kItems; ++k)
+        if (tid + k * kBucketThreads < cnt) atomicAdd(&sm.off[lsl[k]], 1u);
 
-    // ---- rounds: first arrival (smallest input index) per slot ----
+    // ---- 1. rounds ----
     for (int r = 1; r <= eps; ++r) {
         for (int i = tid; i < (int)kBucketSlots; i += kBucketThreads) sm.owner[i] = kUnmapped;
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            uint32_t e = tid + k * kBucketThreads;
-            if (e < cnt && rnd[k] == 0) atomicMin(&sm.owner[lsl[k]], idx[k]);
-        }
+        for (int k = 0; k < kItems; ++k)
+            if (tid + k * kBucketThreads < cnt && rnd[k] == 0) atomicMin(&sm.owner[lsl[k]], idx[k]);
         __syncthreads();
-        uint32_t mine = 0;
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            uint32_t e = tid + k * kBucketThreads;
-            if (e < cnt && rnd[k] == 0 && sm.owner[lsl[k]] == idx[k]) {
-                rnd[k] = (uint8_t)r;
-                atomicOr(&sm.bitmap[r - 1][lsl[k] >> 5], 1u << (lsl[k] & 31));
-                ++mine;
-            }
-        }
-        if (mine) atomicAdd(&sm.placed[r - 1], mine);
+        for (int k = 0; k < kItems; ++k)
+            if (tid + k * kBucketThreads < cnt && rnd[k] == 0 && sm.owner[lsl[k]] == idx[k]) rnd[k] = (uint8_t)r;
         __syncthreads();
     }
 
-    // ---- counts: |c_r| of this range and the stored keys per round ----
-    if (tid == 0) {
-        uint32_t left = cnt;
-        for (int r = 0; r < eps; ++r) {
-            left -= sm.placed[r];
-            atomicAdd(&counters[kCntCollided + r], (unsigned long long)left);
-            atomicAdd(&counters[kCntPlaced + r], (unsigned long long)sm.placed[r]);
-        }
-    }
-    // exclusive popcount prefix of each round's occupancy bitmap (wave 0)
-    if (tid < 64) {
-        for (int r = 0; r < eps; ++r) {
-            uint32_t c = __popc(sm.bitmap[r][tid]);
-            uint32_t incl = c;
-            for (int off = 1; off < 64; off <<= 1) {
-                uint32_t y = __shfl_up(incl, off);
-                if (tid >= off) incl += y;
+    // ---- 2. round counts from slot multiplicities; 3a. slot offsets ----
+    constexpr int kSlotsPer = kBucketSlots / kBucketThreads;  // 8
+    uint32_t ks[kSlotsPer], run = 0;
+    {
+        unsigned long long pl[NNSORT_MAX_EPS] = {0}, co[NNSORT_MAX_EPS] = {0};
+#pragma unroll
+        for (int q = 0; q < kSlotsPer; ++q) {
+            ks[q] = sm.off[tid * kSlotsPer + q];
+            run += ks[q];
+            for (int r = 1; r <= eps; ++r) {
+                pl[r - 1] += ks[q] >= (uint32_t)r ? 1u : 0u;
+                co[r - 1] += ks[q] > (uint32_t)r ? ks[q] - r : 0u;
             }
-            sm.woff[r][tid] = incl - c;
+        }
+        for (int r = 0; r < eps; ++r) {
+            if (pl[r]) atomicAdd(&sm.red[r], pl[r]);
+            if (co[r]) atomicAdd(&sm.red[NNSORT_MAX_EPS + r], co[r]);
+        }
+        sm.wsum[tid] = run;
+    }
+    for (int i = tid; i < (int)kBucketSlots; i += kBucketThreads) sm.owner[i] = 0;  // residue cursors
+    __syncthreads();
+    if (tid < eps) {
+        atomicAdd(&counters[kCntPlaced + tid], sm.red[tid]);
+        atomicAdd(&counters[kCntCollided + tid], sm.red[NNSORT_MAX_EPS + tid]);
+    }
+    // exclusive scan of the 256 per-thread slot totals (Hillis-Steele in place)
+    for (int o = 1; o < kBucketThreads; o <<= 1) {
+        uint32_t y = tid >= o ? sm.wsum[tid - o] : 0;
+        __syncthreads();
+        sm.wsum[tid] += y;
+        __syncthreads();
+    }
+    {
+        uint32_t base = sm.wsum[tid] - run;
+#pragma unroll
+        for (int q = 0; q < kSlotsPer; ++q) {
+            sm.off[tid * kSlotsPer + q] = base;
+            base += ks[q];
         }
     }
     __syncthreads();
 
-    // ---- compaction: o_1 | o_2 | ... | o_eps (each in slot order) | rest ----
-    uint32_t rbase_pos[NNSORT_MAX_EPS + 1];
-    {
-        uint32_t acc = 0;
-        for (int r = 0; r < eps; ++r) {
-            rbase_pos[r] = acc;
-            acc += sm.placed[r];
-        }
-        rbase_pos[eps] = acc;
-    }
+    // ---- 3b. slot-major compaction ----
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        uint32_t e = tid + k * kBucketThreads;
-        if (e >= cnt) continue;
-        uint32_t pos;
-        if (rnd[k]) {
-            int r = rnd[k] - 1;
-            uint32_t w = lsl[k] >> 5;
-            uint32_t below = sm.bitmap[r][w] & ((1u << (lsl[k] & 31)) - 1u);
-            pos = rbase_pos[r] + sm.woff[r][w] + __popc(below);
-        } else {
-            pos = rbase_pos[eps] + atomicAdd(&sm.resid_cursor, 1u);
-        }
-        sm.bufA[pos] = key[k];
+        if (tid + k * kBucketThreads >= cnt) continue;
+        uint32_t pos = sm.off[lsl[k]];
+        pos += rnd[k] ? (uint32_t)(rnd[k] - 1) : (uint32_t)eps + atomicAdd(&sm.owner[lsl[k]], 1u);
+        sm.keys[pos] = key[k];
     }
+    const int ntiles = (int)((cnt + kTile - 1) / kTile);
+    for (int i = (int)cnt + tid; i < ntiles * kTile; i += kBucketThreads) sm.keys[i] = ~0ull;
     __syncthreads();
 
-    // ---- polish: sort the compacted sequence (runs of 16, then merges) ----
-    int npad = kItems;
-    while (npad < (int)cnt) npad <<= 1;
-    const int nthr = npad / kItems;
-    uint64_t* src = sm.bufA;
-    uint64_t* dst = sm.bufB;
-    if (tid < nthr) {
-        uint64_t v[kItems];
+    // ---- 4. polish ----
+    for (int t = tid; t < ntiles; t += kBucketThreads) {
+        uint64_t v[8];
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            int p = tid * kItems + k;
-            v[k] = p < (int)cnt ? src[p] : ~0ull;
-        }
-        sort16(v);
+        for (int q = 0; q < 8; ++q) v[q] = sm.keys[t * 8 + q];
+        sort8(v);
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) src[tid * kItems + k] = v[k];
+        for (int q = 0; q < 8; ++q) sm.keys[t * 8 + q] = v[q];
     }
     __syncthreads();
-    for (int w = kItems; w < npad; w <<= 1) {
-        if (tid < nthr) {
-            int out0 = tid * kItems;
-            int pair = out0 / (2 * w);
-            int d = out0 - pair * 2 * w;
-            const uint64_t* a = src + pair * 2 * w;
-            const uint64_t* bb = a + w;
-            int ia = merge_split(a, w, bb, w, d);
-            int ib = d - ia;
-            uint64_t* o = dst + out0;
+    bool settled = false;
+    for (int round = 0; round <= kMaxTileRounds; ++round) {
+        int bad = 0;
+        for (int t = tid; t + 1 < ntiles; t += kBucketThreads)
+            bad |= sm.keys[t * 8 + 7] > sm.keys[t * 8 + 8] ? 1 : 0;
+        if (bad) sm.flag = round + 1;
+        __syncthreads();
+        int f = sm.flag;
+        __syncthreads();
+        if (f != round + 1) {
+            settled = true;
+            break;
+        }
+        if (round == kMaxTileRounds) break;
+        const int parity = round & 1;
+        for (int p = tid; 2 * p + parity + 1 < ntiles; p += kBucketThreads) {
+            const int t0 = 2 * p + parity;
+            uint64_t v[16];
 #pragma unroll
-            for (int k = 0; k < kItems; ++k) {
-                bool takeA = ib >= w || (ia < w && a[ia] <= bb[ib]);
-                o[k] = takeA ? a[ia] : bb[ib];
-                ia += takeA ? 1 : 0;
-                ib += takeA ? 0 : 1;
-            }
+            for (int q = 0; q < 16; ++q) v[q] = sm.keys[t0 * 8 + q];
+            merge16(v);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) sm.keys[t0 * 8 + q] = v[q];
         }
         __syncthreads();
-        uint64_t* t = src;
-        src = dst;
-        dst = t;
+    }
+    if (!settled) {
+        // f is far from monotone inside this range: bitonic sort of the range
+        int npad = 8;
+        while (npad < ntiles * 8) npad <<= 1;
+        for (int i = ntiles * 8 + tid; i < npad; i += kBucketThreads) sm.keys[i] = ~0ull;
+        __syncthreads();
+        for (int kk = 2; kk <= npad; kk <<= 1) {
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                for (int i = tid; i < npad; i += kBucketThreads) {
+                    int l = i ^ j;
+                    if (l > i) {
+                        uint64_t a = sm.keys[i], c = sm.keys[l];
+                        bool up = (i & kk) == 0;
+                        if ((a > c) == up) {
+                            sm.keys[i] = c;
+                            sm.keys[l] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
     }
 
     // ---- write the range's sorted keys to its segment of M ----
     const uint64_t off = moff[b];
-    for (uint32_t i = tid; i < cnt; i += kBucketThreads) store_key(M, M_is_bits, is_f64, off + i, src[i]);
+    for (uint32_t i = tid; i < cnt; i += kBucketThreads) store_key(M, M_is_bits, is_f64, off + i, sm.keys[i]);
     if (tid == 0) {
-        segmin[b] = src[0];
-        segmax[b] = src[cnt - 1];
+        segmin[b] = sm.keys[0];
+        segmax[b] = sm.keys[cnt - 1];
     }
 }
 
 hipError_t launch_bucket_polish(const uint32_t* d_cnt, const uint64_t* d_moff, int64_t NB,
-                                const uint64_t* d_region_key, const uint64_t* d_region_meta, int eps,
-                                void* d_M, bool M_is_bits, bool is_f64, uint64_t* d_segmin,
-                                uint64_t* d_segmax, uint64_t* d_counters, hipStream_t st) {
+                                const RegionEntry* d_region, int eps, void* d_M, bool M_is_bits, bool is_f64,
+                                uint64_t* d_segmin, uint64_t* d_segmax, uint64_t* d_counters, hipStream_t st) {
     if (NB <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bucket_polish, dim3((unsigned)NB), dim3(kBucketThreads), 0, st, d_cnt, d_moff,
-                       d_region_key, d_region_meta, eps, d_M, M_is_bits ? 1 : 0, is_f64 ? 1 : 0, d_segmin,
-                       d_segmax, (unsigned long long*)d_counters);
+    hipLaunchKernelGGL(k_bucket_polish, dim3((unsigned)NB), dim3(kBucketThreads), 0, st, d_cnt, d_moff, d_region,
+                       eps, d_M, M_is_bits ? 1 : 0, is_f64 ? 1 : 0, d_segmin, d_segmax,
+                       (unsigned long long*)d_counters);
     return hipGetLastError();
 }
 

@@ -78,35 +78,158 @@ __global__ void __launch_bounds__(256) k_make_xy(const uint64_t* __restrict__ so
     y[j] = (float)(((double)j + 0.5) / (double)k);
 }
 
+// ---- knots of the piecewise-linear CDF interpolant ----
+// Greedy maximum-deviation splitting over the sorted sample x[0..k) with ranks
+// y_j = (j + 0.5)/k: split the piece whose points lie farthest (in rank) from
+// the chord between its ends, at the farthest point, until H pieces.  Ties:
+// larger deviation first, then the smaller start / smaller point index.  A
+// piece with < 3 points, zero width, or no point more than 1/k off its chord
+// is final.  One workgroup; every piece scan is a block-wide arg-max.
+constexpr int kKnotThreads = 1024;
+
+__device__ __forceinline__ double rank_of(int64_t j, int64_t k) { return ((double)j + 0.5) / (double)k; }
+
+// Block-wide: (max deviation, first index) over points a+1 .. b-1 of piece (a, b).
+__device__ void piece_dev(const double* __restrict__ x, int64_t k, int64_t a, int64_t b, double* s_d,
+                          int64_t* s_j, double& out_d, int64_t& out_j) {
+    double best = -1.0;
+    int64_t bj = -1;
+    const double xa = x[a], xb = x[b];
+    if (b - a >= 2 && xb != xa) {
+        const double ya = rank_of(a, k), yb = rank_of(b, k);
+        for (int64_t j = a + 1 + threadIdx.x; j < b; j += kKnotThreads) {
+            double lin = ya + ((yb - ya) * (x[j] - xa)) / (xb - xa);
+            double d = fabs(rank_of(j, k) - lin);
+            if (d > best) {
+                best = d;
+                bj = j;
+            }
+        }
+    }
+    s_d[threadIdx.x] = best;
+    s_j[threadIdx.x] = bj;
+    __syncthreads();
+    for (int off = kKnotThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < (unsigned)off) {
+            double d2 = s_d[threadIdx.x + off];
+            int64_t j2 = s_j[threadIdx.x + off];
+            double d1 = s_d[threadIdx.x];
+            int64_t j1 = s_j[threadIdx.x];
+            if (d2 > d1 || (d2 == d1 && j2 >= 0 && (j1 < 0 || j2 < j1))) {
+                s_d[threadIdx.x] = d2;
+                s_j[threadIdx.x] = j2;
+            }
+        }
+        __syncthreads();
+    }
+    out_d = s_d[0];
+    out_j = s_j[0];
+    if (!(out_d > 1.0 / (double)k)) {  // within one rank step of linear: final
+        out_d = 0.0;
+        out_j = -1;
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(kKnotThreads) k_greedy_knots(const double* __restrict__ x, int64_t k, int H,
+                                                               int64_t* knots) {
+    __shared__ double s_d[kKnotThreads];
+    __shared__ int64_t s_j[kKnotThreads];
+    __shared__ int64_t pa[64], pb[64], pj[64];
+    __shared__ double pd[64];
+    __shared__ int np_, best_;
+    double d;
+    int64_t j;
+    piece_dev(x, k, 0, k - 1, s_d, s_j, d, j);
+    if (threadIdx.x == 0) {
+        pa[0] = 0;
+        pb[0] = k - 1;
+        pd[0] = d;
+        pj[0] = j;
+        np_ = 1;
+    }
+    __syncthreads();
+    while (np_ < H) {
+        if (threadIdx.x == 0) {
+            int best = -1;
+            for (int i = 0; i < np_; ++i) {
+                if (pj[i] < 0 || !(pd[i] > 0.0)) continue;
+                if (best < 0 || pd[i] > pd[best] || (pd[i] == pd[best] && pa[i] < pa[best])) best = i;
+            }
+            best_ = best;
+        }
+        __syncthreads();
+        const int best = best_;
+        if (best < 0) break;
+        const int64_t a = pa[best], b = pb[best], sj = pj[best];
+        double d1, d2;
+        int64_t j1, j2;
+        piece_dev(x, k, a, sj, s_d, s_j, d1, j1);
+        piece_dev(x, k, sj, b, s_d, s_j, d2, j2);
+        if (threadIdx.x == 0) {
+            pb[best] = sj;
+            pd[best] = d1;
+            pj[best] = j1;
+            int n = np_;
+            pa[n] = sj;
+            pb[n] = b;
+            pd[n] = d2;
+            pj[n] = j2;
+            np_ = n + 1;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        // starts in ascending order, then the last sample index
+        int n = np_;
+        int64_t st[64];
+        for (int i = 0; i < n; ++i) st[i] = pa[i];
+        for (int i = 1; i < n; ++i) {
+            int64_t v = st[i];
+            int q = i - 1;
+            while (q >= 0 && st[q] > v) {
+                st[q + 1] = st[q];
+                --q;
+            }
+            st[q + 1] = v;
+        }
+        for (int i = 0; i <= H; ++i) knots[i] = i < n ? st[i] : k - 1;
+    }
+}
+
+__global__ void k_quantile_knots(int64_t k, int H, int64_t* knots) {
+    int i = threadIdx.x;
+    if (i <= H) knots[i] = (int64_t)i * (k - 1) / H;
+}
+
 // Initial weights (packed theta of width H).
-__global__ void k_init(float* theta, int H, int init, uint64_t seed, const double* __restrict__ x, int64_t k) {
+// init 1 / 2: ramps through the knots (q_i, F_i) of the sample CDF:
+//   u_i = relu(s_i (x - q_i)), s_i = 1/max(q_{i+1} - q_i, 2^-40);
+//   v_i = relu(1 - u_i);  F = F_H - sum_i (F_{i+1} - F_i) v_i.
+// init 0: uniform(+-1/sqrt(fan_in)).
+__global__ void k_init(float* theta, int H, int init, uint64_t seed, const double* __restrict__ x, int64_t k,
+                       const int64_t* __restrict__ knots) {
     int P = H * H + 4 * H + 1;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
         double v = 0.0;
-        if (init == 1) {
-            // quantile ramps: u_j = relu(s_j (x - q_j)), v_i = relu(1 - u_i), F = 1 - mean v
-            if (p < H) {
-                int j = p;
-                double q0 = x[(int64_t)j * (k - 1) / H], q1 = x[(int64_t)(j + 1) * (k - 1) / H];
-                double w = q1 - q0;
-                w = w > 0x1p-40 ? w : 0x1p-40;
-                v = 1.0 / w;
-            } else if (p < 2 * H) {
-                int j = p - H;
-                double q0 = x[(int64_t)j * (k - 1) / H], q1 = x[(int64_t)(j + 1) * (k - 1) / H];
+        if (init == 1 || init == 2) {
+            if (p < 2 * H) {
+                int i = p < H ? p : p - H;
+                double q0 = x[knots[i]], q1 = x[knots[i + 1]];
                 double w = q1 - q0;
                 w = w > 0x1p-40 ? w : 0x1p-40;
                 double s = 1.0 / w;
-                v = -s * q0;
+                v = p < H ? s : -s * q0;
             } else if (p < 2 * H + H * H) {
                 int e = p - 2 * H;
                 v = (e / H == e % H) ? -1.0 : 0.0;
             } else if (p < 3 * H + H * H) {
                 v = 1.0;
             } else if (p < 4 * H + H * H) {
-                v = -1.0 / H;
+                int i = p - 3 * H - H * H;
+                v = -(rank_of(knots[i + 1], k) - rank_of(knots[i], k));
             } else {
-                v = 1.0;
+                v = rank_of(knots[H], k);
             }
         } else {
             double bound = p < 2 * H ? 1.0 : 1.0 / sqrt((double)H);
@@ -336,6 +459,28 @@ __global__ void __launch_bounds__(256) k_sum_rows(const float* __restrict__ part
     out[p] = s;
 }
 
+// Keep the parameters with the lowest batch loss seen so far (the loss of a
+// step is measured before that step's update).
+__global__ void __launch_bounds__(256) k_keep_best(const float* __restrict__ th, float* best, int P,
+                                                   const float* __restrict__ loss, float* best_loss) {
+    __shared__ int better;
+    if (threadIdx.x == 0) {
+        float l = loss[0];
+        better = l < best_loss[0] ? 1 : 0;
+    }
+    __syncthreads();
+    if (!better) return;
+    for (int p = threadIdx.x; p < P; p += blockDim.x) best[p] = th[p];
+    __syncthreads();
+    if (threadIdx.x == 0) best_loss[0] = loss[0];
+}
+
+hipError_t launch_keep_best(const float* d_theta, float* d_best, int P, const float* d_loss, float* d_best_loss,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_keep_best, dim3(1), dim3(256), 0, st, d_theta, d_best, P, d_loss, d_best_loss);
+    return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(256) k_adam(float* th, const float* __restrict__ g, float* m1, float* m2,
                                               int64_t count, float b1, float b2, float c1, float c2, float lr,
                                               float eps) {
@@ -370,9 +515,13 @@ hipError_t launch_make_xy(const uint64_t* d_sorted, int64_t k, bool is_f64, doub
 }
 
 hipError_t launch_init(float* d_theta, int H, int init, uint64_t seed, const double* d_x, int64_t k,
-                       hipStream_t st) {
+                       int64_t* d_knots, hipStream_t st) {
+    if (init == 1)
+        hipLaunchKernelGGL(k_greedy_knots, dim3(1), dim3(kKnotThreads), 0, st, d_x, k, H, d_knots);
+    else if (init == 2)
+        hipLaunchKernelGGL(k_quantile_knots, dim3(1), dim3(128), 0, st, k, H, d_knots);
     hipLaunchKernelGGL(k_init, dim3(nblk(H * H + 4 * H + 1, 256)), dim3(256), 0, st, d_theta, H, init, seed,
-                       d_x, k);
+                       d_x, k, (const int64_t*)d_knots);
     return hipGetLastError();
 }
 

@@ -46,6 +46,8 @@ __device__ __forceinline__ double model_fp32(const DevModel* __restrict__ m, dou
 
 template <int H>
 __global__ void __launch_bounds__(256) k_infer_fp32(InferArgs a) {
+    __shared__ SpillEntry s_stage[4][kSpillStage];
+    WaveSpill w{s_stage[threadIdx.x >> 6], 0, 0};
     const DevModel* __restrict__ m = a.model;
     const double lo = m->lo, inv = m->inv_range;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -65,12 +67,15 @@ __global__ void __launch_bounds__(256) k_infer_fp32(InferArgs a) {
             if (a.slots_out) a.slots_out[i] = slot;
             if (a.F_out) a.F_out[i] = F;
         }
-        place_key(a, i, active, okey, slot);
+        place_key(a, i, active, okey, slot, w);
     }
+    spill_finish(w, a);
 }
 
 // Caller-given slots (closed-form models in tests): no inference.
 __global__ void __launch_bounds__(256) k_place_given(InferArgs a) {
+    __shared__ SpillEntry s_stage[4][kSpillStage];
+    WaveSpill w{s_stage[threadIdx.x >> 6], 0, 0};
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < a.n; base += stride) {
         int64_t i = base + threadIdx.x;
@@ -81,8 +86,9 @@ __global__ void __launch_bounds__(256) k_place_given(InferArgs a) {
         bool bad = active && slot != kUnmapped && (int64_t)slot >= a.S;
         count_aggregate(bad, &a.counters[kCntBadSlot]);
         if (bad) slot = kUnmapped;
-        place_key(a, i, active, okey, slot);
+        place_key(a, i, active, okey, slot, w);
     }
+    spill_finish(w, a);
 }
 
 // Sum over sorted positions p of |F_p n - p| for mappable keys (F not NaN):

@@ -26,7 +26,7 @@ enum Counter : int {
     kCntUnmapped = 1,     // keys with no slot
     kCntCollided = 2,     // [2, 2 + 8): |c_r| for r = 1..8 (all buckets)
     kCntPlaced = 10,      // [10, 18): keys stored in o_r
-    kCntBigKeys = 18,     // keys of big buckets
+    kCntBigKeys = 18,     // region entries of big buckets (kBucketCap each)
     kCntBigBuckets = 19,
     kCntGlobal = 20,      // entries in the global residue list G
     kCntBoundary = 21,    // keys inside boundary fix-up zones
@@ -36,6 +36,13 @@ enum Counter : int {
     kCntPosErrSum = 25,   // double bits: sum |F n - p|
     kCntPosErrCnt = 26,
     kNumCounters = 32
+};
+
+// A key handed to its slot range's region: order key and (input index << 32 |
+// slot within the range), stored together as one 16-byte write.
+struct RegionEntry {
+    uint64_t okey;
+    uint64_t meta;
 };
 
 // A spill entry: a key whose bucket region was full, or that has no slot.
@@ -76,7 +83,7 @@ struct SortPlan {
     int64_t S;         // slots
     int64_t NB;        // buckets
     int64_t big_max;   // capacity for big buckets' slot histograms
-    size_t off_counters, off_cnt, off_region_key, off_region_meta, off_spill, off_bucket_info,
+    size_t off_counters, off_cnt, off_region, off_spill, off_bucket_info,
         off_segminmax, off_G, off_radix, off_M, off_big_hist, off_model, off_bigmap, total;
     size_t radix_bytes;
 };
@@ -97,8 +104,7 @@ struct InferArgs {
     double* F_out;                // optional per-key F
     int scatter;                  // 1: hand keys to bucket regions / spill
     uint32_t* cnt;
-    uint64_t* region_key;
-    uint64_t* region_meta;
+    RegionEntry* region;
     SpillEntry* spill;
     unsigned long long* counters;
 };

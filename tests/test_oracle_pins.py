@@ -451,16 +451,35 @@ def test_sample_and_batch_indices_in_range_and_spread():
     assert not np.array_equal(b, O.batch_indices(5, 4, 77, 10_000))
 
 
-def test_ramp_init_interpolates_sample_cdf():
-    """Quantile-ramp initialisation: F(q_j) = j/H at the knots."""
+@pytest.mark.parametrize("init", [1, 2])
+def test_ramp_init_interpolates_sample_cdf(init):
+    """Ramp initialisation: F(q_i) = (idx_i + 0.5)/k at every knot, monotone
+    in between (quantile knots for init 2 sit at j/H)."""
     x = W.lognormal(100_000, seed=1)
     H = 16
     s, lo, inv, xh, y = O.fit_sample(x, 0.05, 0)
-    model = O.fit(x, H=H, sample_frac=0.05, steps=0)
-    q = np.array([xh[(j * (xh.size - 1)) // H] for j in range(H + 1)])
-    F = O.eval_F(q, model, O.FORM_FP64)
-    assert np.allclose(F, np.arange(H + 1) / H, atol=2e-3)
+    model = O.fit(x, H=H, sample_frac=0.05, steps=0, init=init)
+    k = xh.size
+    idx = (O.greedy_knot_indices(xh, H) if init == 1
+           else np.array([(j * (k - 1)) // H for j in range(H + 1)]))
+    F = O.eval_F(xh[idx], model, O.FORM_FP64)
+    assert np.allclose(F, (idx + 0.5) / k, atol=1e-6)
+    if init == 2:
+        assert np.allclose(F, np.arange(H + 1) / H, atol=2e-3)
     assert np.all(np.diff(O.eval_F(np.linspace(0, 1, 10001), model)) >= -1e-6)
+
+
+def test_greedy_knots_find_a_density_kink():
+    """100 evenly spaced points on [0, 1/2) then 900 on [1/2, 1]: the chord of
+    the empirical CDF deviates most at the kink, so the first split is there;
+    a straight line (uniform grid) is never split."""
+    xs = np.concatenate([np.linspace(0, 0.5, 100, endpoint=False), np.linspace(0.5, 1, 900)])
+    idx = O.greedy_knot_indices(xs, 2)
+    assert idx[0] == 0 and idx[2] == 999 and idx[1] in (99, 100)
+    flat = O.greedy_knot_indices(np.linspace(0, 1, 1001), 8)
+    assert flat.tolist() == [0] + [1000] * 8
+    dup = O.greedy_knot_indices(np.zeros(50), 4)
+    assert dup.tolist() == [0, 49, 49, 49, 49]
 
 
 def test_fit_reduces_loss_from_random_init():
