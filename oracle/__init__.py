@@ -405,9 +405,12 @@ def fit(x: np.ndarray, H: int = 32, sample_frac: float = 0.01, batch: int = 6553
     """CPU FP64 fit of the CDF model: Adam on MSE (loss 0) or the paper's Huber
     loss (loss 1) to the normalised rank of a random sample.  Returns the
     parameters with the lowest batch loss seen (a step's loss is measured
-    before its update; the initial parameters if no step improved)."""
+    before its update), unless they move F backwards along the sorted sample
+    more than the initial parameters do (disorder sum_j max(0, F_j - F_{j+1}));
+    then the initial parameters."""
     s, lo, inv, xh, y = fit_sample(x, sample_frac, seed)
     th = init_theta(H, init, seed, xh)
+    th0 = th.copy()
     best, best_loss = th.copy(), math.inf
     m1 = np.zeros_like(th)
     m2 = np.zeros_like(th)
@@ -422,6 +425,12 @@ def fit(x: np.ndarray, H: int = 32, sample_frac: float = 0.01, batch: int = 6553
         if L < best_loss:
             best, best_loss = th.copy(), L
         adam_step(th, g, m1, m2, t, lr)
+    if steps > 0 and k2 > 1:
+        def disorder(t):
+            F = eval_F(xh, {"H": H, "theta": t.astype(np.float32)}, FORM_FP64)
+            return float(np.maximum(F[:-1] - F[1:], 0.0).sum())
+        if disorder(best) > disorder(th0):
+            best = th0
     model = {"H": H, "lo": lo, "inv_range": inv, "theta": best.astype(np.float32)}
     if return_history:
         return model, hist

@@ -48,6 +48,8 @@ hipError_t launch_loss_grad(const float* d_F, const float* d_y, int64_t B, int l
                             float* d_loss, float* d_partial, hipStream_t st);
 hipError_t launch_keep_best(const float* d_theta, float* d_best, int P, const float* d_loss, float* d_best_loss,
                             hipStream_t st);
+size_t disorder_ws_doubles();
+hipError_t launch_disorder(const float* d_F, int64_t k, double* d_ws, hipStream_t st);
 }  // namespace nns
 
 using namespace nns;
@@ -375,7 +377,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
 struct FitPlan {
     int64_t k, B;
     int H;
-    size_t off_best, off_knots, off_sample, off_count, off_x, off_y, off_bx, off_by, off_F, off_gF, off_saved, off_bws, off_theta,
+    size_t off_init, off_Fs, off_dis, off_best, off_knots, off_sample, off_count, off_x, off_y, off_bx, off_by, off_F, off_gF, off_saved, off_bws, off_theta,
         off_grad, off_m1, off_m2, off_loss, off_lpart, off_radix, total;
 };
 
@@ -414,6 +416,9 @@ FitPlan plan_fit(int64_t n, const nnsort_fit_params* fp) {
     p.off_lpart = take(loss_ws_floats() * 4);
     p.off_knots = take((NNSORT_MAX_HIDDEN + 1) * 8);
     p.off_best = take((size_t)(P + 64) * 4);
+    p.off_init = take((size_t)P * 4);
+    p.off_Fs = take((size_t)p.k * 4);
+    p.off_dis = take(disorder_ws_doubles() * 2 * 8);
     p.off_radix = take(radix_ws_bytes(p.k));
     p.total = o;
     return p;
@@ -461,6 +466,9 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
     const int Pn = H * H + 4 * H + 1;
     float* best = (float*)(ws + P.off_best);
     float* best_loss = best + Pn;
+    float* init_theta = (float*)(ws + P.off_init);
+    float* Fs = (float*)(ws + P.off_Fs);
+    double* dis = (double*)(ws + P.off_dis);
 
     NNS_HIP(fill_u64(count, 1, 0, st));
     NNS_HIP(launch_sample(d_keys, n, is_f64, fp->seed, P.k, sample, count, st));
@@ -493,6 +501,7 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
     NNS_HIP(hipMemsetAsync(m1, 0, (size_t)Pn * 4, st));
     NNS_HIP(hipMemsetAsync(m2, 0, (size_t)Pn * 4, st));
     NNS_HIP(hipMemcpyAsync(best, theta, (size_t)Pn * 4, hipMemcpyDeviceToDevice, st));
+    NNS_HIP(hipMemcpyAsync(init_theta, theta, (size_t)Pn * 4, hipMemcpyDeviceToDevice, st));
     NNS_HIP(fill_u32((uint32_t*)best_loss, 1, 0x7F800000u, st));  // +inf
     for (int t = 1; t <= fp->steps; ++t) {
         NNS_HIP(launch_batch(x, y, (int64_t)k2, fp->seed, t, P.B, bx, by, st));
@@ -504,10 +513,24 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
         NNS_HIP(launch_mlp_backward(H, theta, bx, P.B, saved, gF, grad, bws, st));
         NNS_HIP(launch_adam(theta, grad, m1, m2, Pn, t, fp->lr, 0.9f, 0.999f, 1e-8f, st));
     }
+    // Returned: the parameters with the lowest batch loss seen, unless they
+    // move F backwards along the sorted sample more than the initial ones do
+    // (a model that is less monotone only adds work to the polish).
+    const float* chosen = best;
+    if (fp->steps > 0) {
+        const size_t dw = disorder_ws_doubles();
+        NNS_HIP(launch_mlp_forward(H, init_theta, x, (int64_t)k2, Fs, nullptr, st));
+        NNS_HIP(launch_disorder(Fs, (int64_t)k2, dis, st));
+        NNS_HIP(launch_mlp_forward(H, best, x, (int64_t)k2, Fs, nullptr, st));
+        NNS_HIP(launch_disorder(Fs, (int64_t)k2, dis + dw, st));
+        double d[2];
+        NNS_HIP(hipMemcpyAsync(&d[0], dis + dw - 1, 8, hipMemcpyDeviceToHost, st));
+        NNS_HIP(hipMemcpyAsync(&d[1], dis + 2 * dw - 1, 8, hipMemcpyDeviceToHost, st));
+        NNS_HIP(hipStreamSynchronize(st));
+        if (d[1] > d[0]) chosen = init_theta;
+    }
     std::vector<float> th((size_t)Pn);
-    // the parameters with the lowest batch loss seen (the initial ones if no
-    // step improved on them)
-    NNS_HIP(hipMemcpyAsync(th.data(), best, (size_t)Pn * 4, hipMemcpyDeviceToHost, st));
+    NNS_HIP(hipMemcpyAsync(th.data(), chosen, (size_t)Pn * 4, hipMemcpyDeviceToHost, st));
     NNS_HIP(hipStreamSynchronize(st));
     M.lo = lo;
     M.inv_range = inv;

@@ -475,6 +475,42 @@ __global__ void __launch_bounds__(256) k_keep_best(const float* __restrict__ th,
     if (threadIdx.x == 0) best_loss[0] = loss[0];
 }
 
+// Disorder of a model over the sorted sample: sum_j max(0, F_j - F_{j+1}),
+// how far F moves backwards along keys that are in order (0 for a monotone
+// model).  Partial sums per block (fixed order), then one block adds them.
+__global__ void __launch_bounds__(256) k_disorder_partial(const float* __restrict__ F, int64_t k, double* part) {
+    __shared__ double s[256];
+    double acc = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j + 1 < k; j += (int64_t)gridDim.x * blockDim.x) {
+        float d = F[j] - F[j + 1];
+        acc += d > 0.0f ? (double)d : 0.0;
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < (unsigned)off) s[threadIdx.x] += s[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ void k_disorder_final(const double* __restrict__ part, int nb, double* out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < nb; ++i) t += part[i];
+        out[0] = t;
+    }
+}
+
+constexpr int kDisorderBlocks = 512;
+size_t disorder_ws_doubles() { return kDisorderBlocks + 1; }
+
+hipError_t launch_disorder(const float* d_F, int64_t k, double* d_ws, hipStream_t st) {
+    hipLaunchKernelGGL(k_disorder_partial, dim3(kDisorderBlocks), dim3(256), 0, st, d_F, k, d_ws);
+    hipLaunchKernelGGL(k_disorder_final, dim3(1), dim3(64), 0, st, d_ws, kDisorderBlocks, d_ws + kDisorderBlocks);
+    return hipGetLastError();
+}
+
 hipError_t launch_keep_best(const float* d_theta, float* d_best, int P, const float* d_loss, float* d_best_loss,
                             hipStream_t st) {
     hipLaunchKernelGGL(k_keep_best, dim3(1), dim3(256), 0, st, d_theta, d_best, P, d_loss, d_best_loss);

@@ -14,9 +14,9 @@
 //    Henry, Tang and Heinecke, 2019) while W2 itself is rounded to bfloat16;
 //  - the accumulators start at b2; lane (j, g) ends with hidden-2 units
 //    32 rb + 8 (v / 4) + 4 g + v % 4 (v = 0..15) of its key;
-//  - layer 3: relu, then a Kahan-compensated FP32 sum per lane, the two halves
-//    combined as (sum - correction) in FP64 so that F keeps a resolution finer
-//    than one slot at n = 1e9.
+//  - layer 3: relu, then a compensated FP32 dot product per lane (Dot2 of
+//    Ogita, Rump and Oishi), the two halves' (sum, correction) pairs added in
+//    FP64 so that F keeps a resolution finer than one slot at n = 1e9.
 // Compiled with -ffp-contract=off.
 #include "infer_common.h"
 
@@ -136,21 +136,25 @@ __global__ void __launch_bounds__(256) k_infer_bf16(InferArgs a) {
             }
         }
 
-        // layer 3: Kahan-compensated sum of w3 * relu(z2) over this lane's units
+        // layer 3: compensated dot product (Dot2: TwoProduct by FMA + TwoSum) of
+        // w3 and relu(z2) over this lane's units; a product rounded to FP32
+        // alone would quantise F to ~1e-8 * w3, more than a slot at n = 1e8
         float sum = g == 0 ? b3 : 0.0f, c = 0.0f;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                float h2 = acc[rb][v] > 0.0f ? acc[rb][v] : 0.0f;
-                float y = w3r[rb][v] * h2 - c;
-                float t = sum + y;
-                c = (t - sum) - y;
-                sum = t;
+                const float h2 = acc[rb][v] > 0.0f ? acc[rb][v] : 0.0f;
+                const float w = w3r[rb][v];
+                const float pr = w * h2;
+                const float r = __builtin_fmaf(w, h2, -pr);
+                float q;
+                sum = two_sum(sum, pr, q);
+                c = c + (q + r);
             }
         const float osum = __shfl_xor(sum, 32);
         const float oc = __shfl_xor(c, 32);
-        const double F = ((double)sum - (double)c) + ((double)osum - (double)oc);
+        const double F = ((double)sum + (double)c) + ((double)osum + (double)oc);
         const uint32_t slot = mapped ? slot_of(F, a.M) : kUnmapped;
         const bool mine = active && g == 0;
         if (mine) {

@@ -211,6 +211,29 @@ def test_bf16_F_within_bound(H):
     assert np.all(d[ok] <= bound[ok] + 1e-300), float(np.max(d[ok] / bound[ok]))
 
 
+@pytest.mark.parametrize("name,H", [("gauss_mix", 64), ("lognormal", 32)])
+def test_bf16_slots_track_fp32_on_ramp_model(name, H):
+    """On a ramp model (W2 = -I is exact in bf16, output weights all different)
+    the three-term BF16 form must give the FP32 form's slots up to rounding:
+    nearly all equal, none more than a few slots away, and the same round
+    counts to within 0.1% of n."""
+    n = 1_000_000
+    x = W.make(name, n)
+    model = O.fit(x, H=H, sample_frac=0.01, steps=0)
+    m = nn.model_from_dict(model)
+    xd = to_dev(x)
+    s32, _ = nn.nnsort_predict(m, xd, nn.sort_params(form=nn.FORM_FP32))
+    s16, _ = nn.nnsort_predict(m, xd, nn.sort_params(form=nn.FORM_BF16, bf16_terms=3))
+    a = s32.cpu().numpy().astype(np.int64)
+    b = s16.cpu().numpy().astype(np.int64)
+    assert np.mean(a == b) > 0.999
+    assert np.max(np.abs(a - b)) <= 4
+    _, st32 = nn.nnsort_sort_with_model(m, xd, sp=nn.sort_params(form=nn.FORM_FP32))
+    _, st16 = nn.nnsort_sort_with_model(m, xd, sp=nn.sort_params(form=nn.FORM_BF16))
+    for c32, c16 in zip(st32["collided"], st16["collided"]):
+        assert abs(c32 - c16) <= n // 1000
+
+
 @pytest.mark.parametrize("terms", [1, 2, 3])
 def test_bf16_sort_exact_and_counts(terms):
     x = W.gauss_mix(400_000, seed=6)
