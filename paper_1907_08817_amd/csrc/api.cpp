@@ -18,13 +18,26 @@ hipError_t fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
 hipError_t launch_classify(const uint32_t* d_cnt, int64_t NB, int64_t big_max, int32_t* d_bigmap,
                            uint64_t* d_moff, int32_t* d_seglist, int32_t* d_bigbucket,
                            uint64_t* d_counters, hipStream_t st);
-hipError_t launch_big_buckets(const int32_t* d_bigbucket, int64_t big_count, const int32_t* d_bigmap,
-                              const RegionEntry* d_region,
-                              const SpillEntry* d_spill, int64_t spill_count, uint32_t* d_big_hist,
-                              uint64_t* d_G, uint64_t* d_counters, int eps, hipStream_t st);
-hipError_t launch_bucket_polish(const uint32_t* d_cnt, const uint64_t* d_moff, int64_t NB,
-                                const RegionEntry* d_region, int eps, void* d_M, bool M_is_bits, bool is_f64,
-                                uint64_t* d_segmin, uint64_t* d_segmax, uint64_t* d_counters, hipStream_t st);
+hipError_t launch_big_counts(const uint32_t* d_hist, int64_t big_count, int eps, uint64_t* d_counters,
+                             hipStream_t st);
+hipError_t launch_bucket_polish(const uint32_t* d_cnt, const int64_t* d_start, const uint64_t* d_moff, int64_t NB,
+                                const uint64_t* d_K, const uint32_t* d_S, int eps, void* d_M, bool M_is_bits,
+                                bool is_f64, uint64_t* d_segmin, uint64_t* d_segmax, uint64_t* d_counters,
+                                hipStream_t st);
+size_t partition_hist_words(int64_t n);
+hipError_t partition_by_range(const uint64_t* in_keys, const uint32_t* in_slots, int64_t n, uint32_t NB, bool is_f64,
+                              uint64_t* K0, uint32_t* S0, uint64_t* K1, uint32_t* S1, uint32_t* blockhist,
+                              uint32_t* sums, int* which, hipStream_t st);
+hipError_t launch_range_bounds(const uint32_t* d_sorted_slots, int64_t n, uint32_t NB, int64_t* d_start,
+                               uint32_t* d_cnt, hipStream_t st);
+hipError_t launch_check_slots(const uint32_t* d_slots, int64_t n, int64_t S, uint64_t* d_bad, hipStream_t st);
+hipError_t launch_big_chunks(const int32_t* d_bigbucket, int64_t big_count, const int64_t* d_start,
+                             int64_t* d_chunk_pref, int64_t* d_gpref, hipStream_t st);
+hipError_t launch_big_gather(const int32_t* d_bigbucket, int64_t big_count, int64_t nchunks,
+                             const int64_t* d_chunk_pref, const int64_t* d_gpref, const int64_t* d_start,
+                             const uint64_t* d_K, const uint32_t* d_S, uint32_t* d_hist, uint64_t* d_G,
+                             hipStream_t st);
+hipError_t launch_copy_u64(const uint64_t* d_in, uint64_t* d_out, int64_t n, hipStream_t st);
 hipError_t launch_boundary_plan(const void* d_M, bool M_is_bits, bool is_f64, const uint64_t* d_moff,
                                 const uint32_t* d_cnt, const int32_t* d_seglist, int64_t K,
                                 const uint64_t* d_segmin, const uint64_t* d_segmax, void* d_zones,
@@ -135,10 +148,17 @@ SortPlan plan_sort(int64_t n, double m) {
     size_t nn = (size_t)(n > 0 ? n : 1);
     p.off_counters = take(kNumCounters * 8);
     p.off_cnt = take((size_t)p.NB * 4);
-    p.off_region = take((size_t)p.NB * kBucketCap * sizeof(RegionEntry));
-    p.off_spill = take(nn * sizeof(SpillEntry));
+    p.off_start = take((size_t)(p.NB + 2) * 8);
+    p.off_slots0 = take(nn * 4);
+    p.off_S0 = take(nn * 4);
+    p.off_K0 = take(nn * 8);
+    p.off_K1 = take(nn * 8);
+    size_t ph = partition_hist_words(n);
+    p.off_phist = take(ph * 4);
+    p.off_psums = take(((ph + 2047) / 2048 + 1) * 4);
     p.off_bucket_info = take(align256((size_t)p.NB * 4) + align256((size_t)p.NB * 8) +
                              align256((size_t)p.NB * 4) + (size_t)p.big_max * 4);
+    p.off_bigpref = take((size_t)(p.big_max + 1) * 2 * 8);
     p.off_segminmax = take((size_t)p.NB * 16 + (size_t)p.NB * zone_bytes());
     p.off_G = take(nn * 8);
     p.off_M = take(nn * 8);
@@ -231,12 +251,19 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     char* ws = (char*)d_ws;
     uint64_t* counters = (uint64_t*)(ws + P.off_counters);
     uint32_t* cnt = (uint32_t*)(ws + P.off_cnt);
-    RegionEntry* region = (RegionEntry*)(ws + P.off_region);
-    SpillEntry* spill = (SpillEntry*)(ws + P.off_spill);
+    int64_t* start = (int64_t*)(ws + P.off_start);
+    uint32_t* slots0 = (uint32_t*)(ws + P.off_slots0);
+    uint32_t* S0 = (uint32_t*)(ws + P.off_S0);
+    uint64_t* K0 = (uint64_t*)(ws + P.off_K0);
+    uint64_t* K1 = (uint64_t*)(ws + P.off_K1);
+    uint32_t* phist = (uint32_t*)(ws + P.off_phist);
+    uint32_t* psums = (uint32_t*)(ws + P.off_psums);
     int32_t* bigmap = (int32_t*)(ws + P.off_bucket_info);
     uint64_t* moff = (uint64_t*)(ws + P.off_bucket_info + align256((size_t)P.NB * 4));
     int32_t* seglist = (int32_t*)((char*)moff + align256((size_t)P.NB * 8));
     int32_t* bigbucket = (int32_t*)((char*)seglist + align256((size_t)P.NB * 4));
+    int64_t* chunk_pref = (int64_t*)(ws + P.off_bigpref);
+    int64_t* gpref = chunk_pref + (P.big_max + 1);
     uint64_t* segmin = (uint64_t*)(ws + P.off_segminmax);
     uint64_t* segmax = segmin + P.NB;
     void* zones = (void*)(segmax + P.NB);
@@ -246,10 +273,9 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     DevModel* dmodel = (DevModel*)(ws + P.off_model);
     void* radix_ws = ws + P.off_radix;
     // the bucket_info carve-up must fit its reservation
-    if ((char*)(bigbucket + P.big_max) > ws + P.off_segminmax) return NNSORT_EINTERNAL;
+    if ((char*)(bigbucket + P.big_max) > ws + P.off_bigpref) return NNSORT_EINTERNAL;
 
     NNS_HIP(fill_u64(counters, kNumCounters, 0, st));
-    NNS_HIP(fill_u32(cnt, P.NB, 0, st));
     DevModel hm;
     int HP = 32;
     if (model) {
@@ -258,7 +284,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
         NNS_HIP(hipMemcpyAsync(dmodel, &hm, sizeof(hm), hipMemcpyHostToDevice, st));
     }
 
-    // ---- input phase + map + hand-off to slot-range buckets ----
+    // ---- input phase + map: a slot per key ----
     InferArgs ia{};
     ia.model = dmodel;
     ia.in = (const uint64_t*)d_in;
@@ -266,44 +292,63 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     ia.is_f64 = is_f64 ? 1 : 0;
     ia.M = prm->m * (double)n;
     ia.S = P.S;
-    ia.given_slots = given_slots;
-    ia.scatter = 1;
-    ia.cnt = cnt;
-    ia.region = region;
-    ia.spill = spill;
-    ia.counters = (unsigned long long*)counters;
+    ia.slots_out = slots0;
     ev.mark(7);
-    NNS_HIP(launch_infer(ia, HP, prm->form, prm->bf16_terms, st));
+    const uint32_t* slots_src = slots0;
+    if (given_slots) {
+        NNS_HIP(launch_check_slots(given_slots, n, P.S, counters + kCntBadSlot, st));
+        slots_src = given_slots;
+    } else {
+        NNS_HIP(launch_infer(ia, HP, prm->form, prm->bf16_terms, st));
+    }
     ev.mark(1);
+
+    // ---- hand-off: stable partition of (key, slot) by slot range ----
+    const uint32_t NB = (uint32_t)P.NB;
+    int which = 0;
+    NNS_HIP(partition_by_range((const uint64_t*)d_in, slots_src, n, NB, is_f64, K0, S0, K1, slots0, phist, psums,
+                               &which, st));
+    const uint64_t* Ks = which ? K1 : K0;
+    const uint32_t* Ss = which ? slots0 : S0;
+    NNS_HIP(launch_range_bounds(Ss, n, NB, start, cnt, st));
     NNS_HIP(launch_classify(cnt, P.NB, P.big_max, bigmap, moff, seglist, bigbucket, counters, st));
     uint64_t c[kNumCounters];
+    int64_t first_unmapped = 0;
     NNS_HIP(hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, st));
+    NNS_HIP(hipMemcpyAsync(&first_unmapped, start + NB, 8, hipMemcpyDeviceToHost, st));
     NNS_HIP(hipStreamSynchronize(st));
     if (c[kCntBadSlot]) return NNSORT_EINVAL;
     const int64_t big_count = (int64_t)c[kCntBigBuckets];
-    // G: the region entries of dense ranges plus every spilled key (overflow
-    // of dense ranges and keys without a slot)
-    const int64_t G_size = (int64_t)(c[kCntBigKeys] + c[kCntSpill]);
-    const int64_t spill_count = (int64_t)c[kCntSpill];
+    const int64_t big_keys = (int64_t)c[kCntBigKeys];
+    const int64_t unm = n - first_unmapped;
+    // G: the keys of ranges too dense for LDS, then the keys without a slot
+    const int64_t G_size = big_keys + unm;
     if (big_count > P.big_max) return NNSORT_EINTERNAL;
 
-    // ---- slot ranges too dense for LDS, and keys without a slot: to G ----
-    if (G_size > 0)
-        NNS_HIP(launch_big_buckets(bigbucket, big_count, bigmap, region, spill, spill_count, big_hist, G,
-                                   counters, eps, st));
+    // ---- dense ranges and keys without a slot: to G ----
+    if (big_count > 0) {
+        NNS_HIP(fill_u32(big_hist, big_count * (int64_t)kBucketSlots, 0u, st));
+        NNS_HIP(launch_big_chunks(bigbucket, big_count, start, chunk_pref, gpref, st));
+        int64_t nchunks = 0;
+        NNS_HIP(hipMemcpyAsync(&nchunks, chunk_pref + big_count, 8, hipMemcpyDeviceToHost, st));
+        NNS_HIP(hipStreamSynchronize(st));
+        NNS_HIP(launch_big_gather(bigbucket, big_count, nchunks, chunk_pref, gpref, start, Ks, Ss, big_hist, G, st));
+        NNS_HIP(launch_big_counts(big_hist, big_count, eps, counters, st));
+    }
+    if (unm > 0) NNS_HIP(launch_copy_u64(Ks + first_unmapped, G + big_keys, unm, st));
     ev.mark(2);
+
     // ---- rounds + polish of each slot range in LDS ----
     const bool M_is_bits = G_size == 0;
     void* M = M_is_bits ? d_out : (void*)Mbuf;
     const int64_t M_len = n - G_size;
-    NNS_HIP(launch_bucket_polish(cnt, moff, P.NB, region, eps, M, M_is_bits, is_f64, segmin, segmax,
+    NNS_HIP(launch_bucket_polish(cnt, start, moff, P.NB, Ks, Ss, eps, M, M_is_bits, is_f64, segmin, segmax,
                                  counters, st));
     const int64_t K = (int64_t)c[kCntSmallBuckets];
     NNS_HIP(launch_boundary_plan(M, M_is_bits, is_f64, moff, cnt, seglist, K, segmin, segmax, zones, counters,
                                  st));
     NNS_HIP(hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, st));
     NNS_HIP(hipStreamSynchronize(st));
-    if ((int64_t)c[kCntGlobal] != G_size) return NNSORT_EINTERNAL;  // every dense/spilled key reached G
     if (c[kCntFallback]) {
         const int mode = M_is_bits ? (is_f64 ? 1 : 2) : 0;
         if (P.radix_bytes < radix_ws_bytes(M_len)) return NNSORT_EINTERNAL;
@@ -328,7 +373,6 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     // while i < eps and count(w) > tau: the rounds were computed for all eps;
     // the procedure stops at the first round whose conflict array is <= tau.
     int t = 1;
-    int64_t unm = (int64_t)c[kCntUnmapped];
     while (t < eps && (int64_t)c[kCntCollided + t - 1] + unm > prm->tau) ++t;
     S.rounds = t;
     for (int r = 0; r < t; ++r) {
@@ -338,15 +382,13 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     S.residue = S.collided[t - 1];
     S.unmapped = unm;
     S.big_buckets = big_count;
-    S.big_bucket_keys = (int64_t)(c[kCntBigKeys] + c[kCntSpill] - c[kCntUnmapped]);
+    S.big_bucket_keys = big_keys;
     S.boundary_keys = (int64_t)c[kCntBoundary];
     S.fallback = c[kCntFallback] ? 1 : 0;
     if (stats && prm->stats_level >= 2 && model) {
-        double* Fbuf = (double*)region;  // region storage is free now
+        double* Fbuf = (double*)K1;  // partition storage is free now
         InferArgs pa = ia;
         pa.in = (const uint64_t*)d_out;
-        pa.given_slots = nullptr;
-        pa.scatter = 0;
         pa.F_out = Fbuf;
         pa.slots_out = nullptr;
         NNS_HIP(launch_infer(pa, HP, prm->form, prm->bf16_terms, st));
@@ -670,7 +712,6 @@ int nnsort_predict(const nnsort_model* model, const void* d_in, int64_t n, nnsor
     ia.S = num_slots(n, params->m);
     ia.slots_out = d_slots;
     ia.F_out = d_F;
-    ia.scatter = 0;
     NNS_HIP(launch_infer(ia, hm.H, params->form, params->bf16_terms, st));
     NNS_HIP(hipStreamSynchronize(st));
     return NNSORT_OK;

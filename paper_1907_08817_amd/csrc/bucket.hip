@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(1024) k_classify(const uint32_t* __restrict__ 
         uint32_t c = cnt[b];
         if (c > kBucketCap) {
             ++big;
-            bigkeys += kBucketCap;
+            bigkeys += c;
         } else {
             small += c;
             seg += c ? 1 : 0;
@@ -131,83 +131,8 @@ hipError_t launch_classify(const uint32_t* d_cnt, int64_t NB, int64_t big_max, i
 }
 
 // ---------------------------------------------------------------------------
-// big buckets: slot multiplicities (for the round counts) and gather to G
+// big buckets: round counts from the slot multiplicities
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void g_append(bool want, uint64_t okey, uint64_t* G,
-                                         unsigned long long* counter) {
-    unsigned long long mask = __ballot(want);
-    if (!mask) return;
-    int leader = __ffsll((long long)mask) - 1;
-    unsigned long long base = 0;
-    if ((int)__lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
-    base = __shfl(base, leader);
-    if (want) G[base + __popcll(mask & ((1ull << __lane_id()) - 1ull))] = okey;
-}
-
-// Region entries of big buckets: thread per (big id, entry).
-__global__ void __launch_bounds__(256) k_big_region(const int32_t* __restrict__ bigbucket, int64_t big_count,
-                                                    const RegionEntry* __restrict__ region, uint32_t* hist,
-                                                    uint64_t* G, unsigned long long* counters) {
-    int64_t total = big_count * (int64_t)kBucketCap;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
-        int64_t i = base + threadIdx.x;
-        bool act = i < total;
-        uint64_t okey = 0;
-        if (act) {
-            int64_t id = i / kBucketCap;
-            int64_t e = (int64_t)bigbucket[id] * kBucketCap + (i % kBucketCap);
-            RegionEntry r = region[e];
-            okey = r.okey;
-            uint32_t lsl = (uint32_t)(r.meta & (kBucketSlots - 1));
-            atomicAdd(&hist[id * kBucketSlots + lsl], 1u);
-        }
-        g_append(act, okey, G, &counters[kCntGlobal]);
-    }
-}
-
-// Spill entries: overflow of big buckets, and keys without a slot.  Spilled
-// keys crowd into few slots, so a wave adds its lanes' slot counts with one
-// atomic per distinct slot (up to 8 distinct slots, then one per lane).
-__global__ void __launch_bounds__(256) k_big_spill(const SpillEntry* __restrict__ spill, int64_t count,
-                                                   const int32_t* __restrict__ bigmap, uint32_t* hist,
-                                                   uint64_t* G, unsigned long long* counters) {
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const unsigned lane = __lane_id();
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < count; base += stride) {
-        int64_t i = base + threadIdx.x;
-        bool act = i < count;
-        uint64_t okey = 0;
-        bool pending = false;
-        uint32_t hidx = 0;
-        if (act) {
-            SpillEntry e = spill[i];
-            okey = e.okey;
-            if (e.slot != kUnmapped) {
-                int32_t id = bigmap[e.slot >> kLogBucketSlots];
-                if (id >= 0) {
-                    pending = true;
-                    hidx = (uint32_t)id * kBucketSlots + (e.slot & (kBucketSlots - 1));
-                } else {
-                    atomicAdd(&counters[kCntBadSlot], 1ull);  // cannot happen: spill implies big
-                }
-            }
-        }
-        for (int it = 0; it < 8; ++it) {
-            unsigned long long mask = __ballot(pending);
-            if (!mask) break;
-            int leader = __ffsll((long long)mask) - 1;
-            uint32_t target = __shfl(hidx, leader);
-            bool same = pending && hidx == target;
-            unsigned long long sm_ = __ballot(same);
-            if (lane == (unsigned)leader) atomicAdd(&hist[target], (uint32_t)__popcll(sm_));
-            if (same) pending = false;
-        }
-        if (pending) atomicAdd(&hist[hidx], 1u);
-        g_append(act, okey, G, &counters[kCntGlobal]);
-    }
-}
-
 // Round counts of big buckets from slot multiplicities k_s: round r stores
 // min(k_s, r) - min(k_s, r - 1) keys of slot s and leaves max(0, k_s - r).
 __global__ void __launch_bounds__(256) k_big_counts(const uint32_t* __restrict__ hist, int64_t total, int eps,
@@ -238,29 +163,12 @@ __global__ void __launch_bounds__(256) k_big_counts(const uint32_t* __restrict__
     }
 }
 
-hipError_t launch_big_buckets(const int32_t* d_bigbucket, int64_t big_count, const int32_t* d_bigmap,
-                              const RegionEntry* d_region,
-                              const SpillEntry* d_spill, int64_t spill_count, uint32_t* d_big_hist,
-                              uint64_t* d_G, uint64_t* d_counters, int eps, hipStream_t st) {
-    unsigned long long* c = (unsigned long long*)d_counters;
-    hipError_t e = fill_u32(d_big_hist, big_count * (int64_t)kBucketSlots, 0u, st);
-    if (e != hipSuccess) return e;
-    if (big_count > 0) {
-        hipLaunchKernelGGL(k_big_region, dim3(blocks_for(big_count * kBucketCap, 256, 16384)), dim3(256), 0,
-                           st, d_bigbucket, big_count, d_region, d_big_hist, d_G, c);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    if (spill_count > 0) {
-        hipLaunchKernelGGL(k_big_spill, dim3(blocks_for(spill_count, 256, 16384)), dim3(256), 0, st,
-                           d_spill, spill_count, d_bigmap, d_big_hist, d_G, c);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    if (big_count > 0) {
-        hipLaunchKernelGGL(k_big_counts, dim3(blocks_for(big_count * kBucketSlots, 256, 2048)), dim3(256),
-                           0, st, d_big_hist, big_count * (int64_t)kBucketSlots, eps, c);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    return hipSuccess;
+hipError_t launch_big_counts(const uint32_t* d_hist, int64_t big_count, int eps, uint64_t* d_counters,
+                             hipStream_t st) {
+    if (big_count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_big_counts, dim3(blocks_for(big_count * kBucketSlots, 256, 2048)), dim3(256), 0, st,
+                       d_hist, big_count * (int64_t)kBucketSlots, eps, (unsigned long long*)d_counters);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -338,15 +246,18 @@ struct BucketSmem {
 //     neighbouring tiles while any tile boundary is out of order (keys only
 //     move as far as f misplaced them); a bitonic sort if that does not settle.
 __global__ void __launch_bounds__(kBucketThreads) k_bucket_polish(
-    const uint32_t* __restrict__ cnt_arr, const uint64_t* __restrict__ moff,
-    const RegionEntry* __restrict__ region, int eps, void* M, int M_is_bits, int is_f64, uint64_t* segmin,
-    uint64_t* segmax, unsigned long long* counters) {
+    const uint32_t* __restrict__ cnt_arr, const int64_t* __restrict__ start, const uint64_t* __restrict__ moff,
+    const uint64_t* __restrict__ K, const uint32_t* __restrict__ Sl, int eps, void* M, int M_is_bits, int is_f64,
+    uint64_t* segmin, uint64_t* segmax, unsigned long long* counters) {
     __shared__ BucketSmem sm;
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
     const uint32_t cnt = cnt_arr[b];
     if (cnt == 0 || cnt > kBucketCap) return;  // empty, or handled by the dense-range path
-    const RegionEntry* reg = region + (size_t)b * kBucketCap;
+    // the range's keys, in input order (the partition is stable): position e
+    // in the range is the processing order used for first arrival
+    const uint64_t* rk = K + start[b];
+    const uint32_t* rs = Sl + start[b];
 
     uint64_t key[kItems];
     uint32_t idx[kItems];
@@ -360,10 +271,9 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket_polish(
         idx[k] = 0;
         lsl[k] = 0;
         if (e < cnt) {
-            RegionEntry r = reg[e];
-            key[k] = r.okey;
-            idx[k] = (uint32_t)(r.meta >> 32);
-            lsl[k] = (uint32_t)(r.meta & (kBucketSlots - 1));
+            key[k] = rk[e];
+            idx[k] = e;
+            lsl[k] = rs[e] & (kBucketSlots - 1);
         }
     }
     for (int i = tid; i < (int)kBucketSlots; i += kBucketThreads) sm.off[i] = 0;
@@ -512,12 +422,13 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket_polish(
     }
 }
 
-hipError_t launch_bucket_polish(const uint32_t* d_cnt, const uint64_t* d_moff, int64_t NB,
-                                const RegionEntry* d_region, int eps, void* d_M, bool M_is_bits, bool is_f64,
-                                uint64_t* d_segmin, uint64_t* d_segmax, uint64_t* d_counters, hipStream_t st) {
+hipError_t launch_bucket_polish(const uint32_t* d_cnt, const int64_t* d_start, const uint64_t* d_moff, int64_t NB,
+                                const uint64_t* d_K, const uint32_t* d_S, int eps, void* d_M, bool M_is_bits,
+                                bool is_f64, uint64_t* d_segmin, uint64_t* d_segmax, uint64_t* d_counters,
+                                hipStream_t st) {
     if (NB <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bucket_polish, dim3((unsigned)NB), dim3(kBucketThreads), 0, st, d_cnt, d_moff, d_region,
-                       eps, d_M, M_is_bits ? 1 : 0, is_f64 ? 1 : 0, d_segmin, d_segmax,
+    hipLaunchKernelGGL(k_bucket_polish, dim3((unsigned)NB), dim3(kBucketThreads), 0, st, d_cnt, d_start, d_moff, d_K,
+                       d_S, eps, d_M, M_is_bits ? 1 : 0, is_f64 ? 1 : 0, d_segmin, d_segmax,
                        (unsigned long long*)d_counters);
     return hipGetLastError();
 }

@@ -1,6 +1,6 @@
 // Input and sorting phases' map (Sec. 2, Procedure NN-sort): translate each
-// key, evaluate the learned model f, round F * m * n to a slot, and hand the
-// key to the bucket region of its slot range (or to the spill list).
+// key, evaluate the learned model f and round F * m * n to a slot.  The keys
+// themselves move in the partition by slot range that follows.
 //
 // FP32 form: one thread per key, weights read as wave-uniform scalars, the
 // operation order fixed exactly as below so that the slot can be reproduced
@@ -46,49 +46,21 @@ __device__ __forceinline__ double model_fp32(const DevModel* __restrict__ m, dou
 
 template <int H>
 __global__ void __launch_bounds__(256) k_infer_fp32(InferArgs a) {
-    __shared__ SpillEntry s_stage[4][kSpillStage];
-    WaveSpill w{s_stage[threadIdx.x >> 6], 0, 0};
     const DevModel* __restrict__ m = a.model;
     const double lo = m->lo, inv = m->inv_range;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < a.n; base += stride) {
-        int64_t i = base + threadIdx.x;
-        bool active = i < a.n;
-        uint64_t bits = active ? a.in[i] : 0;
-        uint64_t okey = order_key(bits, a.is_f64);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+        const uint64_t bits = a.in[i];
         uint32_t slot = kUnmapped;
         double F = __longlong_as_double(0x7FF8000000000000ll);
-        if (active) {
-            double x;
-            if (translate_key(bits, a.is_f64, lo, inv, &x)) {
-                F = model_fp32<H>(m, x);
-                slot = slot_of(F, a.M);
-            }
-            if (a.slots_out) a.slots_out[i] = slot;
-            if (a.F_out) a.F_out[i] = F;
+        double x;
+        if (translate_key(bits, a.is_f64, lo, inv, &x)) {
+            F = model_fp32<H>(m, x);
+            slot = slot_of(F, a.M);
         }
-        place_key(a, i, active, okey, slot, w);
+        if (a.slots_out) a.slots_out[i] = slot;
+        if (a.F_out) a.F_out[i] = F;
     }
-    spill_finish(w, a);
-}
-
-// Caller-given slots (closed-form models in tests): no inference.
-__global__ void __launch_bounds__(256) k_place_given(InferArgs a) {
-    __shared__ SpillEntry s_stage[4][kSpillStage];
-    WaveSpill w{s_stage[threadIdx.x >> 6], 0, 0};
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < a.n; base += stride) {
-        int64_t i = base + threadIdx.x;
-        bool active = i < a.n;
-        uint64_t bits = active ? a.in[i] : 0;
-        uint64_t okey = order_key(bits, a.is_f64);
-        uint32_t slot = active ? a.given_slots[i] : kUnmapped;
-        bool bad = active && slot != kUnmapped && (int64_t)slot >= a.S;
-        count_aggregate(bad, &a.counters[kCntBadSlot]);
-        if (bad) slot = kUnmapped;
-        place_key(a, i, active, okey, slot, w);
-    }
-    spill_finish(w, a);
 }
 
 // Sum over sorted positions p of |F_p n - p| for mappable keys (F not NaN):
@@ -142,10 +114,6 @@ static int grid_for(int64_t n, int threads, int max_blocks) {
 
 hipError_t launch_infer(const InferArgs& a, int H, int form, int bf16_terms, hipStream_t st) {
     if (a.n <= 0) return hipSuccess;
-    if (a.given_slots) {
-        hipLaunchKernelGGL(k_place_given, dim3(grid_for(a.n, 256, 65536)), dim3(256), 0, st, a);
-        return hipGetLastError();
-    }
     if (form == NNSORT_FORM_BF16) return launch_bf16_infer(a, H, bf16_terms, st);
     int grid = grid_for(a.n, 256, 256 * 64);
     if (H == 32)

@@ -45,8 +45,6 @@ __global__ void __launch_bounds__(256) k_infer_bf16(InferArgs a) {
     constexpr int KS = H / 16;  // k-steps of 16 hidden-1 units
     const DevModel* __restrict__ m = a.model;
     __shared__ float s_w1[64], s_b1[64];
-    __shared__ SpillEntry s_stage[4][kSpillStage];
-    WaveSpill wsp{s_stage[threadIdx.x >> 6], 0, 0};
     for (int i = threadIdx.x; i < H; i += blockDim.x) {
         s_w1[i] = m->w1[i];
         s_b1[i] = m->b1[i];
@@ -86,7 +84,6 @@ __global__ void __launch_bounds__(256) k_infer_bf16(InferArgs a) {
         const int64_t i = tile * 32 + j;
         const bool active = i < a.n;
         const uint64_t bits = active ? a.in[i] : 0;
-        const uint64_t okey = order_key(bits, a.is_f64);
         double x = 0.0;
         const bool mapped = active && translate_key(bits, a.is_f64, lo, inv, &x);
         const float xh = (float)x;
@@ -161,9 +158,7 @@ __global__ void __launch_bounds__(256) k_infer_bf16(InferArgs a) {
             if (a.slots_out) a.slots_out[i] = slot;
             if (a.F_out) a.F_out[i] = mapped ? F : __longlong_as_double(0x7FF8000000000000ll);
         }
-        place_key(a, i, mine, okey, slot, wsp);
     }
-    spill_finish(wsp, a);
 }
 
 hipError_t launch_bf16_infer(const InferArgs& a, int H, int bf16_terms, hipStream_t st) {

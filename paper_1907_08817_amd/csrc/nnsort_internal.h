@@ -11,9 +11,9 @@ namespace nns {
 constexpr uint32_t kUnmapped = 0xFFFFFFFFu;
 
 // Slot-range buckets: the sorting phase's slot array o_i is cut into ranges of
-// kBucketSlots consecutive slots; the keys predicted into one range are
-// gathered into a fixed-capacity region of kBucketCap entries so that one
-// workgroup can run every round and the polish of that range in LDS.
+// kBucketSlots consecutive slots; the keys predicted into one range are made
+// contiguous by a stable partition, and a range of at most kBucketCap keys is
+// handled by one workgroup that runs every round and the polish in LDS.
 constexpr int kLogBucketSlots = 11;
 constexpr uint32_t kBucketSlots = 1u << kLogBucketSlots;
 constexpr uint32_t kBucketCap = 4096;
@@ -22,11 +22,11 @@ constexpr int kItemsPerThread = kBucketCap / kBucketThreads;  // 16
 
 // Counters kept in the workspace (uint64 each).
 enum Counter : int {
-    kCntSpill = 0,        // entries in the spill list
+    kCntReserved0 = 0,
     kCntUnmapped = 1,     // keys with no slot
     kCntCollided = 2,     // [2, 2 + 8): |c_r| for r = 1..8 (all buckets)
     kCntPlaced = 10,      // [10, 18): keys stored in o_r
-    kCntBigKeys = 18,     // region entries of big buckets (kBucketCap each)
+    kCntBigKeys = 18,     // keys of big buckets
     kCntBigBuckets = 19,
     kCntGlobal = 20,      // entries in the global residue list G
     kCntBoundary = 21,    // keys inside boundary fix-up zones
@@ -36,20 +36,6 @@ enum Counter : int {
     kCntPosErrSum = 25,   // double bits: sum |F n - p|
     kCntPosErrCnt = 26,
     kNumCounters = 32
-};
-
-// A key handed to its slot range's region: order key and (input index << 32 |
-// slot within the range), stored together as one 16-byte write.
-struct RegionEntry {
-    uint64_t okey;
-    uint64_t meta;
-};
-
-// A spill entry: a key whose bucket region was full, or that has no slot.
-struct SpillEntry {
-    uint64_t okey;
-    uint32_t idx;
-    uint32_t slot;
 };
 
 // IEEE 754-2019 totalOrder as an unsigned 64-bit key (identity for uint64).
@@ -83,8 +69,8 @@ struct SortPlan {
     int64_t S;         // slots
     int64_t NB;        // buckets
     int64_t big_max;   // capacity for big buckets' slot histograms
-    size_t off_counters, off_cnt, off_region, off_spill, off_bucket_info,
-        off_segminmax, off_G, off_radix, off_M, off_big_hist, off_model, off_bigmap, total;
+    size_t off_counters, off_cnt, off_start, off_slots0, off_S0, off_K0, off_K1, off_phist, off_psums,
+        off_bucket_info, off_bigpref, off_segminmax, off_G, off_radix, off_M, off_big_hist, off_model, total;
     size_t radix_bytes;
 };
 
@@ -99,14 +85,8 @@ struct InferArgs {
     int is_f64;
     double M;
     int64_t S;
-    const uint32_t* given_slots;  // non-null: use these slots, no inference
-    uint32_t* slots_out;          // optional per-key slot
-    double* F_out;                // optional per-key F
-    int scatter;                  // 1: hand keys to bucket regions / spill
-    uint32_t* cnt;
-    RegionEntry* region;
-    SpillEntry* spill;
-    unsigned long long* counters;
+    uint32_t* slots_out;  // optional per-key slot
+    double* F_out;        // optional per-key F
 };
 
 // H is the padded model width (32 or 64).

@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(256) k_scan_add(uint32_t* data, int64_t len, c
         if (base + k < len) data[base + k] += add;
 }
 
-static hipError_t exclusive_scan_u32(uint32_t* data, int64_t len, uint32_t* sums, hipStream_t st) {
+hipError_t exclusive_scan_u32(uint32_t* data, int64_t len, uint32_t* sums, hipStream_t st) {
     int64_t chunks = (len + kScanChunk - 1) / kScanChunk;
     hipLaunchKernelGGL(k_scan_chunks, dim3((unsigned)chunks), dim3(256), 0, st, data, len, sums);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, sums, chunks);
