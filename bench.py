@@ -225,7 +225,7 @@ def main():
         "collided_frac": [round(v / n, 5) for v in c],
         "residue_frac": round(ct / n, 5),
         "boundary_keys": stats["boundary_keys"],
-        "fallback": stats["fallback"],
+        "fallback": stats["fallback"], "range_resorts": stats["range_resorts"],
         "big_bucket_keys": stats["big_bucket_keys"],
         "phase_ms": {k: round(stats[k], 3) for k in ("t_infer_ms", "t_place_ms", "t_polish_ms",
                                                        "t_residue_ms", "t_merge_ms", "t_total_ms")},

@@ -139,7 +139,8 @@ typedef struct {
     int64_t big_bucket_keys; /* keys sorted by the radix path for that reason */
     int64_t boundary_keys;   /* keys moved by the tile-boundary fix-up */
     int32_t fallback;        /* 1 if the tile fix-up fell back to a full sort */
-    int32_t reserved;
+    int32_t range_resorts;   /* slot ranges whose neighbour-tile merges did not
+                                settle and were re-sorted whole in LDS */
     double pos_err;          /* stats_level 2: mean |F(key) n - rank| / n */
     double t_infer_ms, t_place_ms, t_polish_ms, t_residue_ms, t_merge_ms, t_total_ms;
 } nnsort_stats;

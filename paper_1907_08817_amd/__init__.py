@@ -59,7 +59,7 @@ class Stats(ctypes.Structure):
                 ("collided", ctypes.c_int64 * MAX_EPS), ("placed", ctypes.c_int64 * MAX_EPS),
                 ("residue", ctypes.c_int64), ("unmapped", ctypes.c_int64), ("big_buckets", ctypes.c_int64),
                 ("big_bucket_keys", ctypes.c_int64), ("boundary_keys", ctypes.c_int64),
-                ("fallback", ctypes.c_int32), ("reserved", ctypes.c_int32), ("pos_err", ctypes.c_double),
+                ("fallback", ctypes.c_int32), ("range_resorts", ctypes.c_int32), ("pos_err", ctypes.c_double),
                 ("t_infer_ms", ctypes.c_double), ("t_place_ms", ctypes.c_double),
                 ("t_polish_ms", ctypes.c_double), ("t_residue_ms", ctypes.c_double),
                 ("t_merge_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
@@ -182,7 +182,7 @@ def stats_to_dict(s: Stats) -> dict:
     return {"n": s.n, "rounds": t, "form": s.form, "collided": list(s.collided)[:t],
             "placed": list(s.placed)[:t], "residue": s.residue, "unmapped": s.unmapped,
             "big_buckets": s.big_buckets, "big_bucket_keys": s.big_bucket_keys,
-            "boundary_keys": s.boundary_keys, "fallback": s.fallback, "pos_err": s.pos_err,
+            "boundary_keys": s.boundary_keys, "fallback": s.fallback, "range_resorts": s.range_resorts, "pos_err": s.pos_err,
             "t_infer_ms": s.t_infer_ms, "t_place_ms": s.t_place_ms, "t_polish_ms": s.t_polish_ms,
             "t_residue_ms": s.t_residue_ms, "t_merge_ms": s.t_merge_ms, "t_total_ms": s.t_total_ms}
 

@@ -15,15 +15,19 @@ namespace nns {
 // launchers defined in the .hip translation units
 hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
-hipError_t launch_classify(const uint32_t* d_cnt, int64_t NB, int64_t big_max, int32_t* d_bigmap,
-                           uint64_t* d_moff, int32_t* d_seglist, int32_t* d_bigbucket,
-                           uint64_t* d_counters, hipStream_t st);
+hipError_t launch_classify(const uint32_t* d_cnt, int64_t NB, int64_t big_max, int32_t* d_seglist,
+                           int32_t* d_bigbucket, uint64_t* d_counters, hipStream_t st);
 hipError_t launch_big_counts(const uint32_t* d_hist, int64_t big_count, int eps, uint64_t* d_counters,
                              hipStream_t st);
-hipError_t launch_bucket_polish(const uint32_t* d_cnt, const int64_t* d_start, const uint64_t* d_moff, int64_t NB,
-                                const uint64_t* d_K, const uint32_t* d_S, int eps, void* d_M, bool M_is_bits,
-                                bool is_f64, uint64_t* d_segmin, uint64_t* d_segmax, uint64_t* d_counters,
+size_t polish_part_words(int64_t NB);
+hipError_t launch_bucket_polish(const uint32_t* d_cnt, const int64_t* d_start, int64_t NB, const uint64_t* d_K,
+                                const uint32_t* d_S, int eps, uint64_t* d_out, int64_t base, bool is_f64,
+                                uint32_t* d_part, uint64_t* d_counters, hipStream_t st);
+hipError_t launch_boundary_plan(const uint64_t* d_out, bool is_f64, int64_t base, const int64_t* d_start,
+                                const int32_t* d_seglist, int64_t K, void* d_zones, uint64_t* d_counters,
                                 hipStream_t st);
+hipError_t launch_boundary_merge(uint64_t* d_out, bool is_f64, const void* d_zones, int64_t K, hipStream_t st);
+size_t zone_bytes();
 size_t partition_hist_words(int64_t n);
 hipError_t partition_by_range(const uint64_t* in_keys, const uint32_t* in_slots, int64_t n, uint32_t NB, bool is_f64,
                               uint64_t* K0, uint32_t* S0, uint64_t* K1, uint32_t* S1, uint32_t* blockhist,
@@ -37,14 +41,12 @@ hipError_t launch_big_gather(const int32_t* d_bigbucket, int64_t big_count, int6
                              const int64_t* d_chunk_pref, const int64_t* d_gpref, const int64_t* d_start,
                              const uint64_t* d_K, const uint32_t* d_S, uint32_t* d_hist, uint64_t* d_G,
                              hipStream_t st);
+hipError_t launch_big_place(const int32_t* d_bigbucket, int64_t big_count, int64_t nchunks,
+                            const int64_t* d_chunk_pref, const int64_t* d_gpref, const int64_t* d_start,
+                            const uint64_t* d_Gs, int64_t u_neg, uint64_t* d_out, bool is_f64, hipStream_t st);
+hipError_t launch_count_neg(const uint64_t* d_K, const int64_t* d_start, uint32_t NB, int64_t n, uint64_t* d_count,
+                            hipStream_t st);
 hipError_t launch_copy_u64(const uint64_t* d_in, uint64_t* d_out, int64_t n, hipStream_t st);
-hipError_t launch_boundary_plan(const void* d_M, bool M_is_bits, bool is_f64, const uint64_t* d_moff,
-                                const uint32_t* d_cnt, const int32_t* d_seglist, int64_t K,
-                                const uint64_t* d_segmin, const uint64_t* d_segmax, void* d_zones,
-                                uint64_t* d_counters, hipStream_t st);
-hipError_t launch_boundary_merge(void* d_M, bool M_is_bits, bool is_f64, const void* d_zones, int64_t K,
-                                 hipStream_t st);
-size_t zone_bytes();
 hipError_t launch_pos_err_sum(const double* d_F, int64_t n, double* d_sum, hipStream_t st);
 // fit
 hipError_t launch_sample(const void* d_in, int64_t n, bool is_f64, uint64_t seed, int64_t k, uint64_t* d_out,
@@ -156,12 +158,12 @@ SortPlan plan_sort(int64_t n, double m) {
     size_t ph = partition_hist_words(n);
     p.off_phist = take(ph * 4);
     p.off_psums = take(((ph + 2047) / 2048 + 1) * 4);
-    p.off_bucket_info = take(align256((size_t)p.NB * 4) + align256((size_t)p.NB * 8) +
-                             align256((size_t)p.NB * 4) + (size_t)p.big_max * 4);
+    p.off_seglist = take((size_t)p.NB * 4);
+    p.off_bigbucket = take((size_t)p.big_max * 4);
     p.off_bigpref = take((size_t)(p.big_max + 1) * 2 * 8);
-    p.off_segminmax = take((size_t)p.NB * 16 + (size_t)p.NB * zone_bytes());
+    p.off_part = take(polish_part_words(p.NB) * 4);
+    p.off_zones = take((size_t)p.NB * zone_bytes());
     p.off_G = take(nn * 8);
-    p.off_M = take(nn * 8);
     p.off_big_hist = take((size_t)p.big_max * kBucketSlots * 4);
     p.off_model = take(sizeof(DevModel));
     p.radix_bytes = radix_ws_bytes(n);
@@ -258,22 +260,17 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     uint64_t* K1 = (uint64_t*)(ws + P.off_K1);
     uint32_t* phist = (uint32_t*)(ws + P.off_phist);
     uint32_t* psums = (uint32_t*)(ws + P.off_psums);
-    int32_t* bigmap = (int32_t*)(ws + P.off_bucket_info);
-    uint64_t* moff = (uint64_t*)(ws + P.off_bucket_info + align256((size_t)P.NB * 4));
-    int32_t* seglist = (int32_t*)((char*)moff + align256((size_t)P.NB * 8));
-    int32_t* bigbucket = (int32_t*)((char*)seglist + align256((size_t)P.NB * 4));
+    int32_t* seglist = (int32_t*)(ws + P.off_seglist);
+    int32_t* bigbucket = (int32_t*)(ws + P.off_bigbucket);
     int64_t* chunk_pref = (int64_t*)(ws + P.off_bigpref);
     int64_t* gpref = chunk_pref + (P.big_max + 1);
-    uint64_t* segmin = (uint64_t*)(ws + P.off_segminmax);
-    uint64_t* segmax = segmin + P.NB;
-    void* zones = (void*)(segmax + P.NB);
+    uint32_t* part = (uint32_t*)(ws + P.off_part);
+    void* zones = ws + P.off_zones;
     uint64_t* G = (uint64_t*)(ws + P.off_G);
-    uint64_t* Mbuf = (uint64_t*)(ws + P.off_M);
     uint32_t* big_hist = (uint32_t*)(ws + P.off_big_hist);
     DevModel* dmodel = (DevModel*)(ws + P.off_model);
     void* radix_ws = ws + P.off_radix;
-    // the bucket_info carve-up must fit its reservation
-    if ((char*)(bigbucket + P.big_max) > ws + P.off_bigpref) return NNSORT_EINTERNAL;
+    uint64_t* out = (uint64_t*)d_out;
 
     NNS_HIP(fill_u64(counters, kNumCounters, 0, st));
     DevModel hm;
@@ -311,7 +308,8 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     const uint64_t* Ks = which ? K1 : K0;
     const uint32_t* Ss = which ? slots0 : S0;
     NNS_HIP(launch_range_bounds(Ss, n, NB, start, cnt, st));
-    NNS_HIP(launch_classify(cnt, P.NB, P.big_max, bigmap, moff, seglist, bigbucket, counters, st));
+    NNS_HIP(launch_classify(cnt, P.NB, P.big_max, seglist, bigbucket, counters, st));
+    NNS_HIP(launch_count_neg(Ks, start, NB, n, counters + kCntUnmappedNeg, st));
     uint64_t c[kNumCounters];
     int64_t first_unmapped = 0;
     NNS_HIP(hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, st));
@@ -320,16 +318,17 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     if (c[kCntBadSlot]) return NNSORT_EINVAL;
     const int64_t big_count = (int64_t)c[kCntBigBuckets];
     const int64_t big_keys = (int64_t)c[kCntBigKeys];
+    const int64_t nseg = (int64_t)c[kCntSegments];
     const int64_t unm = n - first_unmapped;
+    const int64_t u_neg = (int64_t)c[kCntUnmappedNeg];
     // G: the keys of ranges too dense for LDS, then the keys without a slot
     const int64_t G_size = big_keys + unm;
     if (big_count > P.big_max) return NNSORT_EINTERNAL;
 
-    // ---- dense ranges and keys without a slot: to G ----
+    int64_t nchunks = 0;
     if (big_count > 0) {
         NNS_HIP(fill_u32(big_hist, big_count * (int64_t)kBucketSlots, 0u, st));
         NNS_HIP(launch_big_chunks(bigbucket, big_count, start, chunk_pref, gpref, st));
-        int64_t nchunks = 0;
         NNS_HIP(hipMemcpyAsync(&nchunks, chunk_pref + big_count, 8, hipMemcpyDeviceToHost, st));
         NNS_HIP(hipStreamSynchronize(st));
         NNS_HIP(launch_big_gather(bigbucket, big_count, nchunks, chunk_pref, gpref, start, Ks, Ss, big_hist, G, st));
@@ -338,32 +337,32 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     if (unm > 0) NNS_HIP(launch_copy_u64(Ks + first_unmapped, G + big_keys, unm, st));
     ev.mark(2);
 
-    // ---- rounds + polish of each slot range in LDS ----
-    const bool M_is_bits = G_size == 0;
-    void* M = M_is_bits ? d_out : (void*)Mbuf;
-    const int64_t M_len = n - G_size;
-    NNS_HIP(launch_bucket_polish(cnt, start, moff, P.NB, Ks, Ss, eps, M, M_is_bits, is_f64, segmin, segmax,
-                                 counters, st));
-    const int64_t K = (int64_t)c[kCntSmallBuckets];
-    NNS_HIP(launch_boundary_plan(M, M_is_bits, is_f64, moff, cnt, seglist, K, segmin, segmax, zones, counters,
+    // ---- rounds + polish of each slot range in LDS, straight to out ----
+    NNS_HIP(launch_bucket_polish(cnt, start, P.NB, Ks, Ss, eps, out, u_neg, is_f64, part, counters, st));
+    ev.mark(3);
+
+    // ---- dense ranges and keys without a slot: conventional sort, placed ----
+    if (G_size > 0) {
+        NNS_HIP(radix_sort(G, G, G_size, 0, 0, radix_ws, P.radix_bytes, st));
+        NNS_HIP(launch_big_place(bigbucket, big_count, nchunks, chunk_pref, gpref, start, G, u_neg, out, is_f64,
                                  st));
+        if (u_neg > 0) NNS_HIP(launch_convert(G, out, u_neg, 0, is_f64 ? 1 : 2, st));
+        const int64_t u_pos = unm - u_neg;
+        if (u_pos > 0) NNS_HIP(launch_convert(G + G_size - u_pos, out + n - u_pos, u_pos, 0, is_f64 ? 1 : 2, st));
+    }
+    ev.mark(4);
+
+    // ---- boundaries between neighbouring ranges ----
+    NNS_HIP(launch_boundary_plan(out, is_f64, u_neg, start, seglist, nseg, zones, counters, st));
     NNS_HIP(hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, st));
     NNS_HIP(hipStreamSynchronize(st));
     if (c[kCntFallback]) {
-        const int mode = M_is_bits ? (is_f64 ? 1 : 2) : 0;
-        if (P.radix_bytes < radix_ws_bytes(M_len)) return NNSORT_EINTERNAL;
-        NNS_HIP(radix_sort((const uint64_t*)M, (uint64_t*)M, M_len, mode, mode, radix_ws, P.radix_bytes, st));
+        const int mode = is_f64 ? 1 : 2;
+        const int64_t len = first_unmapped;
+        if (P.radix_bytes < radix_ws_bytes(len)) return NNSORT_EINTERNAL;
+        NNS_HIP(radix_sort(out + u_neg, out + u_neg, len, mode, mode, radix_ws, P.radix_bytes, st));
     } else {
-        NNS_HIP(launch_boundary_merge(M, M_is_bits, is_f64, zones, K, st));
-    }
-    ev.mark(3);
-    // ---- last conflict array (and dense ranges): conventional sort, merge ----
-    if (G_size > 0) {
-        NNS_HIP(radix_sort(G, G, G_size, 0, 0, radix_ws, P.radix_bytes, st));
-        ev.mark(4);
-        NNS_HIP(launch_merge(Mbuf, M_len, G, G_size, (uint64_t*)d_out, is_f64 ? 1 : 2, st));
-    } else {
-        ev.mark(4);
+        NNS_HIP(launch_boundary_merge(out, is_f64, zones, nseg, st));
     }
     ev.mark(5);
 
@@ -385,6 +384,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     S.big_bucket_keys = big_keys;
     S.boundary_keys = (int64_t)c[kCntBoundary];
     S.fallback = c[kCntFallback] ? 1 : 0;
+    S.range_resorts = (int32_t)c[kCntResorted];
     if (stats && prm->stats_level >= 2 && model) {
         double* Fbuf = (double*)K1;  // partition storage is free now
         InferArgs pa = ia;
@@ -408,7 +408,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
         S.t_place_ms = ev.ms(1, 2);
         S.t_polish_ms = ev.ms(2, 3);
         S.t_residue_ms = ev.ms(3, 4);
-        S.t_merge_ms = ev.ms(4, 5);
+        S.t_merge_ms = ev.ms(4, 5);  // the boundary check and repair
         S.t_total_ms = ev.ms(0, 5);
     }
     if (stats) *stats = S;

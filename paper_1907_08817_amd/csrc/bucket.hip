@@ -1,19 +1,30 @@
-// Sorting and polish phases on slot-range buckets (Sec. 2, Procedure NN-sort
-// and polish).
+// Sorting and polish phases on slot ranges (Sec. 2, Procedure NN-sort and
+// polish).
 //
-// Every round of the sorting phase stores, for each slot, the first key (in
-// processing order) that maps to it; the rest go to the conflict array and are
-// mapped again.  Since f is fixed, a key keeps its slot in every round, so a
-// slot's keys never interact with another slot's: the rounds of the keys of
-// one slot range can run on their own.  k_bucket_polish runs all rounds of one
-// range in LDS (first arrival = smallest input index, decided with LDS
-// atomic-min), lays the arrays o_r out slot by slot (o_1, o_2, ... then the
-// range's part of the last conflict array), and polishes that nearly sorted
-// sequence in LDS: sorting networks on 8-key tiles, then merges of
-// neighbouring tiles only while a tile boundary is out of order.
-// Adjacent ranges can overlap in key order where f is not monotone or jitters;
-// k_boundary_* repairs each such overlap with an in-place merge, and reports a
-// fallback when the overlap is not confined to neighbours.
+// Every round of the sorting phase stores, for each slot, the first key to
+// arrive there; the rest go to the conflict array and are mapped again.  f is
+// fixed, so a key keeps its slot in every round: the keys of one slot never
+// interact with another slot's, and the rounds of one slot range can run on
+// their own.  k_bucket_polish takes one range (at most kBucketCap keys) into
+// LDS and:
+//  - counts the keys of each slot with LDS atomics; the value an atomic
+//    returns is the key's arrival rank in its slot, so rank r - 1 < eps is
+//    the key stored by round r (o_r), and ranks >= eps form the slot's share
+//    of the last conflict array.  Round counts follow from the multiplicities
+//    k_s: round r stores #{s : k_s >= r} keys and leaves sum_s max(0, k_s - r);
+//  - lays the range out slot by slot (o_1 .. o_eps entries, then the residue
+//    of each slot) and orders each slot's few keys: this merges the arrays o_r
+//    and the residue slot by slot, and is the final order wherever f is
+//    monotone;
+//  - checks for descents, which appear only where f's rounding jitters
+//    between neighbouring slots; such a range is repaired by merges of
+//    neighbouring 8-key tiles, or re-sorted whole.
+// The output position of every range is known from the partition, so each
+// range writes its keys straight to their final place.  Ranges too dense for
+// LDS and keys with no slot go to a conventional radix sort (the residue
+// path).  k_boundary_* then checks every pair of neighbouring ranges and
+// repairs overlaps (where f is not monotone across a range boundary) with an
+// in-place merge, or reports a fallback to a full sort.
 #include "nnsort_internal.h"
 
 namespace nns {
@@ -48,92 +59,68 @@ hipError_t fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st) {
     return hipGetLastError();
 }
 
-__device__ __forceinline__ uint64_t load_key(const void* M, bool M_is_bits, bool is_f64, int64_t i) {
-    uint64_t v = ((const uint64_t*)M)[i];
-    return M_is_bits ? order_key(v, is_f64) : v;
-}
-__device__ __forceinline__ void store_key(void* M, bool M_is_bits, bool is_f64, int64_t i, uint64_t k) {
-    ((uint64_t*)M)[i] = M_is_bits ? order_key_inverse(k, is_f64) : k;
-}
-
 // ---------------------------------------------------------------------------
-// classify: small / big buckets, offsets of small segments, segment list
+// classify: non-empty ranges in order, and the ranges too dense for LDS
 // ---------------------------------------------------------------------------
-// Single workgroup; each thread owns a contiguous chunk of buckets.
-// bucket_info layout (int64 each): bigmap[NB] (id of big bucket or -1),
-// moff[NB] (offset of the segment in M), seglist[NB] (non-empty small buckets
-// in order), bigbucket[big_max] (bucket of big id).
+// Single workgroup; each thread owns a contiguous chunk of ranges.
 __global__ void __launch_bounds__(1024) k_classify(const uint32_t* __restrict__ cnt, int64_t NB,
-                                                   int64_t big_max, int32_t* bigmap, uint64_t* moff,
-                                                   int32_t* seglist, int32_t* bigbucket,
+                                                   int64_t big_max, int32_t* seglist, int32_t* bigbucket,
                                                    unsigned long long* counters) {
-    __shared__ unsigned long long s_small[1024], s_big[1024], s_seg[1024], s_bigkeys[1024];
+    __shared__ unsigned long long s_big[1024], s_seg[1024], s_bigkeys[1024];
     int t = threadIdx.x;
     int64_t chunk = (NB + 1023) / 1024;
     int64_t b0 = t * chunk, b1 = b0 + chunk < NB ? b0 + chunk : NB;
-    unsigned long long small = 0, big = 0, seg = 0, bigkeys = 0;
+    unsigned long long big = 0, seg = 0, bigkeys = 0;
     for (int64_t b = b0; b < b1; ++b) {
         uint32_t c = cnt[b];
+        seg += c ? 1 : 0;
         if (c > kBucketCap) {
             ++big;
             bigkeys += c;
-        } else {
-            small += c;
-            seg += c ? 1 : 0;
         }
     }
-    s_small[t] = small;
     s_big[t] = big;
     s_seg[t] = seg;
     s_bigkeys[t] = bigkeys;
     __syncthreads();
     // inclusive Hillis-Steele scans over 1024 entries
     for (int off = 1; off < 1024; off <<= 1) {
-        unsigned long long a = t >= off ? s_small[t - off] : 0;
         unsigned long long c = t >= off ? s_big[t - off] : 0;
         unsigned long long d = t >= off ? s_seg[t - off] : 0;
         unsigned long long e = t >= off ? s_bigkeys[t - off] : 0;
         __syncthreads();
-        s_small[t] += a;
         s_big[t] += c;
         s_seg[t] += d;
         s_bigkeys[t] += e;
         __syncthreads();
     }
-    unsigned long long po = s_small[t] - small, pb = s_big[t] - big, ps = s_seg[t] - seg;
+    unsigned long long pb = s_big[t] - big, ps = s_seg[t] - seg;
     for (int64_t b = b0; b < b1; ++b) {
         uint32_t c = cnt[b];
+        if (c) seglist[ps++] = (int32_t)b;
         if (c > kBucketCap) {
-            bigmap[b] = (int32_t)pb;
             if ((int64_t)pb < big_max) bigbucket[pb] = (int32_t)b;
             ++pb;
-            moff[b] = po;
-        } else {
-            bigmap[b] = -1;
-            moff[b] = po;
-            po += c;
-            if (c) seglist[ps++] = (int32_t)b;
         }
     }
     if (t == 1023) {
         counters[kCntBigBuckets] = s_big[1023];
         counters[kCntBigKeys] = s_bigkeys[1023];
-        counters[kCntSmallBuckets] = s_seg[1023];
+        counters[kCntSegments] = s_seg[1023];
     }
 }
 
-hipError_t launch_classify(const uint32_t* d_cnt, int64_t NB, int64_t big_max, int32_t* d_bigmap,
-                           uint64_t* d_moff, int32_t* d_seglist, int32_t* d_bigbucket,
-                           uint64_t* d_counters, hipStream_t st) {
-    hipLaunchKernelGGL(k_classify, dim3(1), dim3(1024), 0, st, d_cnt, NB, big_max, d_bigmap, d_moff,
-                       d_seglist, d_bigbucket, (unsigned long long*)d_counters);
+hipError_t launch_classify(const uint32_t* d_cnt, int64_t NB, int64_t big_max, int32_t* d_seglist,
+                           int32_t* d_bigbucket, uint64_t* d_counters, hipStream_t st) {
+    hipLaunchKernelGGL(k_classify, dim3(1), dim3(1024), 0, st, d_cnt, NB, big_max, d_seglist, d_bigbucket,
+                       (unsigned long long*)d_counters);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// big buckets: round counts from the slot multiplicities
+// round counts from slot multiplicities
 // ---------------------------------------------------------------------------
-// Round counts of big buckets from slot multiplicities k_s: round r stores
+// Dense ranges: k_s from their slot histograms.  Round r stores
 // min(k_s, r) - min(k_s, r - 1) keys of slot s and leaves max(0, k_s - r).
 __global__ void __launch_bounds__(256) k_big_counts(const uint32_t* __restrict__ hist, int64_t total, int eps,
                                                     unsigned long long* counters) {
@@ -171,12 +158,47 @@ hipError_t launch_big_counts(const uint32_t* d_hist, int64_t big_count, int eps,
     return hipGetLastError();
 }
 
+// Small ranges: each polish workgroup leaves its per-round counts in
+// part[b * kPartStride + r] (stored) and [.. + NNSORT_MAX_EPS + r]
+// (conflict); summed here instead of with contended global atomics.
+constexpr int kPartStride = 2 * NNSORT_MAX_EPS;
+
+__global__ void __launch_bounds__(256) k_sum_parts(const uint32_t* __restrict__ part, const uint32_t* __restrict__ cnt,
+                                                   int64_t NB, int eps, unsigned long long* counters) {
+    __shared__ unsigned long long s_acc[kPartStride];
+    if (threadIdx.x < kPartStride) s_acc[threadIdx.x] = 0;
+    __syncthreads();
+    unsigned long long acc[kPartStride] = {0};
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < NB; b += stride) {
+        uint32_t c = cnt[b];
+        if (c == 0 || c > kBucketCap) continue;
+        for (int r = 0; r < eps; ++r) {
+            acc[r] += part[b * kPartStride + r];
+            acc[NNSORT_MAX_EPS + r] += part[b * kPartStride + NNSORT_MAX_EPS + r];
+        }
+    }
+    for (int r = 0; r < eps; ++r) {
+        if (acc[r]) atomicAdd(&s_acc[r], acc[r]);
+        if (acc[NNSORT_MAX_EPS + r]) atomicAdd(&s_acc[NNSORT_MAX_EPS + r], acc[NNSORT_MAX_EPS + r]);
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)eps) {
+        atomicAdd(&counters[kCntPlaced + threadIdx.x], s_acc[threadIdx.x]);
+        atomicAdd(&counters[kCntCollided + threadIdx.x], s_acc[NNSORT_MAX_EPS + threadIdx.x]);
+    }
+}
+
+size_t polish_part_words(int64_t NB) { return (size_t)NB * kPartStride; }
+
 // ---------------------------------------------------------------------------
-// per-bucket rounds + polish in LDS
+// per-range rounds + polish in LDS
 // ---------------------------------------------------------------------------
-constexpr int kItems = kItemsPerThread;  // region entries per thread (16)
-constexpr int kTile = 8;                 // keys per polish tile
-constexpr int kMaxTileRounds = 8;        // odd-even tile rounds before the bitonic fallback
+constexpr int kItems = kItemsPerThread;  // keys per thread (16)
+constexpr int kTile = 8;                 // keys per repair tile
+constexpr int kMaxTileRounds = 8;        // odd-even tile rounds before the whole-range re-sort
+constexpr int kSlotsPer = kBucketSlots / kBucketThreads;  // slots owned per thread (8)
+constexpr uint32_t kGroupMax = 32;       // larger slot groups are ordered by the whole-range re-sort
 
 __device__ __forceinline__ void cswap(uint64_t& a, uint64_t& b) {
     uint64_t lo = a < b ? a : b;
@@ -226,134 +248,25 @@ __device__ __forceinline__ int merge_split(const uint64_t* a, int na, const uint
 
 struct BucketSmem {
     uint64_t keys[kBucketCap];
-    uint32_t owner[kBucketSlots];  // rounds: first arrival per slot; then residue cursors
-    uint32_t off[kBucketSlots];    // keys per slot, then their exclusive prefix
-    uint32_t wsum[kBucketThreads];
-    unsigned long long red[2 * NNSORT_MAX_EPS];
+    // per slot, 16 bits: its key count, then its first position; slot 2w in
+    // the low half of word w, slot 2w + 1 in the high half
+    uint32_t off[kBucketSlots / 2];
+    uint32_t wsum[kBucketThreads / 64];
+    uint32_t red[2 * NNSORT_MAX_EPS];
     int flag;
 };
 
-// One workgroup per slot range.  Steps, all in LDS:
-//  1. slot multiplicities k_s and the rounds: in round r each slot keeps the
-//     unplaced key with the smallest input index (its r-th arrival);
-//  2. round counts from k_s: round r stores #{s : k_s >= r} keys and leaves
-//     sum_s max(0, k_s - r) in the conflict array;
-//  3. compaction, slot-major: slot s's keys at offset(s), ordered o_1, o_2, ...,
-//     o_eps, then the slot's share of the last conflict array -- the arrays
-//     o_r interleaved slot by slot, which a near-monotone f leaves nearly
-//     sorted;
-//  4. polish: 8-key tiles sorted by a network, then odd-even merges of
-//     neighbouring tiles while any tile boundary is out of order (keys only
-//     move as far as f misplaced them); a bitonic sort if that does not settle.
-__global__ void __launch_bounds__(kBucketThreads) k_bucket_polish(
-    const uint32_t* __restrict__ cnt_arr, const int64_t* __restrict__ start, const uint64_t* __restrict__ moff,
-    const uint64_t* __restrict__ K, const uint32_t* __restrict__ Sl, int eps, void* M, int M_is_bits, int is_f64,
-    uint64_t* segmin, uint64_t* segmax, unsigned long long* counters) {
-    __shared__ BucketSmem sm;
-    const int tid = threadIdx.x;
-    const int64_t b = blockIdx.x;
-    const uint32_t cnt = cnt_arr[b];
-    if (cnt == 0 || cnt > kBucketCap) return;  // empty, or handled by the dense-range path
-    // the range's keys, in input order (the partition is stable): position e
-    // in the range is the processing order used for first arrival
-    const uint64_t* rk = K + start[b];
-    const uint32_t* rs = Sl + start[b];
+__device__ __forceinline__ uint32_t half_of(uint32_t word, uint32_t s) { return (word >> ((s & 1u) * 16u)) & 0xFFFFu; }
 
-    uint64_t key[kItems];
-    uint32_t idx[kItems];
-    uint32_t lsl[kItems];
-    uint8_t rnd[kItems];  // round that stored the key (0 = still in conflict array)
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        uint32_t e = tid + k * kBucketThreads;
-        rnd[k] = 0;
-        key[k] = 0;
-        idx[k] = 0;
-        lsl[k] = 0;
-        if (e < cnt) {
-            key[k] = rk[e];
-            idx[k] = e;
-            lsl[k] = rs[e] & (kBucketSlots - 1);
-        }
-    }
-    for (int i = tid; i < (int)kBucketSlots; i += kBucketThreads) sm.off[i] = 0;
-    if (tid < 2 * NNSORT_MAX_EPS) sm.red[tid] = 0;
-    if (tid == 0) sm.flag = 0;
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kItems; ++k)
-        if (tid + k * kBucketThreads < cnt) atomicAdd(&sm.off[lsl[k]], 1u);
-
-    // ---- 1. rounds ----
-    for (int r = 1; r <= eps; ++r) {
-        for (int i = tid; i < (int)kBucketSlots; i += kBucketThreads) sm.owner[i] = kUnmapped;
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kItems; ++k)
-            if (tid + k * kBucketThreads < cnt && rnd[k] == 0) atomicMin(&sm.owner[lsl[k]], idx[k]);
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kItems; ++k)
-            if (tid + k * kBucketThreads < cnt && rnd[k] == 0 && sm.owner[lsl[k]] == idx[k]) rnd[k] = (uint8_t)r;
-        __syncthreads();
-    }
-
-    // ---- 2. round counts from slot multiplicities; 3a. slot offsets ----
-    constexpr int kSlotsPer = kBucketSlots / kBucketThreads;  // 8
-    uint32_t ks[kSlotsPer], run = 0;
-    {
-        unsigned long long pl[NNSORT_MAX_EPS] = {0}, co[NNSORT_MAX_EPS] = {0};
-#pragma unroll
-        for (int q = 0; q < kSlotsPer; ++q) {
-            ks[q] = sm.off[tid * kSlotsPer + q];
-            run += ks[q];
-            for (int r = 1; r <= eps; ++r) {
-                pl[r - 1] += ks[q] >= (uint32_t)r ? 1u : 0u;
-                co[r - 1] += ks[q] > (uint32_t)r ? ks[q] - r : 0u;
-            }
-        }
-        for (int r = 0; r < eps; ++r) {
-            if (pl[r]) atomicAdd(&sm.red[r], pl[r]);
-            if (co[r]) atomicAdd(&sm.red[NNSORT_MAX_EPS + r], co[r]);
-        }
-        sm.wsum[tid] = run;
-    }
-    for (int i = tid; i < (int)kBucketSlots; i += kBucketThreads) sm.owner[i] = 0;  // residue cursors
-    __syncthreads();
-    if (tid < eps) {
-        atomicAdd(&counters[kCntPlaced + tid], sm.red[tid]);
-        atomicAdd(&counters[kCntCollided + tid], sm.red[NNSORT_MAX_EPS + tid]);
-    }
-    // exclusive scan of the 256 per-thread slot totals (Hillis-Steele in place)
-    for (int o = 1; o < kBucketThreads; o <<= 1) {
-        uint32_t y = tid >= o ? sm.wsum[tid - o] : 0;
-        __syncthreads();
-        sm.wsum[tid] += y;
-        __syncthreads();
-    }
-    {
-        uint32_t base = sm.wsum[tid] - run;
-#pragma unroll
-        for (int q = 0; q < kSlotsPer; ++q) {
-            sm.off[tid * kSlotsPer + q] = base;
-            base += ks[q];
-        }
-    }
-    __syncthreads();
-
-    // ---- 3b. slot-major compaction ----
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        if (tid + k * kBucketThreads >= cnt) continue;
-        uint32_t pos = sm.off[lsl[k]];
-        pos += rnd[k] ? (uint32_t)(rnd[k] - 1) : (uint32_t)eps + atomicAdd(&sm.owner[lsl[k]], 1u);
-        sm.keys[pos] = key[k];
-    }
+// Repair of a range whose slot-ordered layout has descents: sorting networks
+// on 8-key tiles, odd-even merges of neighbouring tiles while any tile
+// boundary is out of order (keys only move as far as f misplaced them), and a
+// bitonic sort of the whole range if that does not settle.  Returns true if
+// the bitonic sort ran.
+__device__ bool repair_range(BucketSmem& sm, uint32_t cnt, int tid) {
     const int ntiles = (int)((cnt + kTile - 1) / kTile);
     for (int i = (int)cnt + tid; i < ntiles * kTile; i += kBucketThreads) sm.keys[i] = ~0ull;
     __syncthreads();
-
-    // ---- 4. polish ----
     for (int t = tid; t < ntiles; t += kBucketThreads) {
         uint64_t v[8];
 #pragma unroll
@@ -363,19 +276,15 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket_polish(
         for (int q = 0; q < 8; ++q) sm.keys[t * 8 + q] = v[q];
     }
     __syncthreads();
-    bool settled = false;
     for (int round = 0; round <= kMaxTileRounds; ++round) {
         int bad = 0;
         for (int t = tid; t + 1 < ntiles; t += kBucketThreads)
             bad |= sm.keys[t * 8 + 7] > sm.keys[t * 8 + 8] ? 1 : 0;
-        if (bad) sm.flag = round + 1;
+        if (bad) sm.flag = round + 2;
         __syncthreads();
         int f = sm.flag;
         __syncthreads();
-        if (f != round + 1) {
-            settled = true;
-            break;
-        }
+        if (f != round + 2) return false;
         if (round == kMaxTileRounds) break;
         const int parity = round & 1;
         for (int p = tid; 2 * p + parity + 1 < ntiles; p += kBucketThreads) {
@@ -389,102 +298,251 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket_polish(
         }
         __syncthreads();
     }
-    if (!settled) {
-        // f is far from monotone inside this range: bitonic sort of the range
-        int npad = 8;
-        while (npad < ntiles * 8) npad <<= 1;
-        for (int i = ntiles * 8 + tid; i < npad; i += kBucketThreads) sm.keys[i] = ~0ull;
-        __syncthreads();
-        for (int kk = 2; kk <= npad; kk <<= 1) {
-            for (int j = kk >> 1; j > 0; j >>= 1) {
-                for (int i = tid; i < npad; i += kBucketThreads) {
-                    int l = i ^ j;
-                    if (l > i) {
-                        uint64_t a = sm.keys[i], c = sm.keys[l];
-                        bool up = (i & kk) == 0;
-                        if ((a > c) == up) {
-                            sm.keys[i] = c;
-                            sm.keys[l] = a;
-                        }
+    // f is far from monotone inside this range: bitonic sort of the range
+    int npad = 8;
+    while (npad < ntiles * 8) npad <<= 1;
+    for (int i = ntiles * 8 + tid; i < npad; i += kBucketThreads) sm.keys[i] = ~0ull;
+    __syncthreads();
+    for (int kk = 2; kk <= npad; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < npad; i += kBucketThreads) {
+                int l = i ^ j;
+                if (l > i) {
+                    uint64_t a = sm.keys[i], c = sm.keys[l];
+                    bool up = (i & kk) == 0;
+                    if ((a > c) == up) {
+                        sm.keys[i] = c;
+                        sm.keys[l] = a;
                     }
                 }
-                __syncthreads();
             }
+            __syncthreads();
         }
     }
-
-    // ---- write the range's sorted keys to its segment of M ----
-    const uint64_t off = moff[b];
-    for (uint32_t i = tid; i < cnt; i += kBucketThreads) store_key(M, M_is_bits, is_f64, off + i, sm.keys[i]);
-    if (tid == 0) {
-        segmin[b] = sm.keys[0];
-        segmax[b] = sm.keys[cnt - 1];
-    }
+    return true;
 }
 
-hipError_t launch_bucket_polish(const uint32_t* d_cnt, const int64_t* d_start, const uint64_t* d_moff, int64_t NB,
-                                const uint64_t* d_K, const uint32_t* d_S, int eps, void* d_M, bool M_is_bits,
-                                bool is_f64, uint64_t* d_segmin, uint64_t* d_segmax, uint64_t* d_counters,
-                                hipStream_t st) {
+// One workgroup per slot range of at most kBucketCap keys.  K / Sl: the
+// range-partitioned order keys and slots (range b at [start[b], start[b+1]));
+// the range's keys are written as bit patterns to out[base + start[b] ...].
+__global__ void __launch_bounds__(kBucketThreads) k_bucket_polish(
+    const int64_t* __restrict__ start, const uint64_t* __restrict__ K, const uint32_t* __restrict__ Sl, int eps,
+    uint64_t* __restrict__ out, int64_t base, int is_f64, uint32_t* __restrict__ part,
+    unsigned long long* counters) {
+    __shared__ BucketSmem sm;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
+    const int64_t b = blockIdx.x;
+    const int64_t s0 = start[b];
+    const uint32_t cnt = (uint32_t)(start[b + 1] - s0);
+    if (cnt == 0 || cnt > kBucketCap) return;  // empty, or handled by the dense-range path
+    const uint64_t* rk = K + s0;
+    const uint32_t* rs = Sl + s0;
+
+    uint64_t key[kItems];
+    uint32_t sl[kItems];
+    uint32_t rank[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        if (k * kBucketThreads >= (int)cnt) break;
+        const uint32_t e = tid + k * kBucketThreads;
+        key[k] = 0;
+        sl[k] = 0;
+        if (e < cnt) {
+            key[k] = rk[e];
+            sl[k] = rs[e] & (kBucketSlots - 1);
+        }
+    }
+    for (int i = tid; i < (int)kBucketSlots / 2; i += kBucketThreads) sm.off[i] = 0;
+    if (tid < 2 * NNSORT_MAX_EPS) sm.red[tid] = 0;
+    if (tid == 0) sm.flag = 0;
+    __syncthreads();
+    // arrival rank of each key in its slot
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        if (k * kBucketThreads >= (int)cnt) break;
+        if (tid + k * kBucketThreads < cnt) {
+            const uint32_t old = atomicAdd(&sm.off[sl[k] >> 1], 1u << ((sl[k] & 1u) * 16u));
+            rank[k] = half_of(old, sl[k]);
+        }
+    }
+    __syncthreads();
+
+    // round counts from the multiplicities; slot offsets (exclusive scan)
+    uint32_t ks[kSlotsPer], run = 0;
+    {
+        uint32_t pl[NNSORT_MAX_EPS] = {0}, co[NNSORT_MAX_EPS] = {0};
+        bool big_group = false;
+#pragma unroll
+        for (int q = 0; q < kSlotsPer / 2; ++q) {
+            const uint32_t w = sm.off[tid * (kSlotsPer / 2) + q];
+            ks[2 * q] = w & 0xFFFFu;
+            ks[2 * q + 1] = w >> 16;
+        }
+#pragma unroll
+        for (int q = 0; q < kSlotsPer; ++q) {
+            run += ks[q];
+            big_group |= ks[q] > kGroupMax;
+#pragma unroll
+            for (int r = 1; r <= NNSORT_MAX_EPS; ++r) {
+                if (r > eps) break;
+                pl[r - 1] += ks[q] >= (uint32_t)r ? 1u : 0u;
+                co[r - 1] += ks[q] > (uint32_t)r ? ks[q] - r : 0u;
+            }
+        }
+        for (int r = 0; r < eps; ++r) {
+            if (pl[r]) atomicAdd(&sm.red[r], pl[r]);
+            if (co[r]) atomicAdd(&sm.red[NNSORT_MAX_EPS + r], co[r]);
+        }
+        if (big_group) sm.flag = 1;
+    }
+    uint32_t inc = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) sm.wsum[wv] = inc;
+    __syncthreads();
+    {
+        uint32_t pos = inc - run;
+        for (int w = 0; w < wv; ++w) pos += sm.wsum[w];
+#pragma unroll
+        for (int q = 0; q < kSlotsPer / 2; ++q) {
+            const uint32_t lo = pos;
+            const uint32_t hi = pos + ks[2 * q];
+            pos = hi + ks[2 * q + 1];
+            sm.off[tid * (kSlotsPer / 2) + q] = lo | (hi << 16);
+        }
+    }
+    if (tid < eps) {
+        part[b * kPartStride + tid] = sm.red[tid];
+        part[b * kPartStride + NNSORT_MAX_EPS + tid] = sm.red[NNSORT_MAX_EPS + tid];
+    }
+    __syncthreads();
+
+    // slot-major layout: a slot's keys at its offset, in arrival order
+    uint32_t g0[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        if (k * kBucketThreads >= (int)cnt) break;
+        if (tid + k * kBucketThreads < cnt) {
+            g0[k] = half_of(sm.off[sl[k] >> 1], sl[k]);
+            sm.keys[g0[k] + rank[k]] = key[k];
+        }
+    }
+    __syncthreads();
+
+    bool need_repair = sm.flag != 0;
+    if (!need_repair) {
+        // a key's place inside its slot: its rank among the slot's keys by
+        // (key, arrival); groups hold about one key on average
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            if (k * kBucketThreads >= (int)cnt) break;
+            if (tid + k * kBucketThreads < cnt) {
+                const uint32_t s = sl[k];
+                const uint32_t g1 = s + 1 < kBucketSlots ? half_of(sm.off[(s + 1) >> 1], s + 1) : cnt;
+                uint32_t pos = g0[k];
+                for (uint32_t j = g0[k]; j < g1; ++j) {
+                    const uint64_t y = sm.keys[j];
+                    pos += (y < key[k] || (y == key[k] && j - g0[k] < rank[k])) ? 1u : 0u;
+                }
+                rank[k] = pos;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            if (k * kBucketThreads >= (int)cnt) break;
+            if (tid + k * kBucketThreads < cnt) sm.keys[rank[k]] = key[k];
+        }
+        __syncthreads();
+        // descents remain only where f's slots jitter between neighbours
+        int bad = 0;
+        for (uint32_t i = tid; i + 1 < cnt; i += kBucketThreads) bad |= sm.keys[i] > sm.keys[i + 1] ? 1 : 0;
+        if (bad) sm.flag = 1;
+        __syncthreads();
+        need_repair = sm.flag != 0;
+    }
+    if (need_repair) {
+        if (repair_range(sm, cnt, tid) && tid == 0) atomicAdd(&counters[kCntResorted], 1ull);
+    }
+
+    // write the range's sorted keys to their final place
+    uint64_t* o = out + base + s0;
+    for (uint32_t i = tid; i < cnt; i += kBucketThreads) o[i] = order_key_inverse(sm.keys[i], is_f64);
+}
+
+hipError_t launch_bucket_polish(const uint32_t* d_cnt, const int64_t* d_start, int64_t NB, const uint64_t* d_K,
+                                const uint32_t* d_S, int eps, uint64_t* d_out, int64_t base, bool is_f64,
+                                uint32_t* d_part, uint64_t* d_counters, hipStream_t st) {
     if (NB <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bucket_polish, dim3((unsigned)NB), dim3(kBucketThreads), 0, st, d_cnt, d_start, d_moff, d_K,
-                       d_S, eps, d_M, M_is_bits ? 1 : 0, is_f64 ? 1 : 0, d_segmin, d_segmax,
+    hipLaunchKernelGGL(k_bucket_polish, dim3((unsigned)NB), dim3(kBucketThreads), 0, st, d_start, d_K, d_S, eps,
+                       d_out, base, is_f64 ? 1 : 0, d_part, (unsigned long long*)d_counters);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(NB, 256, 256)), dim3(256), 0, st, d_part, d_cnt, NB, eps,
                        (unsigned long long*)d_counters);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// boundary fix-up between consecutive segments of M
+// boundaries between neighbouring ranges, in the output
 // ---------------------------------------------------------------------------
-constexpr int kZoneMax = 4096;  // keys a single boundary repair may hold in LDS
+constexpr int kZoneMax = 4096;
 
-// zone[k] for the boundary between segment k and k+1: {start, tail, head}.
 struct Zone {
     uint64_t start;
     uint32_t tail;
     uint32_t head;
 };
 
-// One thread per segment k: checks that overlaps involve neighbours only
-// (max of segment k-1 <= min of segment k+1) and sizes the zone between k and
-// k+1 by binary search in both sorted segments.
-__global__ void __launch_bounds__(256) k_boundary_plan(const void* M, int M_is_bits, int is_f64,
-                                                       const uint64_t* __restrict__ moff,
-                                                       const uint32_t* __restrict__ cnt,
-                                                       const int32_t* __restrict__ seglist, int64_t K,
-                                                       const uint64_t* __restrict__ segmin,
-                                                       const uint64_t* __restrict__ segmax, Zone* zones,
+__device__ __forceinline__ uint64_t out_key(const uint64_t* out, bool is_f64, int64_t i) {
+    return order_key(out[i], is_f64);
+}
+
+// One thread per non-empty range k (in range order; every range is sorted in
+// place at out[base + start[b]]): checks that overlaps involve neighbours
+// only (max of range k-1 <= min of range k+1) and sizes the zone between k
+// and k+1 by binary search in both.
+__global__ void __launch_bounds__(256) k_boundary_plan(const uint64_t* __restrict__ out, int is_f64, int64_t base,
+                                                       const int64_t* __restrict__ start,
+                                                       const int32_t* __restrict__ seglist, int64_t K, Zone* zones,
                                                        unsigned long long* counters) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= K) return;
-    int32_t b = seglist[k];
+    const int32_t b = seglist[k];
+    const int64_t s0 = base + start[b], n0 = start[b + 1] - start[b];
     if (k > 0 && k + 1 < K) {
-        if (segmax[seglist[k - 1]] > segmin[seglist[k + 1]]) atomicAdd(&counters[kCntFallback], 1ull);
+        const int32_t bp = seglist[k - 1], bn = seglist[k + 1];
+        if (out_key(out, is_f64, base + start[bp + 1] - 1) > out_key(out, is_f64, base + start[bn]))
+            atomicAdd(&counters[kCntFallback], 1ull);
     }
     Zone z{0, 0, 0};
     if (k + 1 < K) {
-        int32_t b2 = seglist[k + 1];
-        uint64_t mx = segmax[b], mn = segmin[b2];
+        const int32_t b2 = seglist[k + 1];
+        const int64_t s1 = base + start[b2], n1 = start[b2 + 1] - start[b2];
+        const uint64_t mx = out_key(out, is_f64, s0 + n0 - 1), mn = out_key(out, is_f64, s1);
         if (mx > mn) {
-            // tail: keys of segment k greater than min of k+1
-            int64_t s0 = moff[b], n0 = cnt[b];
+            // tail: keys of range k greater than the min of k+1
             int64_t lo = 0, hi = n0;
             while (lo < hi) {
                 int64_t mid = (lo + hi) >> 1;
-                if (load_key(M, M_is_bits, is_f64, s0 + mid) > mn) hi = mid;
+                if (out_key(out, is_f64, s0 + mid) > mn) hi = mid;
                 else lo = mid + 1;
             }
-            uint32_t tail = (uint32_t)(n0 - lo);
-            // head: keys of segment k+1 less than max of k
-            int64_t s1 = moff[b2], n1 = cnt[b2];
+            const uint32_t tail = (uint32_t)(n0 - lo);
+            // head: keys of range k+1 less than the max of k
             lo = 0;
             hi = n1;
             while (lo < hi) {
                 int64_t mid = (lo + hi) >> 1;
-                if (load_key(M, M_is_bits, is_f64, s1 + mid) < mx) lo = mid + 1;
+                if (out_key(out, is_f64, s1 + mid) < mx) lo = mid + 1;
                 else hi = mid;
             }
-            uint32_t head = (uint32_t)lo;
+            const uint32_t head = (uint32_t)lo;
             z.start = (uint64_t)(s0 + n0 - tail);
             z.tail = tail;
             z.head = head;
@@ -495,16 +553,16 @@ __global__ void __launch_bounds__(256) k_boundary_plan(const void* M, int M_is_b
     zones[k] = z;
 }
 
-// One workgroup per boundary: merge tail and head (adjacent in M) in place.
-__global__ void __launch_bounds__(256) k_boundary_merge(void* M, int M_is_bits, int is_f64,
-                                                        const Zone* __restrict__ zones, int64_t K) {
+// One workgroup per boundary: merge tail and head (adjacent in out) in place.
+__global__ void __launch_bounds__(256) k_boundary_merge(uint64_t* out, int is_f64, const Zone* __restrict__ zones,
+                                                        int64_t K) {
     __shared__ uint64_t buf[kZoneMax];
     int64_t k = blockIdx.x;
     if (k >= K) return;
     Zone z = zones[k];
     int total = (int)(z.tail + z.head);
     if (z.tail == 0 || z.head == 0 || total > kZoneMax) return;
-    for (int i = threadIdx.x; i < total; i += blockDim.x) buf[i] = load_key(M, M_is_bits, is_f64, z.start + i);
+    for (int i = threadIdx.x; i < total; i += blockDim.x) buf[i] = out_key(out, is_f64, z.start + i);
     __syncthreads();
     const uint64_t* a = buf;
     const uint64_t* b = buf + z.tail;
@@ -520,27 +578,24 @@ __global__ void __launch_bounds__(256) k_boundary_merge(void* M, int M_is_bits, 
             uint64_t v = takeA ? a[ia] : b[ib];
             ia += takeA ? 1 : 0;
             ib += takeA ? 0 : 1;
-            store_key(M, M_is_bits, is_f64, z.start + d, v);
+            out[z.start + d] = order_key_inverse(v, is_f64);
         }
     }
 }
 
-hipError_t launch_boundary_plan(const void* d_M, bool M_is_bits, bool is_f64, const uint64_t* d_moff,
-                                const uint32_t* d_cnt, const int32_t* d_seglist, int64_t K,
-                                const uint64_t* d_segmin, const uint64_t* d_segmax, void* d_zones,
-                                uint64_t* d_counters, hipStream_t st) {
+hipError_t launch_boundary_plan(const uint64_t* d_out, bool is_f64, int64_t base, const int64_t* d_start,
+                                const int32_t* d_seglist, int64_t K, void* d_zones, uint64_t* d_counters,
+                                hipStream_t st) {
     if (K <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_boundary_plan, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, d_M,
-                       M_is_bits ? 1 : 0, is_f64 ? 1 : 0, d_moff, d_cnt, d_seglist, K, d_segmin,
-                       d_segmax, (Zone*)d_zones, (unsigned long long*)d_counters);
+    hipLaunchKernelGGL(k_boundary_plan, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, d_out,
+                       is_f64 ? 1 : 0, base, d_start, d_seglist, K, (Zone*)d_zones, (unsigned long long*)d_counters);
     return hipGetLastError();
 }
 
-hipError_t launch_boundary_merge(void* d_M, bool M_is_bits, bool is_f64, const void* d_zones, int64_t K,
-                                 hipStream_t st) {
+hipError_t launch_boundary_merge(uint64_t* d_out, bool is_f64, const void* d_zones, int64_t K, hipStream_t st) {
     if (K <= 1) return hipSuccess;
-    hipLaunchKernelGGL(k_boundary_merge, dim3((unsigned)(K - 1)), dim3(256), 0, st, d_M, M_is_bits ? 1 : 0,
-                       is_f64 ? 1 : 0, (const Zone*)d_zones, K - 1);
+    hipLaunchKernelGGL(k_boundary_merge, dim3((unsigned)(K - 1)), dim3(256), 0, st, d_out, is_f64 ? 1 : 0,
+                       (const Zone*)d_zones, K - 1);
     return hipGetLastError();
 }
 

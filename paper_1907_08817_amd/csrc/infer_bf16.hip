@@ -14,9 +14,9 @@
 //    Henry, Tang and Heinecke, 2019) while W2 itself is rounded to bfloat16;
 //  - the accumulators start at b2; lane (j, g) ends with hidden-2 units
 //    32 rb + 8 (v / 4) + 4 g + v % 4 (v = 0..15) of its key;
-//  - layer 3: relu, then a compensated FP32 dot product per lane (Dot2 of
-//    Ogita, Rump and Oishi), the two halves' (sum, correction) pairs added in
-//    FP64 so that F keeps a resolution finer than one slot at n = 1e9.
+//  - layer 3: relu, then the dot product with w3 accumulated in FP64 (each
+//    FP32 x FP32 product is exact there), the two halves' sums added in FP64,
+//    so that F keeps a resolution finer than one slot at n = 1e9.
 // Compiled with -ffp-contract=off.
 #include "infer_common.h"
 
@@ -40,14 +40,27 @@ __device__ __forceinline__ uint32_t pack_hi(float x, float y) {
 __device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
 template <int H, int T>
-__global__ void __launch_bounds__(256) k_infer_bf16(InferArgs a) {
+__global__ void __launch_bounds__(256, 3) k_infer_bf16(InferArgs a) {
     constexpr int RB = H / 32;  // 32-row blocks of hidden-2 units
     constexpr int KS = H / 16;  // k-steps of 16 hidden-1 units
     const DevModel* __restrict__ m = a.model;
+    // Per-unit vectors live in LDS and are re-read every tile: held in
+    // registers they would cost 128 VGPRs at H = 64 and cut occupancy to one
+    // wave per SIMD, leaving no other wave to cover MFMA and load latency.
+    // s_w1 / s_b1 in layer-1 lane order, s_b2 / s_w3 in accumulator order:
+    // entry (g, rb, v) for unit 32 rb + 8 (v / 4) + 4 g + v % 4.
     __shared__ float s_w1[64], s_b1[64];
+    __shared__ float s_b2[2][64];
+    __shared__ double s_w3[2][64];
     for (int i = threadIdx.x; i < H; i += blockDim.x) {
         s_w1[i] = m->w1[i];
         s_b1[i] = m->b1[i];
+    }
+    for (int i = threadIdx.x; i < 2 * H; i += blockDim.x) {
+        const int g = i / H, rb = (i % H) / 16, v = i % 16;
+        const int u = 32 * rb + 8 * (v >> 2) + 4 * g + (v & 3);
+        s_b2[g][i % H] = m->b2[u];
+        s_w3[g][i % H] = (double)m->w3[u];
     }
     __syncthreads();
     const int lane = __lane_id();
@@ -65,22 +78,19 @@ __global__ void __launch_bounds__(256) k_infer_bf16(InferArgs a) {
             for (int q = 0; q < 4; ++q)
                 A[rb][s][q] = bf16_rne_bits(row[2 * q]) | (bf16_rne_bits(row[2 * q + 1]) << 16);
         }
-    float b2r[RB][16], w3r[RB][16];
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            int u = 32 * rb + 8 * (v >> 2) + 4 * g + (v & 3);
-            b2r[rb][v] = m->b2[u];
-            w3r[rb][v] = m->w3[u];
-        }
     const float b3 = m->b3;
     const double lo = m->lo, inv = m->inv_range;
+    const float* __restrict__ w1g = s_w1 + 8 * g;
+    const float* __restrict__ b1g = s_b1 + 8 * g;
+    const float* __restrict__ b2g = s_b2[g];
+    const double* __restrict__ w3g = s_w3[g];
 
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t ntiles = (a.n + 31) >> 5;
     for (int64_t tile = wave; tile < ntiles; tile += nwaves) {
+        // keeps the compiler from hoisting the LDS vectors into registers
+        __asm__ volatile("" ::: "memory");
         const int64_t i = tile * 32 + j;
         const bool active = i < a.n;
         const uint64_t bits = active ? a.in[i] : 0;
@@ -93,16 +103,16 @@ __global__ void __launch_bounds__(256) k_infer_bf16(InferArgs a) {
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int v = 0; v < 16; ++v) acc[rb][v] = b2r[rb][v];
+            for (int v = 0; v < 16; ++v) acc[rb][v] = b2g[16 * rb + v];
 
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             float h[8];
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                const int u = 16 * s + 8 * g + t;
-                float z = __builtin_fmaf(s_w1[u], xh, s_b1[u]);
-                z = __builtin_fmaf(s_w1[u], xl, z);
+                const int u = 16 * s + t;
+                float z = __builtin_fmaf(w1g[u], xh, b1g[u]);
+                z = __builtin_fmaf(w1g[u], xl, z);
                 h[t] = z > 0.0f ? z : 0.0f;
             }
             u32x4 B0, B1, B2;
@@ -133,28 +143,21 @@ __global__ void __launch_bounds__(256) k_infer_bf16(InferArgs a) {
             }
         }
 
-        // layer 3: compensated dot product (Dot2: TwoProduct by FMA + TwoSum) of
-        // w3 and relu(z2) over this lane's units; a product rounded to FP32
-        // alone would quantise F to ~1e-8 * w3, more than a slot at n = 1e8
-        float sum = g == 0 ? b3 : 0.0f, c = 0.0f;
+        // layer 3: w3 . relu(z2) accumulated in FP64.  A product of two FP32
+        // values is exact in FP64, so the sum carries ~2^-53 relative error
+        // per step: F keeps a resolution far below one slot at n = 1e9, at
+        // three VALU operations per unit (relu, convert, FP64 FMA)
+        double sum = g == 0 ? (double)b3 : 0.0;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const float h2 = acc[rb][v] > 0.0f ? acc[rb][v] : 0.0f;
-                const float w = w3r[rb][v];
-                const float pr = w * h2;
-                const float r = __builtin_fmaf(w, h2, -pr);
-                float q;
-                sum = two_sum(sum, pr, q);
-                c = c + (q + r);
+                sum = __builtin_fma(w3g[16 * rb + v], (double)h2, sum);
             }
-        const float osum = __shfl_xor(sum, 32);
-        const float oc = __shfl_xor(c, 32);
-        const double F = ((double)sum + (double)c) + ((double)osum + (double)oc);
+        const double F = sum + __shfl_xor(sum, 32);
         const uint32_t slot = mapped ? slot_of(F, a.M) : kUnmapped;
-        const bool mine = active && g == 0;
-        if (mine) {
+        if (active && g == 0) {
             if (a.slots_out) a.slots_out[i] = slot;
             if (a.F_out) a.F_out[i] = mapped ? F : __longlong_as_double(0x7FF8000000000000ll);
         }

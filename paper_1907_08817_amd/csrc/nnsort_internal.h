@@ -22,19 +22,19 @@ constexpr int kItemsPerThread = kBucketCap / kBucketThreads;  // 16
 
 // Counters kept in the workspace (uint64 each).
 enum Counter : int {
-    kCntReserved0 = 0,
+    kCntResorted = 0,     // ranges re-sorted whole after the tile merges
     kCntUnmapped = 1,     // keys with no slot
     kCntCollided = 2,     // [2, 2 + 8): |c_r| for r = 1..8 (all buckets)
     kCntPlaced = 10,      // [10, 18): keys stored in o_r
     kCntBigKeys = 18,     // keys of big buckets
     kCntBigBuckets = 19,
-    kCntGlobal = 20,      // entries in the global residue list G
     kCntBoundary = 21,    // keys inside boundary fix-up zones
     kCntFallback = 22,    // nonzero: tile fix-up needs the full-sort fallback
     kCntBadSlot = 23,     // caller-given slot out of range
-    kCntSmallBuckets = 24,
+    kCntSegments = 24,    // non-empty slot ranges
     kCntPosErrSum = 25,   // double bits: sum |F n - p|
     kCntPosErrCnt = 26,
+    kCntUnmappedNeg = 27, // keys with no slot whose order key has the top bit clear
     kNumCounters = 32
 };
 
@@ -70,7 +70,8 @@ struct SortPlan {
     int64_t NB;        // buckets
     int64_t big_max;   // capacity for big buckets' slot histograms
     size_t off_counters, off_cnt, off_start, off_slots0, off_S0, off_K0, off_K1, off_phist, off_psums,
-        off_bucket_info, off_bigpref, off_segminmax, off_G, off_radix, off_M, off_big_hist, off_model, total;
+        off_seglist, off_bigbucket, off_bigpref, off_part, off_zones, off_G, off_radix, off_big_hist, off_model,
+        total;
     size_t radix_bytes;
 };
 
@@ -96,10 +97,6 @@ hipError_t launch_infer(const InferArgs& a, int H, int form, int bf16_terms, hip
 // 2 = u64 bits (converted on load / store).
 hipError_t radix_sort(const uint64_t* d_in, uint64_t* d_out, int64_t n, int in_mode, int out_mode,
                       void* d_ws, size_t ws_bytes, hipStream_t st);
-
-// Merge two ascending order-key arrays into bits (out_mode as above).
-hipError_t launch_merge(const uint64_t* d_a, int64_t na, const uint64_t* d_b, int64_t nb,
-                        uint64_t* d_out, int out_mode, hipStream_t st);
 
 // Copy with conversion between order keys and bits.
 hipError_t launch_convert(const uint64_t* d_in, uint64_t* d_out, int64_t n, int in_mode, int out_mode,

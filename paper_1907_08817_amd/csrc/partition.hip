@@ -20,9 +20,10 @@ __device__ __forceinline__ uint32_t range_of(uint32_t slot, uint32_t NB) {
     return slot == kUnmapped ? NB : (slot >> kLogBucketSlots);
 }
 
+// Digit histogram of one 4096-key tile, stored as hist[tile * 256 + digit].
 __global__ void __launch_bounds__(kPartThreads) k_part_upsweep(const uint32_t* __restrict__ slots, int64_t n,
                                                                uint32_t NB, int shift, uint32_t mask,
-                                                               uint32_t* blockhist, int64_t nblocks) {
+                                                               uint32_t* blockhist) {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -33,23 +34,97 @@ __global__ void __launch_bounds__(kPartThreads) k_part_upsweep(const uint32_t* _
         if (i < n) atomicAdd(&h[(range_of(slots[i], NB) >> shift) & mask], 1u);
     }
     __syncthreads();
-    blockhist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    blockhist[(int64_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
+}
+
+// Offsets from the tile histograms, in two coalesced passes.  Tiles are taken
+// in chunks of kScanTiles: (1) per chunk and digit, the exclusive prefix over
+// the chunk's tiles in place, and the chunk total; (2) per digit, the
+// exclusive prefix over chunks plus the digit's start (all digits below it).
+// A tile's output offset for digit d is then hist[t][d] + chunk[t / kScanTiles][d].
+constexpr int kScanTiles = 128;
+
+__global__ void __launch_bounds__(256) k_part_scan_chunks(uint32_t* hist, int64_t ntiles, uint32_t* chunk) {
+    const int d = threadIdx.x;
+    const int64_t t0 = (int64_t)blockIdx.x * kScanTiles;
+    const int64_t t1 = t0 + kScanTiles < ntiles ? t0 + kScanTiles : ntiles;
+    uint32_t run = 0;
+    int64_t t = t0;
+    for (; t + 8 <= t1; t += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = hist[(t + q) * 256 + d];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            hist[(t + q) * 256 + d] = run;
+            run += v[q];
+        }
+    }
+    for (; t < t1; ++t) {
+        uint32_t v = hist[t * 256 + d];
+        hist[t * 256 + d] = run;
+        run += v;
+    }
+    chunk[(int64_t)blockIdx.x * 256 + d] = run;
+}
+
+__global__ void __launch_bounds__(256) k_part_scan_top(uint32_t* chunk, int64_t nchunks) {
+    __shared__ uint32_t wtot[4];
+    const int d = threadIdx.x;
+    const int lane = d & 63, w = d >> 6;
+    uint32_t run = 0;
+    for (int64_t c = 0; c < nchunks; ++c) {
+        uint32_t v = chunk[c * 256 + d];
+        chunk[c * 256 + d] = run;
+        run += v;
+    }
+    // start of digit d = sum of the totals of digits below it
+    uint32_t inc = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) wtot[w] = inc;
+    __syncthreads();
+    uint32_t base = inc - run;
+    for (int ww = 0; ww < w; ++ww) base += wtot[ww];
+    for (int64_t c = 0; c < nchunks; ++c) chunk[c * 256 + d] += base;
+}
+
+// Tile handled by workgroup `bid`.  Workgroups are dealt to the 8 XCDs in turn
+// (workgroup i on XCD i mod 8), so XCD x is given the x-th contiguous eighth
+// of the tiles: the runs that consecutive tiles write for one digit are then
+// adjacent in memory and meet in the same L2 before they are written back.
+__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t ntiles) {
+    const int64_t q = ntiles >> 3, r = ntiles & 7;
+    const int64_t x = bid & 7, j = bid >> 3;
+    return x * q + (x < r ? x : r) + j;
 }
 
 // Stable scatter of (key, slot) pairs by one digit of the range id.  in_bits:
 // keys arrive as caller bit patterns (first pass) and leave as order keys.
+// The tile is first reordered by digit in LDS, then written out by
+// consecutive threads, so each digit's run of the tile (16 keys on average)
+// leaves as a few full cache lines instead of 16 scattered 8-byte writes.
 __global__ void __launch_bounds__(kPartThreads) k_part_downsweep(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ sin, uint64_t* __restrict__ kout,
     uint32_t* __restrict__ sout, int64_t n, uint32_t NB, int shift, uint32_t mask, int in_bits, int is_f64,
-    const uint32_t* __restrict__ scanned, int64_t nblocks) {
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ chunk, int64_t nblocks) {
+    __shared__ uint64_t s_key[kPartTile];
+    __shared__ uint32_t s_slot[kPartTile];
     __shared__ uint32_t wcnt[kPartWaves][256];
+    __shared__ uint32_t dstart[256];
     __shared__ uint32_t gofs[256];
+    __shared__ uint32_t wtot[kPartWaves];
     const int lane = __lane_id();
     const int w = threadIdx.x >> 6;
+    const int64_t tile = xcd_tile(blockIdx.x, nblocks);
     for (int i = threadIdx.x; i < kPartWaves * 256; i += kPartThreads) (&wcnt[0][0])[i] = 0;
-    gofs[threadIdx.x] = scanned[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+    gofs[threadIdx.x] = hist[tile * 256 + threadIdx.x] + chunk[(tile / kScanTiles) * 256 + threadIdx.x];
     __syncthreads();
-    const int64_t t0 = (int64_t)blockIdx.x * kPartTile + (int64_t)w * (kPartItems * 64);
+    const int64_t tile0 = tile * kPartTile;
+    const int64_t t0 = tile0 + (int64_t)w * (kPartItems * 64);
     uint64_t key[kPartItems];
     uint32_t slot[kPartItems];
     uint32_t rank[kPartItems];
@@ -73,9 +148,25 @@ __global__ void __launch_bounds__(kPartThreads) k_part_downsweep(
         if (valid && (peers & lt) == 0) wcnt[w][d] = base + (uint32_t)__popcll(peers);
     }
     __syncthreads();
+    // digit d = threadIdx.x: tile total, block-wide exclusive scan over digits,
+    // then each wave's start inside the digit's run
     {
-        uint32_t d = threadIdx.x;
-        uint32_t run = gofs[d];
+        const uint32_t d = threadIdx.x;
+        uint32_t tot = 0;
+#pragma unroll
+        for (int ww = 0; ww < kPartWaves; ++ww) tot += wcnt[ww][d];
+        uint32_t inc = tot;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(inc, o);
+            if (lane >= o) inc += y;
+        }
+        if (lane == 63) wtot[w] = inc;
+        __syncthreads();
+        uint32_t pre = 0;
+        for (int ww = 0; ww < w; ++ww) pre += wtot[ww];
+        uint32_t run = pre + inc - tot;
+        dstart[d] = run;
 #pragma unroll
         for (int ww = 0; ww < kPartWaves; ++ww) {
             uint32_t c = wcnt[ww][d];
@@ -89,10 +180,19 @@ __global__ void __launch_bounds__(kPartThreads) k_part_downsweep(
         int64_t i = t0 + k * 64 + lane;
         if (i < n) {
             uint32_t d = (range_of(slot[k], NB) >> shift) & mask;
-            uint32_t pos = wcnt[w][d] + rank[k];
-            kout[pos] = key[k];
-            sout[pos] = slot[k];
+            uint32_t lp = wcnt[w][d] + rank[k];
+            s_key[lp] = key[k];
+            s_slot[lp] = slot[k];
         }
+    }
+    __syncthreads();
+    const int cnt = (int)(n - tile0 < kPartTile ? n - tile0 : kPartTile);
+    for (int i = threadIdx.x; i < cnt; i += kPartThreads) {
+        const uint32_t sl = s_slot[i];
+        const uint32_t d = (range_of(sl, NB) >> shift) & mask;
+        const uint32_t pos = gofs[d] + (uint32_t)i - dstart[d];
+        kout[pos] = s_key[i];
+        sout[pos] = sl;
     }
 }
 
@@ -185,13 +285,51 @@ __global__ void __launch_bounds__(256) k_big_gather(const int32_t* __restrict__ 
         if (h[i]) atomicAdd(&hist[id * kBucketSlots + i], h[i]);
 }
 
+// After the residue sort, G in order is: keys without a slot whose order key
+// has the top bit clear (negative NaN, -inf), then the dense ranges' keys,
+// then the other keys without a slot.  Where f is monotone across ranges the
+// middle part is the dense ranges one after another, so range id's slice
+// G[u_neg + gpref[id] ...] goes to its place out[u_neg + start[b] ...]; the
+// boundary check that follows catches any overlap.
+__global__ void __launch_bounds__(256) k_big_place(const int32_t* __restrict__ bigbucket, int64_t big_count,
+                                                   const int64_t* __restrict__ chunk_pref,
+                                                   const int64_t* __restrict__ gpref,
+                                                   const int64_t* __restrict__ start, const uint64_t* __restrict__ Gs,
+                                                   int64_t u_neg, uint64_t* __restrict__ out, int is_f64) {
+    const int64_t chunk = blockIdx.x;
+    int64_t lo = 0, hi = big_count - 1;
+    while (lo < hi) {
+        int64_t mid = (lo + hi + 1) >> 1;
+        if (chunk_pref[mid] <= chunk) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t id = lo;
+    const int32_t b = bigbucket[id];
+    const int64_t len = start[b + 1] - start[b];
+    const int64_t c0 = (chunk - chunk_pref[id]) * kChunk;
+    const int64_t c1 = c0 + kChunk < len ? c0 + kChunk : len;
+    const uint64_t* src = Gs + u_neg + gpref[id];
+    uint64_t* dst = out + u_neg + start[b];
+    for (int64_t e = c0 + threadIdx.x; e < c1; e += blockDim.x) dst[e] = order_key_inverse(src[e], is_f64);
+}
+
+// Keys without a slot whose order key has the top bit clear.
+__global__ void __launch_bounds__(256) k_count_neg(const uint64_t* __restrict__ K, const int64_t* __restrict__ start,
+                                                   uint32_t NB, int64_t n, unsigned long long* count) {
+    const int64_t s0 = start[NB];
+    unsigned long long c = 0;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = s0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        c += (K[i] >> 63) ? 0 : 1;
+    if (c) atomicAdd(count, c);
+}
+
 __global__ void __launch_bounds__(256) k_copy_u64(const uint64_t* __restrict__ in, uint64_t* out, int64_t n) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = in[i];
 }
 
 // ---- host-side launch sequence ----
-hipError_t exclusive_scan_u32(uint32_t* data, int64_t len, uint32_t* sums, hipStream_t st);
 
 int range_passes(uint32_t NB, int* shifts, uint32_t* masks) {
     int bits = 1;
@@ -206,9 +344,12 @@ int range_passes(uint32_t NB, int* shifts, uint32_t* masks) {
     return passes;
 }
 
+// Tile histograms followed by the chunk offsets.
 size_t partition_hist_words(int64_t n) {
     int64_t nblocks = (n + kPartTile - 1) / kPartTile;
-    return (size_t)256 * (nblocks > 0 ? nblocks : 1);
+    if (nblocks < 1) nblocks = 1;
+    int64_t nchunks = (nblocks + kScanTiles - 1) / kScanTiles;
+    return (size_t)256 * (nblocks + nchunks);
 }
 
 // Partition (keys, slots) by range id.  in_keys are caller bit patterns;
@@ -220,6 +361,9 @@ hipError_t partition_by_range(const uint64_t* in_keys, const uint32_t* in_slots,
     uint32_t masks[4];
     int passes = range_passes(NB, shifts, masks);
     const int64_t nblocks = (n + kPartTile - 1) / kPartTile;
+    const int64_t nchunks = (nblocks + kScanTiles - 1) / kScanTiles;
+    uint32_t* chunk = blockhist + 256 * nblocks;
+    (void)sums;
     uint64_t* Kb[2] = {K0, K1};
     uint32_t* Sb[2] = {S0, S1};
     const uint64_t* kin = in_keys;
@@ -229,10 +373,11 @@ hipError_t partition_by_range(const uint64_t* in_keys, const uint32_t* in_slots,
         uint64_t* ko = Kb[p & 1];
         uint32_t* so = Sb[p & 1];
         hipLaunchKernelGGL(k_part_upsweep, dim3((unsigned)nblocks), dim3(kPartThreads), 0, st, sin, n, NB, shifts[p],
-                           masks[p], blockhist, nblocks);
-        if ((e = exclusive_scan_u32(blockhist, 256 * nblocks, sums, st)) != hipSuccess) return e;
+                           masks[p], blockhist);
+        hipLaunchKernelGGL(k_part_scan_chunks, dim3((unsigned)nchunks), dim3(256), 0, st, blockhist, nblocks, chunk);
+        hipLaunchKernelGGL(k_part_scan_top, dim3(1), dim3(256), 0, st, chunk, nchunks);
         hipLaunchKernelGGL(k_part_downsweep, dim3((unsigned)nblocks), dim3(kPartThreads), 0, st, kin, sin, ko, so, n,
-                           NB, shifts[p], masks[p], p == 0 ? 1 : 0, is_f64 ? 1 : 0, blockhist, nblocks);
+                           NB, shifts[p], masks[p], p == 0 ? 1 : 0, is_f64 ? 1 : 0, blockhist, chunk, nblocks);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         kin = ko;
         sin = so;
@@ -272,6 +417,21 @@ hipError_t launch_big_gather(const int32_t* d_bigbucket, int64_t big_count, int6
     if (nchunks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_big_gather, dim3((unsigned)nchunks), dim3(256), 0, st, d_bigbucket, big_count, d_chunk_pref,
                        d_gpref, d_start, d_K, d_S, d_hist, d_G);
+    return hipGetLastError();
+}
+
+hipError_t launch_big_place(const int32_t* d_bigbucket, int64_t big_count, int64_t nchunks,
+                            const int64_t* d_chunk_pref, const int64_t* d_gpref, const int64_t* d_start,
+                            const uint64_t* d_Gs, int64_t u_neg, uint64_t* d_out, bool is_f64, hipStream_t st) {
+    if (nchunks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_big_place, dim3((unsigned)nchunks), dim3(256), 0, st, d_bigbucket, big_count, d_chunk_pref,
+                       d_gpref, d_start, d_Gs, u_neg, d_out, is_f64 ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_neg(const uint64_t* d_K, const int64_t* d_start, uint32_t NB, int64_t n, uint64_t* d_count,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_count_neg, dim3(64), dim3(256), 0, st, d_K, d_start, NB, n, (unsigned long long*)d_count);
     return hipGetLastError();
 }
 
