@@ -73,7 +73,18 @@ __global__ void __launch_bounds__(256) k_part_scan_top(uint32_t* chunk, int64_t 
     const int d = threadIdx.x;
     const int lane = d & 63, w = d >> 6;
     uint32_t run = 0;
-    for (int64_t c = 0; c < nchunks; ++c) {
+    int64_t c = 0;
+    for (; c + 8 <= nchunks; c += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = chunk[(c + q) * 256 + d];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            chunk[(c + q) * 256 + d] = run;
+            run += v[q];
+        }
+    }
+    for (; c < nchunks; ++c) {
         uint32_t v = chunk[c * 256 + d];
         chunk[c * 256 + d] = run;
         run += v;
@@ -89,7 +100,8 @@ __global__ void __launch_bounds__(256) k_part_scan_top(uint32_t* chunk, int64_t 
     __syncthreads();
     uint32_t base = inc - run;
     for (int ww = 0; ww < w; ++ww) base += wtot[ww];
-    for (int64_t c = 0; c < nchunks; ++c) chunk[c * 256 + d] += base;
+#pragma unroll 8
+    for (int64_t c2 = 0; c2 < nchunks; ++c2) chunk[c2 * 256 + d] += base;
 }
 
 // Tile handled by workgroup `bid`.  Workgroups are dealt to the 8 XCDs in turn
@@ -102,59 +114,89 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t ntiles) {
     return x * q + (x < r ? x : r) + j;
 }
 
-// Stable scatter of (key, slot) pairs by one digit of the range id.  in_bits:
-// keys arrive as caller bit patterns (first pass) and leave as order keys.
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Scatter of (key, slot) pairs by one digit of the range id.  in_bits: keys
+// arrive as caller bit patterns (first pass) and leave as order keys.
+//
+// STABLE (every pass after the first, as LSD grouping needs): a key's rank
+// among the tile's keys of its digit follows input order -- within a wave by
+// matching digits bit by bit with ballots, across waves by per-wave counters.
+// The first pass need not be stable (only the last pass's order within a
+// digit matters for grouping by range), so there one LDS atomic per key
+// gives its rank.
+//
 // The tile is first reordered by digit in LDS, then written out by
 // consecutive threads, so each digit's run of the tile (16 keys on average)
 // leaves as a few full cache lines instead of 16 scattered 8-byte writes.
+template <bool STABLE>
 __global__ void __launch_bounds__(kPartThreads) k_part_downsweep(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ sin, uint64_t* __restrict__ kout,
-    uint32_t* __restrict__ sout, int64_t n, uint32_t NB, int shift, uint32_t mask, int in_bits, int is_f64,
-    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ chunk, int64_t nblocks) {
+    uint32_t* __restrict__ sout, int64_t n, uint32_t NB, int shift, uint32_t mask, int nbits, int in_bits,
+    int is_f64, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ chunk, int64_t nblocks) {
+    // the rank counters are dead once every key knows its place in the tile,
+    // so they share storage with the staged slots
     __shared__ uint64_t s_key[kPartTile];
-    __shared__ uint32_t s_slot[kPartTile];
-    __shared__ uint32_t wcnt[kPartWaves][256];
+    __shared__ union {
+        uint32_t slot[kPartTile];
+        uint32_t cnt[kPartWaves][256];
+    } s_u;
     __shared__ uint32_t dstart[256];
     __shared__ uint32_t gofs[256];
     __shared__ uint32_t wtot[kPartWaves];
     const int lane = __lane_id();
     const int w = threadIdx.x >> 6;
     const int64_t tile = xcd_tile(blockIdx.x, nblocks);
-    for (int i = threadIdx.x; i < kPartWaves * 256; i += kPartThreads) (&wcnt[0][0])[i] = 0;
+    const int64_t tile0 = tile * kPartTile;
+    const int lim = (int)(n - tile0 < kPartTile ? n - tile0 : kPartTile);
+    for (int i = threadIdx.x; i < kPartWaves * 256; i += kPartThreads) (&s_u.cnt[0][0])[i] = 0;
     gofs[threadIdx.x] = hist[tile * 256 + threadIdx.x] + chunk[(tile / kScanTiles) * 256 + threadIdx.x];
     __syncthreads();
-    const int64_t tile0 = tile * kPartTile;
-    const int64_t t0 = tile0 + (int64_t)w * (kPartItems * 64);
+
+    const uint64_t* __restrict__ kb = kin + tile0;
+    const uint32_t* __restrict__ sb = sin + tile0;
     uint64_t key[kPartItems];
     uint32_t slot[kPartItems];
     uint32_t rank[kPartItems];
-    const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
     for (int k = 0; k < kPartItems; ++k) {
-        int64_t i = t0 + k * 64 + lane;
-        bool valid = i < n;
-        uint64_t v = valid ? kin[i] : 0;
+        const int idx = w * (kPartItems * 64) + k * 64 + lane;
+        const bool valid = idx < lim;
+        const uint64_t v = valid ? kb[idx] : 0;
         key[k] = in_bits ? order_key(v, is_f64) : v;
-        slot[k] = valid ? sin[i] : 0;
-        uint32_t d = (range_of(slot[k], NB) >> shift) & mask;
-        unsigned long long peers = __ballot(valid);
+        slot[k] = valid ? sb[idx] : 0;
+        const uint32_t d = (range_of(slot[k], NB) >> shift) & mask;
+        if (STABLE) {
+            unsigned long long peers = __ballot(valid);
 #pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
-            unsigned long long bb = __ballot(valid && ((d >> bit) & 1u));
-            peers &= ((d >> bit) & 1u) ? bb : ~bb;
+            for (int bit = 0; bit < 8; ++bit) {
+                if (bit >= nbits) break;
+                const bool on = (d >> bit) & 1u;
+                const unsigned long long bb = __ballot(on);
+                peers &= on ? bb : ~bb;
+            }
+            const uint32_t below = lanes_below(peers);
+            const uint32_t base = valid ? s_u.cnt[w][d] : 0;
+            rank[k] = base + below;
+            if (valid && below == 0) s_u.cnt[w][d] = base + (uint32_t)__popcll(peers);
+        } else {
+            if (valid) rank[k] = atomicAdd(&s_u.cnt[0][d], 1u);
         }
-        uint32_t base = valid ? wcnt[w][d] : 0;
-        rank[k] = base + (uint32_t)__popcll(peers & lt);
-        if (valid && (peers & lt) == 0) wcnt[w][d] = base + (uint32_t)__popcll(peers);
     }
     __syncthreads();
     // digit d = threadIdx.x: tile total, block-wide exclusive scan over digits,
-    // then each wave's start inside the digit's run
+    // then (STABLE) each wave's start inside the digit's run
     {
         const uint32_t d = threadIdx.x;
         uint32_t tot = 0;
+        if (STABLE) {
 #pragma unroll
-        for (int ww = 0; ww < kPartWaves; ++ww) tot += wcnt[ww][d];
+            for (int ww = 0; ww < kPartWaves; ++ww) tot += s_u.cnt[ww][d];
+        } else {
+            tot = s_u.cnt[0][d];
+        }
         uint32_t inc = tot;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -163,32 +205,39 @@ __global__ void __launch_bounds__(kPartThreads) k_part_downsweep(
         }
         if (lane == 63) wtot[w] = inc;
         __syncthreads();
-        uint32_t pre = 0;
-        for (int ww = 0; ww < w; ++ww) pre += wtot[ww];
-        uint32_t run = pre + inc - tot;
+        uint32_t run = inc - tot;
+        for (int ww = 0; ww < w; ++ww) run += wtot[ww];
         dstart[d] = run;
+        if (STABLE) {
 #pragma unroll
-        for (int ww = 0; ww < kPartWaves; ++ww) {
-            uint32_t c = wcnt[ww][d];
-            wcnt[ww][d] = run;
-            run += c;
+            for (int ww = 0; ww < kPartWaves; ++ww) {
+                uint32_t c = s_u.cnt[ww][d];
+                s_u.cnt[ww][d] = run;
+                run += c;
+            }
         }
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kPartItems; ++k) {
-        int64_t i = t0 + k * 64 + lane;
-        if (i < n) {
-            uint32_t d = (range_of(slot[k], NB) >> shift) & mask;
-            uint32_t lp = wcnt[w][d] + rank[k];
-            s_key[lp] = key[k];
-            s_slot[lp] = slot[k];
+        const int idx = w * (kPartItems * 64) + k * 64 + lane;
+        if (idx < lim) {
+            const uint32_t d = (range_of(slot[k], NB) >> shift) & mask;
+            rank[k] += STABLE ? s_u.cnt[w][d] : dstart[d];
         }
     }
     __syncthreads();
-    const int cnt = (int)(n - tile0 < kPartTile ? n - tile0 : kPartTile);
-    for (int i = threadIdx.x; i < cnt; i += kPartThreads) {
-        const uint32_t sl = s_slot[i];
+#pragma unroll
+    for (int k = 0; k < kPartItems; ++k) {
+        const int idx = w * (kPartItems * 64) + k * 64 + lane;
+        if (idx < lim) {
+            s_key[rank[k]] = key[k];
+            s_u.slot[rank[k]] = slot[k];
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < lim; i += kPartThreads) {
+        const uint32_t sl = s_u.slot[i];
         const uint32_t d = (range_of(sl, NB) >> shift) & mask;
         const uint32_t pos = gofs[d] + (uint32_t)i - dstart[d];
         kout[pos] = s_key[i];
@@ -331,7 +380,7 @@ __global__ void __launch_bounds__(256) k_copy_u64(const uint64_t* __restrict__ i
 
 // ---- host-side launch sequence ----
 
-int range_passes(uint32_t NB, int* shifts, uint32_t* masks) {
+int range_passes(uint32_t NB, int* shifts, uint32_t* masks, int* widths) {
     int bits = 1;
     while (bits < 32 && ((uint64_t)NB >> bits) != 0) ++bits;  // range ids 0..NB
     int passes = (bits + 7) / 8;
@@ -340,6 +389,7 @@ int range_passes(uint32_t NB, int* shifts, uint32_t* masks) {
         shifts[p] = p * per;
         int w = bits - p * per < per ? bits - p * per : per;
         masks[p] = (1u << w) - 1u;
+        widths[p] = w;
     }
     return passes;
 }
@@ -357,9 +407,9 @@ size_t partition_hist_words(int64_t n) {
 hipError_t partition_by_range(const uint64_t* in_keys, const uint32_t* in_slots, int64_t n, uint32_t NB, bool is_f64,
                               uint64_t* K0, uint32_t* S0, uint64_t* K1, uint32_t* S1, uint32_t* blockhist,
                               uint32_t* sums, int* which, hipStream_t st) {
-    int shifts[4];
+    int shifts[4], widths[4];
     uint32_t masks[4];
-    int passes = range_passes(NB, shifts, masks);
+    int passes = range_passes(NB, shifts, masks, widths);
     const int64_t nblocks = (n + kPartTile - 1) / kPartTile;
     const int64_t nchunks = (nblocks + kScanTiles - 1) / kScanTiles;
     uint32_t* chunk = blockhist + 256 * nblocks;
@@ -376,8 +426,14 @@ hipError_t partition_by_range(const uint64_t* in_keys, const uint32_t* in_slots,
                            masks[p], blockhist);
         hipLaunchKernelGGL(k_part_scan_chunks, dim3((unsigned)nchunks), dim3(256), 0, st, blockhist, nblocks, chunk);
         hipLaunchKernelGGL(k_part_scan_top, dim3(1), dim3(256), 0, st, chunk, nchunks);
-        hipLaunchKernelGGL(k_part_downsweep, dim3((unsigned)nblocks), dim3(kPartThreads), 0, st, kin, sin, ko, so, n,
-                           NB, shifts[p], masks[p], p == 0 ? 1 : 0, is_f64 ? 1 : 0, blockhist, chunk, nblocks);
+        if (p == 0)
+            hipLaunchKernelGGL(k_part_downsweep<false>, dim3((unsigned)nblocks), dim3(kPartThreads), 0, st, kin, sin,
+                               ko, so, n, NB, shifts[p], masks[p], widths[p], 1, is_f64 ? 1 : 0, blockhist, chunk,
+                               nblocks);
+        else
+            hipLaunchKernelGGL(k_part_downsweep<true>, dim3((unsigned)nblocks), dim3(kPartThreads), 0, st, kin, sin,
+                               ko, so, n, NB, shifts[p], masks[p], widths[p], 0, is_f64 ? 1 : 0, blockhist, chunk,
+                               nblocks);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         kin = ko;
         sin = so;
