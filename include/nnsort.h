@@ -142,6 +142,11 @@ typedef struct {
     int32_t range_resorts;   /* slot ranges whose neighbour-tile merges did not
                                 settle and were re-sorted whole in LDS */
     double pos_err;          /* stats_level 2: mean |F(key) n - rank| / n */
+    /* stats_level >= 1: t_infer = the map kernel; t_place = the partition of
+     * keys by slot range and the gather of dense ranges; t_polish = rounds and
+     * polish of every range in LDS; t_residue = the conventional sort of the
+     * residue path and its placement; t_merge = the check and repair of the
+     * boundaries between neighbouring ranges; t_total = the whole call. */
     double t_infer_ms, t_place_ms, t_polish_ms, t_residue_ms, t_merge_ms, t_total_ms;
 } nnsort_stats;
 

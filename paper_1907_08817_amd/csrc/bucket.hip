@@ -252,7 +252,7 @@ struct BucketSmem {
     // the low half of word w, slot 2w + 1 in the high half
     uint32_t off[kBucketSlots / 2];
     uint32_t wsum[kBucketThreads / 64];
-    uint32_t red[2 * NNSORT_MAX_EPS];
+    uint32_t red[(kBucketThreads / 64) * NNSORT_MAX_EPS];  // per-wave stored counts per round
     int flag;
 };
 
@@ -355,7 +355,6 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket_polish(
         }
     }
     for (int i = tid; i < (int)kBucketSlots / 2; i += kBucketThreads) sm.off[i] = 0;
-    if (tid < 2 * NNSORT_MAX_EPS) sm.red[tid] = 0;
     if (tid == 0) sm.flag = 0;
     __syncthreads();
     // arrival rank of each key in its slot
@@ -369,10 +368,11 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket_polish(
     }
     __syncthreads();
 
-    // round counts from the multiplicities; slot offsets (exclusive scan)
+    // round counts from the multiplicities: round r stores #{s : k_s >= r}
+    // keys (wave totals by ballot); the conflict array after round r holds
+    // cnt - sum_{j <= r} stored_j.  Slot offsets by an exclusive scan.
     uint32_t ks[kSlotsPer], run = 0;
     {
-        uint32_t pl[NNSORT_MAX_EPS] = {0}, co[NNSORT_MAX_EPS] = {0};
         bool big_group = false;
 #pragma unroll
         for (int q = 0; q < kSlotsPer / 2; ++q) {
@@ -380,6 +380,7 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket_polish(
             ks[2 * q] = w & 0xFFFFu;
             ks[2 * q + 1] = w >> 16;
         }
+        uint32_t wpl[NNSORT_MAX_EPS] = {0};
 #pragma unroll
         for (int q = 0; q < kSlotsPer; ++q) {
             run += ks[q];
@@ -387,15 +388,13 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket_polish(
 #pragma unroll
             for (int r = 1; r <= NNSORT_MAX_EPS; ++r) {
                 if (r > eps) break;
-                pl[r - 1] += ks[q] >= (uint32_t)r ? 1u : 0u;
-                co[r - 1] += ks[q] > (uint32_t)r ? ks[q] - r : 0u;
+                wpl[r - 1] += (uint32_t)__popcll(__ballot(ks[q] >= (uint32_t)r));
             }
         }
-        for (int r = 0; r < eps; ++r) {
-            if (pl[r]) atomicAdd(&sm.red[r], pl[r]);
-            if (co[r]) atomicAdd(&sm.red[NNSORT_MAX_EPS + r], co[r]);
+        if (lane == 0) {
+            for (int r = 0; r < eps; ++r) sm.red[wv * NNSORT_MAX_EPS + r] = wpl[r];
         }
-        if (big_group) sm.flag = 1;
+        if (__ballot(big_group) && lane == 0) sm.flag = 1;
     }
     uint32_t inc = run;
 #pragma unroll
@@ -417,8 +416,15 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket_polish(
         }
     }
     if (tid < eps) {
-        part[b * kPartStride + tid] = sm.red[tid];
-        part[b * kPartStride + NNSORT_MAX_EPS + tid] = sm.red[NNSORT_MAX_EPS + tid];
+        uint32_t stored = 0, cum = 0;
+        for (int r = 0; r <= tid; ++r) {
+            uint32_t p = 0;
+            for (int w = 0; w < kBucketThreads / 64; ++w) p += sm.red[w * NNSORT_MAX_EPS + r];
+            cum += p;
+            stored = p;
+        }
+        part[b * kPartStride + tid] = stored;
+        part[b * kPartStride + NNSORT_MAX_EPS + tid] = cnt - cum;
     }
     __syncthreads();
 
@@ -444,10 +450,16 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket_polish(
             if (tid + k * kBucketThreads < cnt) {
                 const uint32_t s = sl[k];
                 const uint32_t g1 = s + 1 < kBucketSlots ? half_of(sm.off[(s + 1) >> 1], s + 1) : cnt;
+                const uint64_t me = key[k];
+                const uint32_t mine = g0[k] + rank[k];
                 uint32_t pos = g0[k];
-                for (uint32_t j = g0[k]; j < g1; ++j) {
-                    const uint64_t y = sm.keys[j];
-                    pos += (y < key[k] || (y == key[k] && j - g0[k] < rank[k])) ? 1u : 0u;
+                for (uint32_t j0 = g0[k]; j0 < g1; j0 += 8) {
+                    uint64_t y[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) y[q] = j0 + q < g1 ? sm.keys[j0 + q] : ~0ull;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        pos += (y[q] < me || (y[q] == me && j0 + q < mine)) ? 1u : 0u;
                 }
                 rank[k] = pos;
             }
