@@ -16,7 +16,8 @@ namespace nns {
 hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
 hipError_t launch_classify(const uint32_t* d_cnt, int64_t NB, int64_t big_max, int32_t* d_seglist,
-                           int32_t* d_bigbucket, uint64_t* d_counters, hipStream_t st);
+                           int32_t* d_bigbucket, uint64_t* d_bsum, uint64_t* d_counters, hipStream_t st);
+size_t classify_ws_words(int64_t NB);
 hipError_t launch_big_counts(const uint32_t* d_hist, int64_t big_count, int eps, uint64_t* d_counters,
                              hipStream_t st);
 size_t polish_part_words(int64_t NB);
@@ -31,7 +32,7 @@ size_t zone_bytes();
 size_t partition_hist_words(int64_t n);
 hipError_t partition_by_range(const uint64_t* in_keys, const uint32_t* in_slots, int64_t n, uint32_t NB, bool is_f64,
                               uint64_t* K0, uint32_t* S0, uint64_t* K1, uint32_t* S1, uint32_t* blockhist,
-                              uint32_t* sums, int* which, hipStream_t st);
+                              int* which, hipStream_t st);
 hipError_t launch_range_bounds(const uint32_t* d_sorted_slots, int64_t n, uint32_t NB, int64_t* d_start,
                                uint32_t* d_cnt, hipStream_t st);
 hipError_t launch_check_slots(const uint32_t* d_slots, int64_t n, int64_t S, uint64_t* d_bad, hipStream_t st);
@@ -155,9 +156,8 @@ SortPlan plan_sort(int64_t n, double m) {
     p.off_S0 = take(nn * 4);
     p.off_K0 = take(nn * 8);
     p.off_K1 = take(nn * 8);
-    size_t ph = partition_hist_words(n);
-    p.off_phist = take(ph * 4);
-    p.off_psums = take(((ph + 2047) / 2048 + 1) * 4);
+    p.off_phist = take(partition_hist_words(n) * 4);
+    p.off_psums = take(classify_ws_words(p.NB) * 8);
     p.off_seglist = take((size_t)p.NB * 4);
     p.off_bigbucket = take((size_t)p.big_max * 4);
     p.off_bigpref = take((size_t)(p.big_max + 1) * 2 * 8);
@@ -259,7 +259,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     uint64_t* K0 = (uint64_t*)(ws + P.off_K0);
     uint64_t* K1 = (uint64_t*)(ws + P.off_K1);
     uint32_t* phist = (uint32_t*)(ws + P.off_phist);
-    uint32_t* psums = (uint32_t*)(ws + P.off_psums);
+    uint64_t* clsum = (uint64_t*)(ws + P.off_psums);
     int32_t* seglist = (int32_t*)(ws + P.off_seglist);
     int32_t* bigbucket = (int32_t*)(ws + P.off_bigbucket);
     int64_t* chunk_pref = (int64_t*)(ws + P.off_bigpref);
@@ -303,12 +303,12 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     // ---- hand-off: stable partition of (key, slot) by slot range ----
     const uint32_t NB = (uint32_t)P.NB;
     int which = 0;
-    NNS_HIP(partition_by_range((const uint64_t*)d_in, slots_src, n, NB, is_f64, K0, S0, K1, slots0, phist, psums,
-                               &which, st));
+    NNS_HIP(partition_by_range((const uint64_t*)d_in, slots_src, n, NB, is_f64, K0, S0, K1, slots0, phist, &which,
+                               st));
     const uint64_t* Ks = which ? K1 : K0;
     const uint32_t* Ss = which ? slots0 : S0;
     NNS_HIP(launch_range_bounds(Ss, n, NB, start, cnt, st));
-    NNS_HIP(launch_classify(cnt, P.NB, P.big_max, seglist, bigbucket, counters, st));
+    NNS_HIP(launch_classify(cnt, P.NB, P.big_max, seglist, bigbucket, clsum, counters, st));
     NNS_HIP(launch_count_neg(Ks, start, NB, n, counters + kCntUnmappedNeg, st));
     uint64_t c[kNumCounters];
     int64_t first_unmapped = 0;
@@ -325,12 +325,13 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     const int64_t G_size = big_keys + unm;
     if (big_count > P.big_max) return NNSORT_EINTERNAL;
 
-    int64_t nchunks = 0;
+    // chunks of kBucketCap keys over the dense ranges: at most one partial
+    // chunk per range beyond the full ones; the kernels skip chunks past the
+    // real count, so no host round trip is needed
+    const int64_t nchunks = big_count > 0 ? big_keys / kBucketCap + big_count : 0;
     if (big_count > 0) {
         NNS_HIP(fill_u32(big_hist, big_count * (int64_t)kBucketSlots, 0u, st));
         NNS_HIP(launch_big_chunks(bigbucket, big_count, start, chunk_pref, gpref, st));
-        NNS_HIP(hipMemcpyAsync(&nchunks, chunk_pref + big_count, 8, hipMemcpyDeviceToHost, st));
-        NNS_HIP(hipStreamSynchronize(st));
         NNS_HIP(launch_big_gather(bigbucket, big_count, nchunks, chunk_pref, gpref, start, Ks, Ss, big_hist, G, st));
         NNS_HIP(launch_big_counts(big_hist, big_count, eps, counters, st));
     }
@@ -361,7 +362,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
         const int64_t len = first_unmapped;
         if (P.radix_bytes < radix_ws_bytes(len)) return NNSORT_EINTERNAL;
         NNS_HIP(radix_sort(out + u_neg, out + u_neg, len, mode, mode, radix_ws, P.radix_bytes, st));
-    } else {
+    } else if (c[kCntBoundary]) {
         NNS_HIP(launch_boundary_merge(out, is_f64, zones, nseg, st));
     }
     ev.mark(5);

@@ -62,58 +62,101 @@ hipError_t fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // classify: non-empty ranges in order, and the ranges too dense for LDS
 // ---------------------------------------------------------------------------
-// Single workgroup; each thread owns a contiguous chunk of ranges.
-__global__ void __launch_bounds__(1024) k_classify(const uint32_t* __restrict__ cnt, int64_t NB,
-                                                   int64_t big_max, int32_t* seglist, int32_t* bigbucket,
-                                                   unsigned long long* counters) {
-    __shared__ unsigned long long s_big[1024], s_seg[1024], s_bigkeys[1024];
-    int t = threadIdx.x;
-    int64_t chunk = (NB + 1023) / 1024;
-    int64_t b0 = t * chunk, b1 = b0 + chunk < NB ? b0 + chunk : NB;
-    unsigned long long big = 0, seg = 0, bigkeys = 0;
-    for (int64_t b = b0; b < b1; ++b) {
-        uint32_t c = cnt[b];
-        seg += c ? 1 : 0;
-        if (c > kBucketCap) {
-            ++big;
-            bigkeys += c;
-        }
+// Three passes over blocks of 256 ranges: per-block counts, an exclusive scan
+// of those counts, and the ordered write of both lists.
+__device__ __forceinline__ uint32_t below_in_wave(unsigned long long m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__global__ void __launch_bounds__(256) k_cls_count(const uint32_t* __restrict__ cnt, int64_t NB,
+                                                   unsigned long long* bsum) {
+    __shared__ unsigned long long s[3][4];
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint32_t c = b < NB ? cnt[b] : 0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    unsigned long long ne = __popcll(__ballot(c != 0));
+    unsigned long long bg = __popcll(__ballot(c > kBucketCap));
+    unsigned long long bk = c > kBucketCap ? c : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) bk += __shfl_xor(bk, o);
+    if (lane == 0) {
+        s[0][w] = ne;
+        s[1][w] = bg;
+        s[2][w] = bk;
     }
-    s_big[t] = big;
-    s_seg[t] = seg;
-    s_bigkeys[t] = bigkeys;
     __syncthreads();
-    // inclusive Hillis-Steele scans over 1024 entries
-    for (int off = 1; off < 1024; off <<= 1) {
-        unsigned long long c = t >= off ? s_big[t - off] : 0;
-        unsigned long long d = t >= off ? s_seg[t - off] : 0;
-        unsigned long long e = t >= off ? s_bigkeys[t - off] : 0;
+    if (threadIdx.x < 3)
+        bsum[blockIdx.x * 3 + threadIdx.x] =
+            s[threadIdx.x][0] + s[threadIdx.x][1] + s[threadIdx.x][2] + s[threadIdx.x][3];
+}
+
+// Exclusive scan of the per-block counts (in place); totals to the counters.
+__global__ void __launch_bounds__(256) k_cls_scan(unsigned long long* bsum, int64_t nblk,
+                                                  unsigned long long* counters) {
+    __shared__ unsigned long long s[3][256];
+    const int t = threadIdx.x;
+    const int64_t per = (nblk + 255) / 256;
+    const int64_t b0 = t * per, b1 = b0 + per < nblk ? b0 + per : nblk;
+    unsigned long long tot[3] = {0, 0, 0};
+    for (int64_t i = b0; i < b1; ++i)
+        for (int q = 0; q < 3; ++q) tot[q] += bsum[i * 3 + q];
+    for (int q = 0; q < 3; ++q) s[q][t] = tot[q];
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        unsigned long long y[3];
+        for (int q = 0; q < 3; ++q) y[q] = t >= off ? s[q][t - off] : 0;
         __syncthreads();
-        s_big[t] += c;
-        s_seg[t] += d;
-        s_bigkeys[t] += e;
+        for (int q = 0; q < 3; ++q) s[q][t] += y[q];
         __syncthreads();
     }
-    unsigned long long pb = s_big[t] - big, ps = s_seg[t] - seg;
-    for (int64_t b = b0; b < b1; ++b) {
-        uint32_t c = cnt[b];
-        if (c) seglist[ps++] = (int32_t)b;
-        if (c > kBucketCap) {
-            if ((int64_t)pb < big_max) bigbucket[pb] = (int32_t)b;
-            ++pb;
+    unsigned long long run[3];
+    for (int q = 0; q < 3; ++q) run[q] = s[q][t] - tot[q];
+    for (int64_t i = b0; i < b1; ++i)
+        for (int q = 0; q < 3; ++q) {
+            unsigned long long v = bsum[i * 3 + q];
+            bsum[i * 3 + q] = run[q];
+            run[q] += v;
         }
-    }
-    if (t == 1023) {
-        counters[kCntBigBuckets] = s_big[1023];
-        counters[kCntBigKeys] = s_bigkeys[1023];
-        counters[kCntSegments] = s_seg[1023];
+    if (t == 255) {
+        counters[kCntSegments] = s[0][255];
+        counters[kCntBigBuckets] = s[1][255];
+        counters[kCntBigKeys] = s[2][255];
     }
 }
 
+__global__ void __launch_bounds__(256) k_cls_write(const uint32_t* __restrict__ cnt, int64_t NB, int64_t big_max,
+                                                   const unsigned long long* __restrict__ bsum, int32_t* seglist,
+                                                   int32_t* bigbucket) {
+    __shared__ uint32_t s[2][4];
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint32_t c = b < NB ? cnt[b] : 0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const unsigned long long mne = __ballot(c != 0), mbg = __ballot(c > kBucketCap);
+    if (lane == 0) {
+        s[0][w] = (uint32_t)__popcll(mne);
+        s[1][w] = (uint32_t)__popcll(mbg);
+    }
+    __syncthreads();
+    unsigned long long pne = bsum[blockIdx.x * 3 + 0] + below_in_wave(mne);
+    unsigned long long pbg = bsum[blockIdx.x * 3 + 1] + below_in_wave(mbg);
+    for (int ww = 0; ww < w; ++ww) {
+        pne += s[0][ww];
+        pbg += s[1][ww];
+    }
+    if (c != 0) seglist[pne] = (int32_t)b;
+    if (c > kBucketCap && (int64_t)pbg < big_max) bigbucket[pbg] = (int32_t)b;
+}
+
+size_t classify_ws_words(int64_t NB) { return (size_t)((NB + 255) / 256) * 3; }
+
 hipError_t launch_classify(const uint32_t* d_cnt, int64_t NB, int64_t big_max, int32_t* d_seglist,
-                           int32_t* d_bigbucket, uint64_t* d_counters, hipStream_t st) {
-    hipLaunchKernelGGL(k_classify, dim3(1), dim3(1024), 0, st, d_cnt, NB, big_max, d_seglist, d_bigbucket,
-                       (unsigned long long*)d_counters);
+                           int32_t* d_bigbucket, uint64_t* d_bsum, uint64_t* d_counters, hipStream_t st) {
+    const int64_t nblk = (NB + 255) / 256;
+    unsigned long long* bs = (unsigned long long*)d_bsum;
+    hipLaunchKernelGGL(k_cls_count, dim3((unsigned)nblk), dim3(256), 0, st, d_cnt, NB, bs);
+    hipLaunchKernelGGL(k_cls_scan, dim3(1), dim3(256), 0, st, bs, nblk, (unsigned long long*)d_counters);
+    hipLaunchKernelGGL(k_cls_write, dim3((unsigned)nblk), dim3(256), 0, st, d_cnt, NB, big_max, bs, d_seglist,
+                       d_bigbucket);
     return hipGetLastError();
 }
 

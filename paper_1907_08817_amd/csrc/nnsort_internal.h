@@ -20,6 +20,15 @@ constexpr uint32_t kBucketCap = 4096;
 constexpr int kBucketThreads = 256;
 constexpr int kItemsPerThread = kBucketCap / kBucketThreads;  // 16
 
+// Partition of keys by slot range: tiles of kPartTile keys in input order,
+// 256 digits per pass.
+constexpr int kPartTile = 4096;
+
+// Range id of a slot; keys without a slot sort after every range.
+__device__ __forceinline__ uint32_t range_of(uint32_t slot, uint32_t NB) {
+    return slot == kUnmapped ? NB : (slot >> kLogBucketSlots);
+}
+
 // Counters kept in the workspace (uint64 each).
 enum Counter : int {
     kCntResorted = 0,     // ranges re-sorted whole after the tile merges

@@ -11,14 +11,8 @@
 namespace nns {
 
 constexpr int kPartThreads = 256;
-constexpr int kPartItems = 16;
-constexpr int kPartTile = kPartThreads * kPartItems;  // 4096
+constexpr int kPartItems = kPartTile / kPartThreads;  // 16
 constexpr int kPartWaves = kPartThreads / 64;
-
-// Range id of a slot; keys without a slot sort after every range.
-__device__ __forceinline__ uint32_t range_of(uint32_t slot, uint32_t NB) {
-    return slot == kUnmapped ? NB : (slot >> kLogBucketSlots);
-}
 
 // Digit histogram of one 4096-key tile, stored as hist[tile * 256 + digit].
 __global__ void __launch_bounds__(kPartThreads) k_part_upsweep(const uint32_t* __restrict__ slots, int64_t n,
@@ -311,6 +305,7 @@ __global__ void __launch_bounds__(256) k_big_gather(const int32_t* __restrict__ 
                                                     uint32_t* hist, uint64_t* G) {
     __shared__ uint32_t h[kBucketSlots];
     const int64_t chunk = blockIdx.x;
+    if (chunk >= chunk_pref[big_count]) return;  // the grid is an upper bound
     // big range of this chunk: last i with chunk_pref[i] <= chunk
     int64_t lo = 0, hi = big_count - 1;
     while (lo < hi) {
@@ -346,6 +341,7 @@ __global__ void __launch_bounds__(256) k_big_place(const int32_t* __restrict__ b
                                                    const int64_t* __restrict__ start, const uint64_t* __restrict__ Gs,
                                                    int64_t u_neg, uint64_t* __restrict__ out, int is_f64) {
     const int64_t chunk = blockIdx.x;
+    if (chunk >= chunk_pref[big_count]) return;  // the grid is an upper bound
     int64_t lo = 0, hi = big_count - 1;
     while (lo < hi) {
         int64_t mid = (lo + hi + 1) >> 1;
@@ -406,14 +402,13 @@ size_t partition_hist_words(int64_t n) {
 // result in (K[res], S[res]) as order keys; returns res via *which.
 hipError_t partition_by_range(const uint64_t* in_keys, const uint32_t* in_slots, int64_t n, uint32_t NB, bool is_f64,
                               uint64_t* K0, uint32_t* S0, uint64_t* K1, uint32_t* S1, uint32_t* blockhist,
-                              uint32_t* sums, int* which, hipStream_t st) {
+                              int* which, hipStream_t st) {
     int shifts[4], widths[4];
     uint32_t masks[4];
     int passes = range_passes(NB, shifts, masks, widths);
     const int64_t nblocks = (n + kPartTile - 1) / kPartTile;
     const int64_t nchunks = (nblocks + kScanTiles - 1) / kScanTiles;
     uint32_t* chunk = blockhist + 256 * nblocks;
-    (void)sums;
     uint64_t* Kb[2] = {K0, K1};
     uint32_t* Sb[2] = {S0, S1};
     const uint64_t* kin = in_keys;
