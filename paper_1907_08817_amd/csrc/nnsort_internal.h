@@ -22,7 +22,7 @@ constexpr int kItemsPerThread = kBucketCap / kBucketThreads;  // 16
 
 // Partition of keys by slot range: tiles of kPartTile keys in input order,
 // 256 digits per pass.
-constexpr int kPartTile = 4096;
+constexpr int kPartTile = 2048;
 
 // Range id of a slot; keys without a slot sort after every range.
 __device__ __forceinline__ uint32_t range_of(uint32_t slot, uint32_t NB) {

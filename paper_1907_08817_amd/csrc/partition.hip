@@ -14,7 +14,7 @@ constexpr int kPartThreads = 256;
 constexpr int kPartItems = kPartTile / kPartThreads;  // 16
 constexpr int kPartWaves = kPartThreads / 64;
 
-// Digit histogram of one 4096-key tile, stored as hist[tile * 256 + digit].
+// Digit histogram of one kPartTile-key tile, stored as hist[tile * 256 + digit].
 __global__ void __launch_bounds__(kPartThreads) k_part_upsweep(const uint32_t* __restrict__ slots, int64_t n,
                                                                uint32_t NB, int shift, uint32_t mask,
                                                                uint32_t* blockhist) {
@@ -22,10 +22,20 @@ __global__ void __launch_bounds__(kPartThreads) k_part_upsweep(const uint32_t* _
     h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t t0 = (int64_t)blockIdx.x * kPartTile;
-#pragma unroll 4
-    for (int k = 0; k < kPartItems; ++k) {
-        int64_t i = t0 + k * kPartThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(range_of(slots[i], NB) >> shift) & mask], 1u);
+    if (t0 + kPartTile <= n) {
+        // full tile: 16-byte loads (the tile starts on a 16-byte boundary)
+        const uint4* v = (const uint4*)(slots + t0);
+#pragma unroll
+        for (int k = 0; k < kPartTile / (4 * kPartThreads); ++k) {
+            const uint4 q = v[k * kPartThreads + threadIdx.x];
+            atomicAdd(&h[(range_of(q.x, NB) >> shift) & mask], 1u);
+            atomicAdd(&h[(range_of(q.y, NB) >> shift) & mask], 1u);
+            atomicAdd(&h[(range_of(q.z, NB) >> shift) & mask], 1u);
+            atomicAdd(&h[(range_of(q.w, NB) >> shift) & mask], 1u);
+        }
+    } else {
+        for (int64_t i = t0 + threadIdx.x; i < n; i += kPartThreads)
+            atomicAdd(&h[(range_of(slots[i], NB) >> shift) & mask], 1u);
     }
     __syncthreads();
     blockhist[(int64_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
@@ -62,40 +72,59 @@ __global__ void __launch_bounds__(256) k_part_scan_chunks(uint32_t* hist, int64_
     chunk[(int64_t)blockIdx.x * 256 + d] = run;
 }
 
-__global__ void __launch_bounds__(256) k_part_scan_top(uint32_t* chunk, int64_t nchunks) {
+// Per digit, the exclusive prefix over chunks plus the digit's start.  Four
+// threads per digit, each over a quarter of the chunks, so that many loads
+// are in flight.
+__global__ void __launch_bounds__(1024) k_part_scan_top(uint32_t* chunk, int64_t nchunks) {
+    __shared__ uint32_t s_q[4][256];
+    __shared__ uint32_t s_base[256];
     __shared__ uint32_t wtot[4];
-    const int d = threadIdx.x;
-    const int lane = d & 63, w = d >> 6;
-    uint32_t run = 0;
-    int64_t c = 0;
-    for (; c + 8 <= nchunks; c += 8) {
+    const int t = threadIdx.x;
+    const int d = t & 255, q = t >> 8;
+    const int64_t per = (nchunks + 3) / 4;
+    const int64_t c0 = q * per, c1 = c0 + per < nchunks ? c0 + per : nchunks;
+    uint32_t tot = 0;
+#pragma unroll 16
+    for (int64_t c = c0; c < c1; ++c) tot += chunk[c * 256 + d];
+    s_q[q][d] = tot;
+    __syncthreads();
+    uint32_t pre = 0, all = 0;
+    for (int qq = 0; qq < 4; ++qq) {
+        const uint32_t v = s_q[qq][d];
+        pre += qq < q ? v : 0;
+        all += v;
+    }
+    if (q == 0) {
+        // start of digit d = sum of the totals of digits below it
+        const int lane = d & 63, w = d >> 6;
+        uint32_t inc = all;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(inc, o);
+            if (lane >= o) inc += y;
+        }
+        if (lane == 63) wtot[w] = inc;
+        s_base[d] = inc - all;
+    }
+    __syncthreads();
+    uint32_t run = s_base[d] + pre;
+    for (int ww = 0; ww < (d >> 6); ++ww) run += wtot[ww];
+    int64_t c = c0;
+    for (; c + 8 <= c1; c += 8) {
         uint32_t v[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = chunk[(c + q) * 256 + d];
+        for (int k = 0; k < 8; ++k) v[k] = chunk[(c + k) * 256 + d];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            chunk[(c + q) * 256 + d] = run;
-            run += v[q];
+        for (int k = 0; k < 8; ++k) {
+            chunk[(c + k) * 256 + d] = run;
+            run += v[k];
         }
     }
-    for (; c < nchunks; ++c) {
+    for (; c < c1; ++c) {
         uint32_t v = chunk[c * 256 + d];
         chunk[c * 256 + d] = run;
         run += v;
     }
-    // start of digit d = sum of the totals of digits below it
-    uint32_t inc = run;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = __shfl_up(inc, o);
-        if (lane >= o) inc += y;
-    }
-    if (lane == 63) wtot[w] = inc;
-    __syncthreads();
-    uint32_t base = inc - run;
-    for (int ww = 0; ww < w; ++ww) base += wtot[ww];
-#pragma unroll 8
-    for (int64_t c2 = 0; c2 < nchunks; ++c2) chunk[c2 * 256 + d] += base;
 }
 
 // Tile handled by workgroup `bid`.  Workgroups are dealt to the 8 XCDs in turn
@@ -123,7 +152,7 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long m) {
 // gives its rank.
 //
 // The tile is first reordered by digit in LDS, then written out by
-// consecutive threads, so each digit's run of the tile (16 keys on average)
+// consecutive threads, so each digit's run of the tile (8 keys on average)
 // leaves as a few full cache lines instead of 16 scattered 8-byte writes.
 template <bool STABLE>
 __global__ void __launch_bounds__(kPartThreads) k_part_downsweep(
@@ -420,7 +449,7 @@ hipError_t partition_by_range(const uint64_t* in_keys, const uint32_t* in_slots,
         hipLaunchKernelGGL(k_part_upsweep, dim3((unsigned)nblocks), dim3(kPartThreads), 0, st, sin, n, NB, shifts[p],
                            masks[p], blockhist);
         hipLaunchKernelGGL(k_part_scan_chunks, dim3((unsigned)nchunks), dim3(256), 0, st, blockhist, nblocks, chunk);
-        hipLaunchKernelGGL(k_part_scan_top, dim3(1), dim3(256), 0, st, chunk, nchunks);
+        hipLaunchKernelGGL(k_part_scan_top, dim3(1), dim3(1024), 0, st, chunk, nchunks);
         if (p == 0)
             hipLaunchKernelGGL(k_part_downsweep<false>, dim3((unsigned)nblocks), dim3(kPartThreads), 0, st, kin, sin,
                                ko, so, n, NB, shifts[p], masks[p], widths[p], 1, is_f64 ? 1 : 0, blockhist, chunk,
