@@ -10,7 +10,7 @@
 
 namespace nns {
 
-constexpr int kPartThreads = 256;
+constexpr int kPartThreads = 512;
 constexpr int kPartItems = kPartTile / kPartThreads;  // 16
 constexpr int kPartWaves = kPartThreads / 64;
 
@@ -19,7 +19,7 @@ __global__ void __launch_bounds__(kPartThreads) k_part_upsweep(const uint32_t* _
                                                                uint32_t NB, int shift, uint32_t mask,
                                                                uint32_t* blockhist) {
     __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    if (threadIdx.x < 256) h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t t0 = (int64_t)blockIdx.x * kPartTile;
     if (t0 + kPartTile <= n) {
@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(kPartThreads) k_part_upsweep(const uint32_t* _
             atomicAdd(&h[(range_of(slots[i], NB) >> shift) & mask], 1u);
     }
     __syncthreads();
-    blockhist[(int64_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < 256) blockhist[(int64_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
 }
 
 // Offsets from the tile histograms, in two coalesced passes.  Tiles are taken
@@ -175,7 +175,8 @@ __global__ void __launch_bounds__(kPartThreads) k_part_downsweep(
     const int64_t tile0 = tile * kPartTile;
     const int lim = (int)(n - tile0 < kPartTile ? n - tile0 : kPartTile);
     for (int i = threadIdx.x; i < kPartWaves * 256; i += kPartThreads) (&s_u.cnt[0][0])[i] = 0;
-    gofs[threadIdx.x] = hist[tile * 256 + threadIdx.x] + chunk[(tile / kScanTiles) * 256 + threadIdx.x];
+    if (threadIdx.x < 256)
+        gofs[threadIdx.x] = hist[tile * 256 + threadIdx.x] + chunk[(tile / kScanTiles) * 256 + threadIdx.x];
     __syncthreads();
 
     const uint64_t* __restrict__ kb = kin + tile0;
@@ -209,34 +210,39 @@ __global__ void __launch_bounds__(kPartThreads) k_part_downsweep(
         }
     }
     __syncthreads();
-    // digit d = threadIdx.x: tile total, block-wide exclusive scan over digits,
-    // then (STABLE) each wave's start inside the digit's run
+    // digit d = threadIdx.x < 256 (waves 0..3): tile total, block-wide
+    // exclusive scan over digits, then (STABLE) each wave's start inside the
+    // digit's run
     {
         const uint32_t d = threadIdx.x;
-        uint32_t tot = 0;
-        if (STABLE) {
+        uint32_t tot = 0, inc = 0;
+        if (d < 256) {
+            if (STABLE) {
 #pragma unroll
-            for (int ww = 0; ww < kPartWaves; ++ww) tot += s_u.cnt[ww][d];
-        } else {
-            tot = s_u.cnt[0][d];
-        }
-        uint32_t inc = tot;
+                for (int ww = 0; ww < kPartWaves; ++ww) tot += s_u.cnt[ww][d];
+            } else {
+                tot = s_u.cnt[0][d];
+            }
+            inc = tot;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            uint32_t y = __shfl_up(inc, o);
-            if (lane >= o) inc += y;
+            for (int o = 1; o < 64; o <<= 1) {
+                uint32_t y = __shfl_up(inc, o);
+                if (lane >= o) inc += y;
+            }
+            if (lane == 63) wtot[w] = inc;
         }
-        if (lane == 63) wtot[w] = inc;
         __syncthreads();
-        uint32_t run = inc - tot;
-        for (int ww = 0; ww < w; ++ww) run += wtot[ww];
-        dstart[d] = run;
-        if (STABLE) {
+        if (d < 256) {
+            uint32_t run = inc - tot;
+            for (int ww = 0; ww < w; ++ww) run += wtot[ww];
+            dstart[d] = run;
+            if (STABLE) {
 #pragma unroll
-            for (int ww = 0; ww < kPartWaves; ++ww) {
-                uint32_t c = s_u.cnt[ww][d];
-                s_u.cnt[ww][d] = run;
-                run += c;
+                for (int ww = 0; ww < kPartWaves; ++ww) {
+                    uint32_t c = s_u.cnt[ww][d];
+                    s_u.cnt[ww][d] = run;
+                    run += c;
+                }
             }
         }
     }
