@@ -1,0 +1,207 @@
+"""Parity at the benchmark's full sizes, in the configuration bench.py times:
+device fit (1% sample, 200 Adam steps; 10% for the zipf fit), then one sort
+through the C ABI with the same parameters (m 1.25, eps 3, tau 1024).
+
+At sizes the oracle finishes in seconds (1e6, 1e7) the whole output and every
+round count are compared with oracle.nnsort on the same model.  At 1e8 and 1e9
+the checks are ones that hold at any size, plus sampled outputs recomputed one
+by one from the definition of the result:
+  - the output is the input in ascending totalOrder (a library sort of the
+    input's order keys on the device) and is non-decreasing;
+  - sampled output positions p: the key there has exactly p keys below it in
+    the input or ties around p (counted on the host from the order keys);
+  - round counts: |c_r| = sum_s max(0, k_s - r) from the slot histogram of the
+    same map (the identity of the sorting phase), and at most eps rounds;
+  - the map: FP32 form slots equal the oracle's canonical FP32 slots on a
+    sample of keys; BF16 form F within the a-priori bound of the oracle's FP64
+    evaluation of the bf16-rounded model on a sample of keys.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1907_08817_amd as nn
+from paper_1907_08817_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+MIN64 = -(2 ** 63)
+
+
+def skey(t, is_f64):
+    """Order keys of a device tensor of key bits, shifted so that signed int64
+    comparison is totalOrder (f64) or numeric order (u64)."""
+    o = t.view(torch.int64)
+    if is_f64:
+        return torch.where(o < 0, torch.bitwise_xor(torch.bitwise_not(o), MIN64), o)
+    return torch.bitwise_xor(o, MIN64)
+
+
+def mag_bf16(model, xh):
+    """Sum of the absolute values of every term of F (W2 rounded to bf16),
+    the magnitude that scales the FP32 accumulation error of the BF16 form."""
+    H = model["H"]
+    th = model["theta"].astype(np.float64)
+    w1, b1 = th[:H], th[H:2 * H]
+    W2 = np.array([O.round_bf16(v) for v in th[2 * H:2 * H + H * H]]).reshape(H, H)
+    b2, w3, b3 = th[2 * H + H * H:3 * H + H * H], th[3 * H + H * H:4 * H + H * H], th[-1]
+    a1 = np.abs(w1)[None, :] * np.abs(xh)[:, None] + np.abs(b1)[None, :]
+    a2 = np.abs(b2)[None, :] + a1 @ np.abs(W2).T
+    return np.abs(b3) + a2 @ np.abs(w3)
+
+
+def run_config(cfg, stats_level=2):
+    name, n, H, form, frac = W.CONFIGS[cfg]
+    x = W.make(name, n)
+    is_f64 = x.dtype == np.float64
+    keys = torch.from_numpy(x if is_f64 else x.view(np.int64)).to(DEV)
+    dt = nn.F64 if is_f64 else nn.U64
+    sp = nn.sort_params(form=nn.FORM_BF16 if form == "bf16" else nn.FORM_FP32, stats_level=stats_level)
+    fp = nn.fit_params(hidden=H, sample_frac=frac)
+    ws = nn.alloc_workspace(nn.workspace_size(n, dt, sp, fp), DEV)
+    model = nn.nnsort_fit(keys, fp, ws=ws)
+    out = torch.empty_like(keys)
+    _, st = nn.nnsort_sort_with_model(model, keys, out=out, sp=sp, ws=ws)
+    torch.cuda.synchronize()
+    del ws
+    return x, keys, out, model, sp, st
+
+
+def check_sorted_permutation(keys, out, is_f64):
+    so = skey(out, is_f64)
+    assert bool((so[1:] >= so[:-1]).all().item()), "output not in ascending order"
+    ref = torch.sort(skey(keys, is_f64)).values
+    assert torch.equal(ref, so), "output is not the input in ascending order"
+    del ref
+
+
+def check_sampled_ranks(x, out, is_f64, samples, seed=0):
+    ok = O.order_keys(x)
+    n = x.size
+    rng = np.random.default_rng(seed)
+    pos = np.concatenate([[0, n - 1], rng.integers(0, n, samples)])
+    vals = out[torch.from_numpy(pos).to(DEV)].cpu().numpy()
+    vals = vals if is_f64 else vals.view(np.uint64)
+    vk = O.order_keys(vals)
+    for p, v in zip(pos, vk):
+        below = int(np.count_nonzero(ok < v))
+        upto = int(np.count_nonzero(ok <= v))
+        assert below <= p < upto, (p, below, upto)
+
+
+def check_round_counts(model, keys, sp, st):
+    slots, _ = nn.nnsort_predict(model, keys, sp, want_F=False)
+    unm = int((slots == 0xFFFFFFFF).sum().item())
+    k = torch.bincount(slots[slots != 0xFFFFFFFF])
+    del slots
+    assert 1 <= st["rounds"] <= 3
+    assert st["unmapped"] == unm
+    for r in range(1, st["rounds"] + 1):
+        c = int(torch.clamp(k - r, min=0).sum().item()) + unm
+        p = int((k >= r).sum().item())
+        assert st["collided"][r - 1] == c, (r, st["collided"], c)
+        assert st["placed"][r - 1] == p, (r, st["placed"], p)
+    assert st["residue"] == st["collided"][st["rounds"] - 1]
+
+
+def sample_keys(x, m, seed=1):
+    idx = np.sort(np.random.default_rng(seed).choice(x.size, m, replace=False))
+    return idx, x[idx]
+
+
+# ---------------------------------------------------------------------------
+# 1e6 uniform (FP32, H 32) and 1e7 zipf (FP32 form, H 64, 10% sample fit):
+# whole output and every count against the oracle on the device-fitted model
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("cfg", ["uniform_1e6_fp32_h32", "zipf_u64_1e7_fit_h64"])
+def test_fullsize_matches_oracle(cfg):
+    x, keys, out, model, sp, st = run_config(cfg)
+    md = nn.model_to_dict(model)
+    ref, ost = O.nnsort(x, md, form=O.FORM_FP32C)
+    got = out.cpu().numpy()
+    got = got if x.dtype == np.float64 else got.view(np.uint64)
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+    for k in ("rounds", "collided", "placed", "residue"):
+        assert st[k] == ost[k], (k, st[k], ost[k])
+    assert 0.0 <= st["pos_err"] < 0.05
+
+
+def test_zipf_fit_gradients_at_fitted_weights():
+    """Gradients of the zipf fit (10% sample) at the trained weights, on one
+    batch of its training set: GPU FP32 kernels vs the oracle's FP64 analytic
+    gradient."""
+    name, n, H, form, frac = W.CONFIGS["zipf_u64_1e7_fit_h64"]
+    x = W.make(name, n)
+    keys = torch.from_numpy(x.view(np.int64)).to(DEV)
+    fp = nn.fit_params(hidden=H, sample_frac=frac)
+    model = nn.nnsort_fit(keys, fp)
+    md = nn.model_to_dict(model)
+    _, lo, inv, xh, y = O.fit_sample(x, frac, 0)
+    assert md["lo"] == lo and md["inv_range"] == inv
+    bi = O.batch_indices(3, 0, xh.size, 4096)
+    xb, yb = xh[bi], y[bi].astype(np.float32).astype(np.float64)
+    th = torch.from_numpy(md["theta"]).to(DEV)
+    saved = torch.empty(xb.size * 2 * H, dtype=torch.float32, device=DEV)
+    F = nn.nnsort_mlp_forward(H, th, torch.from_numpy(xb).to(DEV), saved)
+    L, gF = nn.nnsort_loss_grad(F, torch.from_numpy(yb.astype(np.float32)).to(DEV))
+    g = nn.nnsort_mlp_backward(H, th, torch.from_numpy(xb).to(DEV), saved, gF).cpu().numpy().astype(np.float64)
+    Lr, gr = O.loss_grad(md["theta"].astype(np.float64), H, xb, yb)
+    assert abs(float(L.item()) - Lr) <= 1e-4 * max(Lr, 1e-6)
+    assert np.linalg.norm(g - gr) <= 1e-3 * np.linalg.norm(gr), np.linalg.norm(g - gr) / np.linalg.norm(gr)
+
+
+# ---------------------------------------------------------------------------
+# 1e8 lognormal, FP32 form, H 32
+# ---------------------------------------------------------------------------
+def test_fullsize_lognormal_1e8_fp32():
+    x, keys, out, model, sp, st = run_config("lognormal_1e8_fp32_h32")
+    check_sorted_permutation(keys, out, True)
+    check_sampled_ranks(x, out, True, 24)
+    check_round_counts(model, keys, sp, st)
+    idx, xs = sample_keys(x, 1_000_000)
+    slots, _ = nn.nnsort_predict(model, keys, sp, want_F=False)
+    got = slots[torch.from_numpy(idx).to(DEV)].cpu().numpy().astype(np.uint32)
+    md = nn.model_to_dict(model)
+    # a key's slot depends on n through M = m n: evaluate F on the sample and
+    # round with the full n
+    xh, okm = O.translate(xs, md["lo"], md["inv_range"])
+    F = O.eval_F(xh, md, O.FORM_FP32C)
+    ref = O.slots_from_F(F, 1.25 * x.size)
+    ref[~okm] = 0xFFFFFFFF
+    assert np.array_equal(got, ref.astype(np.uint32)), int(np.count_nonzero(got != ref))
+    assert 0.0 <= st["pos_err"] < 0.05
+
+
+# ---------------------------------------------------------------------------
+# 1e8 Gaussian mixture, BF16 form, H 64 (the benchmark's workload)
+# ---------------------------------------------------------------------------
+def test_fullsize_gauss_mix_1e8_bf16():
+    x, keys, out, model, sp, st = run_config("gauss_mix_1e8_bf16_h64")
+    check_sorted_permutation(keys, out, True)
+    check_sampled_ranks(x, out, True, 24)
+    check_round_counts(model, keys, sp, st)
+    md = nn.model_to_dict(model)
+    idx, xs = sample_keys(x, 100_000)
+    _, F = nn.nnsort_predict(model, keys, sp, want_slots=False)
+    got = F[torch.from_numpy(idx).to(DEV)].cpu().numpy()
+    xh, okm = O.translate(xs, md["lo"], md["inv_range"])
+    ref = O.eval_F(xh, md, O.FORM_BF16W)
+    u = 2.0 ** -24
+    k = 3 * md["H"] + 8
+    bound = 2 * k * u / (1 - k * u) * mag_bf16(md, xh)
+    d = np.abs(got - ref)
+    assert np.all(d[okm] <= bound[okm] + 1e-300), float(np.max(d[okm] / bound[okm]))
+    assert 0.0 <= st["pos_err"] < 0.05
+
+
+# ---------------------------------------------------------------------------
+# 1e9 piecewise uniform, device fit + BF16 form, H 64 (end to end at scale)
+# ---------------------------------------------------------------------------
+@pytest.mark.timeout(900)
+def test_fullsize_piecewise_uniform_1e9_bf16():
+    x, keys, out, model, sp, st = run_config("piecewise_uniform_1e9_bf16_h64", stats_level=1)
+    check_sorted_permutation(keys, out, True)
+    check_sampled_ranks(x, out, True, 6)
+    check_round_counts(model, keys, sp, st)
