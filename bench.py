@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--n", type=int, default=0, help="override the key count (testing only)")
     ap.add_argument("--bf16-terms", type=int, default=3)
     ap.add_argument("--no-context", action="store_true", help="skip FP32/radix/CPU context legs")
-    ap.add_argument("--cpu-sample", type=int, default=4_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=20_000_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter calibration)")
     return ap.parse_args()
