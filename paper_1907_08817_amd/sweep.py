@@ -1,0 +1,111 @@
+"""Parameter and distribution-shift sweeps of the GPU NN-sort.
+
+    python -m paper_1907_08817_amd.sweep params [--workload NAME] [--n N]
+    python -m paper_1907_08817_amd.sweep shift  [--n N]
+
+params: one device-fitted model, then sorts with eps = 1..5 (eps = 1 is a
+single mapping round, the SageDB-style one-pass use of the model), m in
+{1.0, 1.25, 1.5, 2.0} and tau in {0, 1024, 1e6}; per setting the rounds run,
+the conflict array after each round as a fraction of n, and the time of each
+phase (Sec. 4, Exp-4: the number of iterations; Sec. 3: the relaxation factor
+m trades slots for conflicts).
+
+shift: a model fitted on uniform keys sorts uniform keys with a growing
+fraction replaced by normal keys (Sec. 4, Exp-3), beside the GPU radix sort of
+the same keys.
+
+Each setting prints one JSON line.  Times are medians of --reps sorts, from
+HIP events on the call's stream, with keys resident in device memory.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import statistics
+import time
+
+import numpy as np
+
+from . import workloads as W
+from . import (F64, U64, FORM_BF16, FORM_FP32, alloc_workspace, fit_params, nnsort_fit, nnsort_radix_sort,
+               nnsort_sort_with_model, sort_params, workspace_size, _lib)
+
+
+def _timed(fn, reps, torch):
+    ts, out = [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return statistics.median(ts), out
+
+
+def _phases(st):
+    return {k: round(v, 3) for k, v in st.items() if k.startswith("t_")}
+
+
+def sweep_params(args, torch, dev):
+    name, n, H, form, frac = W.CONFIGS[args.workload]
+    n = args.n or n
+    x = W.make(name, n)
+    is_f64 = x.dtype == np.float64
+    keys = torch.from_numpy(x if is_f64 else x.view(np.int64)).to(dev)
+    dt = F64 if is_f64 else U64
+    fc = FORM_BF16 if form == "bf16" else FORM_FP32
+    big = sort_params(m=3.0, form=fc)
+    ws = alloc_workspace(workspace_size(n, dt, big, fit_params(hidden=H, sample_frac=frac)), dev)
+    model = nnsort_fit(keys, fit_params(hidden=H, sample_frac=frac), ws=ws)
+    out = torch.empty_like(keys)
+    grid = [(e, 1.25, 1024) for e in range(1, 6)] + [(3, m, 1024) for m in (1.0, 1.5, 2.0)] + \
+           [(3, 1.25, t) for t in (0, 1_000_000)]
+    for eps, m, tau in grid:
+        sp = sort_params(form=fc, eps=eps, m=m, tau=tau, stats_level=1)
+        nnsort_sort_with_model(model, keys, out=out, sp=sp, ws=ws)
+        ms, (_, st) = _timed(lambda: nnsort_sort_with_model(model, keys, out=out, sp=sp, ws=ws), args.reps, torch)
+        print(json.dumps({"sweep": "params", "workload": args.workload, "n": n, "eps": eps, "m": m, "tau": tau,
+                          "rounds": st["rounds"], "conflict_frac": [round(c / n, 5) for c in st["collided"][:st["rounds"]]],
+                          "residue_frac": round(st["residue"] / n, 5), "ms": round(ms, 3),
+                          "gkeys_s": round(n / ms / 1e6, 3), "phases": _phases(st)}), flush=True)
+
+
+def sweep_shift(args, torch, dev):
+    n = args.n or 100_000_000
+    fx = W.uniform(n, seed=0)
+    fkeys = torch.from_numpy(fx).to(dev)
+    fp = fit_params(hidden=32, sample_frac=0.01)
+    sp = sort_params(form=FORM_FP32, stats_level=1)
+    ws = alloc_workspace(workspace_size(n, F64, sp, fp), dev)
+    model = nnsort_fit(fkeys, fp, ws=ws)
+    del fkeys
+    rws = alloc_workspace(_lib().nnsort_radix_workspace_size(n), dev)
+    for noise in (0.0, 0.05, 0.1, 0.2, 0.3, 0.4, 0.5):
+        x = W.noisy_uniform(n, noise, seed=5)
+        keys = torch.from_numpy(x).to(dev)
+        out = torch.empty_like(keys)
+        nnsort_sort_with_model(model, keys, out=out, sp=sp, ws=ws)
+        ms, (_, st) = _timed(lambda: nnsort_sort_with_model(model, keys, out=out, sp=sp, ws=ws), args.reps, torch)
+        rms, _ = _timed(lambda: nnsort_radix_sort(keys, out=out, ws=rws), args.reps, torch)
+        print(json.dumps({"sweep": "shift", "n": n, "noise": noise, "rounds": st["rounds"],
+                          "conflict_frac": [round(c / n, 5) for c in st["collided"][:st["rounds"]]],
+                          "residue_frac": round(st["residue"] / n, 5), "ms": round(ms, 3),
+                          "gkeys_s": round(n / ms / 1e6, 3), "radix_ms": round(rms, 3),
+                          "radix_gkeys_s": round(n / rms / 1e6, 3), "phases": _phases(st)}), flush=True)
+        del keys, out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=["params", "shift"])
+    ap.add_argument("--workload", default="gauss_mix_1e8_bf16_h64")
+    ap.add_argument("--n", type=int, default=0)
+    ap.add_argument("--reps", type=int, default=5)
+    args = ap.parse_args()
+    import torch
+    dev = torch.device("cuda:0")
+    (sweep_params if args.what == "params" else sweep_shift)(args, torch, dev)
+
+
+if __name__ == "__main__":
+    main()

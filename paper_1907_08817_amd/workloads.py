@@ -72,6 +72,19 @@ def piecewise_uniform(n: int, seed: int = 4, breakpoints: int = 10_000,
     return out
 
 
+def noisy_uniform(n: int, noise: float, seed: int = 5, mu: float = 0.5, sd: float = 0.1) -> np.ndarray:
+    """Uniform [0, 1) keys with a fraction `noise` replaced by Normal(mu, sd)
+    keys (the paper's changing-distribution experiment, Sec. 4, Exp-3: a model
+    trained on uniform data sorts uniform + normal mixes)."""
+    rng = np.random.default_rng(seed)
+    x = rng.random(n)
+    k = int(round(noise * n))
+    if k:
+        pos = rng.choice(n, k, replace=False)
+        x[pos] = rng.normal(mu, sd, k)
+    return x
+
+
 def make(name: str, n: int, seed: int | None = None) -> np.ndarray:
     fn = {"uniform": uniform, "lognormal": lognormal, "gauss_mix": gauss_mix,
           "zipf_u64": zipf_u64, "piecewise_uniform": piecewise_uniform}[name]

@@ -373,3 +373,33 @@ def test_errors_reported():
         nn.nnsort_sort_with_model(m, x, ws=nn.alloc_workspace(1024))
     with pytest.raises(nn.NNSortError):
         nn.nnsort_sort_with_model(m, x, sp=nn.sort_params(eps=9))
+
+
+# ---------------------------------------------------------------------------
+# the procedure's parameters (m, eps, tau), and a model that does not fit the
+# data (Sec. 4, Exp-3 and Exp-4)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("m,eps,tau", [(1.0, 1, 1024), (1.0, 3, 0), (1.5, 2, 1024), (2.0, 5, 1024),
+                                       (1.25, 1, 0), (3.0, 8, 100_000)])
+def test_sort_parameters_match_oracle(m, eps, tau):
+    x = W.lognormal(300_000, seed=21)
+    model = O.fit(x, H=32, sample_frac=0.01, batch=4096, steps=5)
+    out, st = gpu_sort(x, model, m=m, eps=eps, tau=tau)
+    ref, ost = O.nnsort(x, model, m=m, eps=eps, tau=tau)
+    assert_same_bits(out, ref)
+    for k in ("rounds", "collided", "placed", "residue"):
+        assert st[k] == ost[k], (k, st[k], ost[k])
+
+
+@pytest.mark.parametrize("noise", [0.0, 0.1, 0.5])
+def test_model_fitted_on_other_data(noise):
+    """A model fitted on uniform keys sorts uniform + normal mixes exactly;
+    only the conflict counts grow with the mismatch."""
+    fit_x = W.uniform(200_000, seed=3)
+    model = O.fit(fit_x, H=32, sample_frac=0.05, batch=4096, steps=5)
+    x = W.noisy_uniform(250_000, noise, seed=9)
+    out, st = gpu_sort(x, model)
+    ref, ost = O.nnsort(x, model)
+    assert_same_bits(out, ref)
+    for k in ("rounds", "collided", "placed", "residue"):
+        assert st[k] == ost[k], (k, st[k], ost[k])
