@@ -134,18 +134,23 @@ def default_params() -> tuple[SortParams, FitParams]:
     return sp, fp
 
 
+def _set_fields(st, kw):
+    names = {f[0] for f in type(st)._fields_}
+    for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"{type(st).__name__} has no field {k!r}")
+        setattr(st, k, v)
+    return st
+
+
 def sort_params(**kw) -> SortParams:
     sp, _ = default_params()
-    for k, v in kw.items():
-        setattr(sp, k, v)
-    return sp
+    return _set_fields(sp, kw)
 
 
 def fit_params(**kw) -> FitParams:
     _, fp = default_params()
-    for k, v in kw.items():
-        setattr(fp, k, v)
-    return fp
+    return _set_fields(fp, kw)
 
 
 def model_from_dict(d: dict) -> Model:

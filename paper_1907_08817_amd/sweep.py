@@ -2,6 +2,7 @@
 
     python -m paper_1907_08817_amd.sweep params [--workload NAME] [--n N]
     python -m paper_1907_08817_amd.sweep shift  [--n N]
+    python -m paper_1907_08817_amd.sweep fit    [--workload NAME] [--n N]
 
 params: one device-fitted model, then sorts with eps = 1..5 (eps = 1 is a
 single mapping round, the SageDB-style one-pass use of the model), m in
@@ -13,6 +14,11 @@ m trades slots for conflicts).
 shift: a model fitted on uniform keys sorts uniform keys with a growing
 fraction replaced by normal keys (Sec. 4, Exp-3), beside the GPU radix sort of
 the same keys.
+
+fit: the device fit under three recipes -- MSE with batches of 65,536 (the
+default), and the paper's Huber loss (Sec. 4.1, Eq. (loss)) with batches of
+65,536 and of 128 -- with the fit time, the batch loss before the first and
+after the last step, and the sort that the fitted model gives.
 
 Each setting prints one JSON line.  Times are medians of --reps sorts, from
 HIP events on the call's stream, with keys resident in device memory.
@@ -95,16 +101,40 @@ def sweep_shift(args, torch, dev):
         del keys, out
 
 
+def sweep_fit(args, torch, dev):
+    name, n, H, form, frac = W.CONFIGS[args.workload]
+    n = args.n or n
+    x = W.make(name, n)
+    is_f64 = x.dtype == np.float64
+    keys = torch.from_numpy(x if is_f64 else x.view(np.int64)).to(dev)
+    dt = F64 if is_f64 else U64
+    fc = FORM_BF16 if form == "bf16" else FORM_FP32
+    sp = sort_params(form=fc, stats_level=1)
+    ws = alloc_workspace(workspace_size(n, dt, sp, fit_params(hidden=H, sample_frac=frac)), dev)
+    out = torch.empty_like(keys)
+    for loss, delta, batch in ((0, 1.0, 65536), (1, 0.01, 65536), (1, 0.01, 128)):
+        fp = fit_params(hidden=H, sample_frac=frac, loss=loss, huber_delta=delta, batch=batch)
+        fit_ms, (model, hist) = _timed(lambda: nnsort_fit(keys, fp, ws=ws, history=True), 1, torch)
+        nnsort_sort_with_model(model, keys, out=out, sp=sp, ws=ws)
+        ms, (_, st) = _timed(lambda: nnsort_sort_with_model(model, keys, out=out, sp=sp, ws=ws), args.reps, torch)
+        print(json.dumps({"sweep": "fit", "workload": args.workload, "n": n, "loss": "huber" if loss else "mse",
+                          "delta": delta, "batch": batch, "steps": fp.steps, "fit_ms": round(fit_ms, 2),
+                          "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
+                          "conflict_frac": [round(c / n, 5) for c in st["collided"][:st["rounds"]]],
+                          "residue_frac": round(st["residue"] / n, 5), "dense_range_keys": st["big_bucket_keys"],
+                          "ms": round(ms, 3), "gkeys_s": round(n / ms / 1e6, 3)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["params", "shift"])
+    ap.add_argument("what", choices=["params", "shift", "fit"])
     ap.add_argument("--workload", default="gauss_mix_1e8_bf16_h64")
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--reps", type=int, default=5)
     args = ap.parse_args()
     import torch
     dev = torch.device("cuda:0")
-    (sweep_params if args.what == "params" else sweep_shift)(args, torch, dev)
+    {"params": sweep_params, "shift": sweep_shift, "fit": sweep_fit}[args.what](args, torch, dev)
 
 
 if __name__ == "__main__":

@@ -403,3 +403,20 @@ def test_model_fitted_on_other_data(noise):
     assert_same_bits(out, ref)
     for k in ("rounds", "collided", "placed", "residue"):
         assert st[k] == ost[k], (k, st[k], ost[k])
+
+
+@pytest.mark.parametrize("batch,delta", [(128, 0.01), (4096, 0.05)])
+def test_huber_fit_tracks_oracle(batch, delta):
+    """The paper's training recipe (Sec. 4.1, Eq. (loss)): Huber loss, small
+    batches.  Same Philox sample, initial weights and batches on both sides:
+    the first loss agrees to FP32 rounding, both fits lower the loss, and the
+    final losses stay close."""
+    x = W.uniform(100_000, seed=8)
+    kw = dict(sample_frac=0.2, batch=batch, steps=40, init=0, lr=1e-2, seed=3, loss=1, delta=delta)
+    fp = nn.fit_params(hidden=16, sample_frac=kw["sample_frac"], batch=batch, steps=kw["steps"], init=0,
+                       lr=kw["lr"], seed=3, loss=1, huber_delta=delta)
+    m, hist = nn.nnsort_fit(to_dev(x), fp, history=True)
+    ref, rhist = O.fit(x, H=16, return_history=True, **kw)
+    assert abs(hist[0] - rhist[0]) <= 1e-5 * max(1.0, rhist[0])
+    assert hist[-1] < 0.7 * hist[0] and rhist[-1] < 0.7 * rhist[0]
+    assert abs(hist[-1] - rhist[-1]) <= 0.1 * rhist[-1] + 1e-7

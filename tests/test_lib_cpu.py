@@ -107,3 +107,11 @@ def test_model_file_round_trip(tmp_path):
         nn.model_load(path)
     with pytest.raises(nn.NNSortError):
         nn.model_load(str(tmp_path / "missing"))
+
+
+def test_parameter_names_are_checked():
+    with pytest.raises(TypeError):
+        nn.sort_params(epsilon=3)
+    with pytest.raises(TypeError):
+        nn.fit_params(delta=0.1)
+    assert nn.fit_params(huber_delta=0.25).huber_delta == 0.25
