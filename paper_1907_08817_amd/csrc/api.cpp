@@ -16,14 +16,20 @@ namespace nns {
 hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
 hipError_t launch_classify(const uint32_t* d_cnt, int64_t NB, int64_t big_max, int32_t* d_seglist,
-                           int32_t* d_bigbucket, uint64_t* d_bsum, uint64_t* d_counters, hipStream_t st);
+                           int32_t* d_bigbucket, int32_t* d_halflist, uint64_t* d_bsum, uint64_t* d_counters,
+                           hipStream_t st);
 size_t classify_ws_words(int64_t NB);
 hipError_t launch_big_counts(const uint32_t* d_hist, int64_t big_count, int eps, uint64_t* d_counters,
                              hipStream_t st);
 size_t polish_part_words(int64_t NB);
-hipError_t launch_bucket_polish(const uint32_t* d_cnt, const int64_t* d_start, int64_t NB, const uint64_t* d_K,
-                                const uint32_t* d_S, int eps, uint64_t* d_out, int64_t base, bool is_f64,
-                                uint32_t* d_part, uint64_t* d_counters, hipStream_t st);
+hipError_t launch_polish_small(const int64_t* d_start, int64_t NB, const uint64_t* d_K, const uint32_t* d_S, int eps,
+                               uint64_t* d_out, int64_t base, bool is_f64, uint32_t* d_part, uint64_t* d_counters,
+                               hipStream_t st);
+hipError_t launch_polish_half(const int64_t* d_start, const int32_t* d_halflist, int64_t n_half, const uint64_t* d_K,
+                              const uint32_t* d_S, int eps, uint64_t* d_out, int64_t base, bool is_f64,
+                              uint32_t* d_part, uint64_t* d_counters, hipStream_t st);
+hipError_t launch_sum_parts(const uint32_t* d_part, const uint32_t* d_cnt, int64_t NB, int eps, uint64_t* d_counters,
+                            hipStream_t st);
 hipError_t launch_boundary_plan(const uint64_t* d_out, bool is_f64, int64_t base, const int64_t* d_start,
                                 const int32_t* d_seglist, int64_t K, void* d_zones, uint64_t* d_counters,
                                 hipStream_t st);
@@ -160,6 +166,7 @@ SortPlan plan_sort(int64_t n, double m) {
     p.off_psums = take(classify_ws_words(p.NB) * 8);
     p.off_seglist = take((size_t)p.NB * 4);
     p.off_bigbucket = take((size_t)p.big_max * 4);
+    p.off_halflist = take((size_t)p.NB * 4);
     p.off_bigpref = take((size_t)(p.big_max + 1) * 2 * 8);
     p.off_part = take(polish_part_words(p.NB) * 4);
     p.off_zones = take((size_t)p.NB * zone_bytes());
@@ -262,6 +269,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     uint64_t* clsum = (uint64_t*)(ws + P.off_psums);
     int32_t* seglist = (int32_t*)(ws + P.off_seglist);
     int32_t* bigbucket = (int32_t*)(ws + P.off_bigbucket);
+    int32_t* halflist = (int32_t*)(ws + P.off_halflist);
     int64_t* chunk_pref = (int64_t*)(ws + P.off_bigpref);
     int64_t* gpref = chunk_pref + (P.big_max + 1);
     uint32_t* part = (uint32_t*)(ws + P.off_part);
@@ -308,7 +316,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     const uint64_t* Ks = which ? K1 : K0;
     const uint32_t* Ss = which ? slots0 : S0;
     NNS_HIP(launch_range_bounds(Ss, n, NB, start, cnt, st));
-    NNS_HIP(launch_classify(cnt, P.NB, P.big_max, seglist, bigbucket, clsum, counters, st));
+    NNS_HIP(launch_classify(cnt, P.NB, P.big_max, seglist, bigbucket, halflist, clsum, counters, st));
     NNS_HIP(launch_count_neg(Ks, start, NB, n, counters + kCntUnmappedNeg, st));
     uint64_t c[kNumCounters];
     int64_t first_unmapped = 0;
@@ -339,7 +347,10 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     ev.mark(2);
 
     // ---- rounds + polish of each slot range in LDS, straight to out ----
-    NNS_HIP(launch_bucket_polish(cnt, start, P.NB, Ks, Ss, eps, out, u_neg, is_f64, part, counters, st));
+    NNS_HIP(launch_polish_half(start, halflist, (int64_t)c[kCntHalfFull], Ks, Ss, eps, out, u_neg, is_f64, part,
+                               counters, st));
+    NNS_HIP(launch_polish_small(start, P.NB, Ks, Ss, eps, out, u_neg, is_f64, part, counters, st));
+    NNS_HIP(launch_sum_parts(part, cnt, P.NB, eps, counters, st));
     ev.mark(3);
 
     // ---- dense ranges and keys without a slot: conventional sort, placed ----

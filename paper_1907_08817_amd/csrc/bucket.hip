@@ -68,14 +68,20 @@ __device__ __forceinline__ uint32_t below_in_wave(unsigned long long m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// Ranges of more than kHalfCap keys (and at most kBucketCap) are polished by
+// the larger-LDS variant, from a list.
+constexpr uint32_t kHalfCap = kBucketCap / 2;
+constexpr int kClsQ = 4;  // per block: non-empty, dense, dense keys, half-full
+
 __global__ void __launch_bounds__(256) k_cls_count(const uint32_t* __restrict__ cnt, int64_t NB,
                                                    unsigned long long* bsum) {
-    __shared__ unsigned long long s[3][4];
+    __shared__ unsigned long long s[kClsQ][4];
     const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const uint32_t c = b < NB ? cnt[b] : 0;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     unsigned long long ne = __popcll(__ballot(c != 0));
     unsigned long long bg = __popcll(__ballot(c > kBucketCap));
+    unsigned long long md = __popcll(__ballot(c > kHalfCap && c <= kBucketCap));
     unsigned long long bk = c > kBucketCap ? c : 0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) bk += __shfl_xor(bk, o);
@@ -83,80 +89,88 @@ __global__ void __launch_bounds__(256) k_cls_count(const uint32_t* __restrict__ 
         s[0][w] = ne;
         s[1][w] = bg;
         s[2][w] = bk;
+        s[3][w] = md;
     }
     __syncthreads();
-    if (threadIdx.x < 3)
-        bsum[blockIdx.x * 3 + threadIdx.x] =
+    if (threadIdx.x < kClsQ)
+        bsum[blockIdx.x * kClsQ + threadIdx.x] =
             s[threadIdx.x][0] + s[threadIdx.x][1] + s[threadIdx.x][2] + s[threadIdx.x][3];
 }
 
 // Exclusive scan of the per-block counts (in place); totals to the counters.
 __global__ void __launch_bounds__(256) k_cls_scan(unsigned long long* bsum, int64_t nblk,
                                                   unsigned long long* counters) {
-    __shared__ unsigned long long s[3][256];
+    __shared__ unsigned long long s[kClsQ][256];
     const int t = threadIdx.x;
     const int64_t per = (nblk + 255) / 256;
     const int64_t b0 = t * per, b1 = b0 + per < nblk ? b0 + per : nblk;
-    unsigned long long tot[3] = {0, 0, 0};
+    unsigned long long tot[kClsQ] = {0, 0, 0, 0};
     for (int64_t i = b0; i < b1; ++i)
-        for (int q = 0; q < 3; ++q) tot[q] += bsum[i * 3 + q];
-    for (int q = 0; q < 3; ++q) s[q][t] = tot[q];
+        for (int q = 0; q < kClsQ; ++q) tot[q] += bsum[i * kClsQ + q];
+    for (int q = 0; q < kClsQ; ++q) s[q][t] = tot[q];
     __syncthreads();
     for (int off = 1; off < 256; off <<= 1) {
-        unsigned long long y[3];
-        for (int q = 0; q < 3; ++q) y[q] = t >= off ? s[q][t - off] : 0;
+        unsigned long long y[kClsQ];
+        for (int q = 0; q < kClsQ; ++q) y[q] = t >= off ? s[q][t - off] : 0;
         __syncthreads();
-        for (int q = 0; q < 3; ++q) s[q][t] += y[q];
+        for (int q = 0; q < kClsQ; ++q) s[q][t] += y[q];
         __syncthreads();
     }
-    unsigned long long run[3];
-    for (int q = 0; q < 3; ++q) run[q] = s[q][t] - tot[q];
+    unsigned long long run[kClsQ];
+    for (int q = 0; q < kClsQ; ++q) run[q] = s[q][t] - tot[q];
     for (int64_t i = b0; i < b1; ++i)
-        for (int q = 0; q < 3; ++q) {
-            unsigned long long v = bsum[i * 3 + q];
-            bsum[i * 3 + q] = run[q];
+        for (int q = 0; q < kClsQ; ++q) {
+            unsigned long long v = bsum[i * kClsQ + q];
+            bsum[i * kClsQ + q] = run[q];
             run[q] += v;
         }
     if (t == 255) {
         counters[kCntSegments] = s[0][255];
         counters[kCntBigBuckets] = s[1][255];
         counters[kCntBigKeys] = s[2][255];
+        counters[kCntHalfFull] = s[3][255];
     }
 }
 
 __global__ void __launch_bounds__(256) k_cls_write(const uint32_t* __restrict__ cnt, int64_t NB, int64_t big_max,
                                                    const unsigned long long* __restrict__ bsum, int32_t* seglist,
-                                                   int32_t* bigbucket) {
-    __shared__ uint32_t s[2][4];
+                                                   int32_t* bigbucket, int32_t* halflist) {
+    __shared__ uint32_t s[3][4];
     const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const uint32_t c = b < NB ? cnt[b] : 0;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const unsigned long long mne = __ballot(c != 0), mbg = __ballot(c > kBucketCap);
+    const bool half = c > kHalfCap && c <= kBucketCap;
+    const unsigned long long mne = __ballot(c != 0), mbg = __ballot(c > kBucketCap), mhf = __ballot(half);
     if (lane == 0) {
         s[0][w] = (uint32_t)__popcll(mne);
         s[1][w] = (uint32_t)__popcll(mbg);
+        s[2][w] = (uint32_t)__popcll(mhf);
     }
     __syncthreads();
-    unsigned long long pne = bsum[blockIdx.x * 3 + 0] + below_in_wave(mne);
-    unsigned long long pbg = bsum[blockIdx.x * 3 + 1] + below_in_wave(mbg);
+    unsigned long long pne = bsum[blockIdx.x * kClsQ + 0] + below_in_wave(mne);
+    unsigned long long pbg = bsum[blockIdx.x * kClsQ + 1] + below_in_wave(mbg);
+    unsigned long long phf = bsum[blockIdx.x * kClsQ + 3] + below_in_wave(mhf);
     for (int ww = 0; ww < w; ++ww) {
         pne += s[0][ww];
         pbg += s[1][ww];
+        phf += s[2][ww];
     }
     if (c != 0) seglist[pne] = (int32_t)b;
     if (c > kBucketCap && (int64_t)pbg < big_max) bigbucket[pbg] = (int32_t)b;
+    if (half) halflist[phf] = (int32_t)b;
 }
 
-size_t classify_ws_words(int64_t NB) { return (size_t)((NB + 255) / 256) * 3; }
+size_t classify_ws_words(int64_t NB) { return (size_t)((NB + 255) / 256) * kClsQ; }
 
 hipError_t launch_classify(const uint32_t* d_cnt, int64_t NB, int64_t big_max, int32_t* d_seglist,
-                           int32_t* d_bigbucket, uint64_t* d_bsum, uint64_t* d_counters, hipStream_t st) {
+                           int32_t* d_bigbucket, int32_t* d_halflist, uint64_t* d_bsum, uint64_t* d_counters,
+                           hipStream_t st) {
     const int64_t nblk = (NB + 255) / 256;
     unsigned long long* bs = (unsigned long long*)d_bsum;
     hipLaunchKernelGGL(k_cls_count, dim3((unsigned)nblk), dim3(256), 0, st, d_cnt, NB, bs);
     hipLaunchKernelGGL(k_cls_scan, dim3(1), dim3(256), 0, st, bs, nblk, (unsigned long long*)d_counters);
     hipLaunchKernelGGL(k_cls_write, dim3((unsigned)nblk), dim3(256), 0, st, d_cnt, NB, big_max, bs, d_seglist,
-                       d_bigbucket);
+                       d_bigbucket, d_halflist);
     return hipGetLastError();
 }
 
@@ -237,7 +251,6 @@ size_t polish_part_words(int64_t NB) { return (size_t)NB * kPartStride; }
 // ---------------------------------------------------------------------------
 // per-range rounds + polish in LDS
 // ---------------------------------------------------------------------------
-constexpr int kItems = kItemsPerThread;  // keys per thread (16)
 constexpr int kTile = 8;                 // keys per repair tile
 constexpr int kMaxTileRounds = 8;        // odd-even tile rounds before the whole-range re-sort
 constexpr int kSlotsPer = kBucketSlots / kBucketThreads;  // slots owned per thread (8)
@@ -289,8 +302,9 @@ __device__ __forceinline__ int merge_split(const uint64_t* a, int na, const uint
     return lo;
 }
 
+template <int CAP>
 struct BucketSmem {
-    uint64_t keys[kBucketCap];
+    uint64_t keys[CAP];
     // per slot, 16 bits: its key count, then its first position; slot 2w in
     // the low half of word w, slot 2w + 1 in the high half
     uint32_t off[kBucketSlots / 2];
@@ -306,7 +320,8 @@ __device__ __forceinline__ uint32_t half_of(uint32_t word, uint32_t s) { return 
 // boundary is out of order (keys only move as far as f misplaced them), and a
 // bitonic sort of the whole range if that does not settle.  Returns true if
 // the bitonic sort ran.
-__device__ bool repair_range(BucketSmem& sm, uint32_t cnt, int tid) {
+template <int CAP>
+__device__ bool repair_range(BucketSmem<CAP>& sm, uint32_t cnt, int tid) {
     const int ntiles = (int)((cnt + kTile - 1) / kTile);
     for (int i = (int)cnt + tid; i < ntiles * kTile; i += kBucketThreads) sm.keys[i] = ~0ull;
     __syncthreads();
@@ -365,21 +380,25 @@ __device__ bool repair_range(BucketSmem& sm, uint32_t cnt, int tid) {
     return true;
 }
 
-// One workgroup per slot range of at most kBucketCap keys.  K / Sl: the
+// One workgroup per slot range with LO < count <= CAP keys (CAP a power of
+// two; the LDS a workgroup needs grows with CAP, so ranges of up to half the
+// capacity run in a variant with twice as many workgroups per CU).  K / Sl: the
 // range-partitioned order keys and slots (range b at [start[b], start[b+1]));
 // the range's keys are written as bit patterns to out[base + start[b] ...].
+template <int CAP, int LO>
 __global__ void __launch_bounds__(kBucketThreads) k_bucket_polish(
-    const int64_t* __restrict__ start, const uint64_t* __restrict__ K, const uint32_t* __restrict__ Sl, int eps,
-    uint64_t* __restrict__ out, int64_t base, int is_f64, uint32_t* __restrict__ part,
-    unsigned long long* counters) {
-    __shared__ BucketSmem sm;
+    const int64_t* __restrict__ start, const int32_t* __restrict__ list, const uint64_t* __restrict__ K,
+    const uint32_t* __restrict__ Sl, int eps, uint64_t* __restrict__ out, int64_t base, int is_f64,
+    uint32_t* __restrict__ part, unsigned long long* counters) {
+    constexpr int kItems = CAP / kBucketThreads;
+    __shared__ BucketSmem<CAP> sm;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = tid >> 6;
-    const int64_t b = blockIdx.x;
+    const int64_t b = list ? list[blockIdx.x] : blockIdx.x;
     const int64_t s0 = start[b];
     const uint32_t cnt = (uint32_t)(start[b + 1] - s0);
-    if (cnt == 0 || cnt > kBucketCap) return;  // empty, or handled by the dense-range path
+    if (cnt <= (uint32_t)LO || cnt > (uint32_t)CAP) return;  // another variant's, or the dense-range path's
     const uint64_t* rk = K + s0;
     const uint32_t* rs = Sl + s0;
 
@@ -530,14 +549,33 @@ __global__ void __launch_bounds__(kBucketThreads) k_bucket_polish(
     for (uint32_t i = tid; i < cnt; i += kBucketThreads) o[i] = order_key_inverse(sm.keys[i], is_f64);
 }
 
-hipError_t launch_bucket_polish(const uint32_t* d_cnt, const int64_t* d_start, int64_t NB, const uint64_t* d_K,
-                                const uint32_t* d_S, int eps, uint64_t* d_out, int64_t base, bool is_f64,
-                                uint32_t* d_part, uint64_t* d_counters, hipStream_t st) {
+// Ranges of at most kHalfCap keys: one workgroup per range id (others exit
+// at once).
+hipError_t launch_polish_small(const int64_t* d_start, int64_t NB, const uint64_t* d_K, const uint32_t* d_S, int eps,
+                               uint64_t* d_out, int64_t base, bool is_f64, uint32_t* d_part, uint64_t* d_counters,
+                               hipStream_t st) {
     if (NB <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bucket_polish, dim3((unsigned)NB), dim3(kBucketThreads), 0, st, d_start, d_K, d_S, eps,
-                       d_out, base, is_f64 ? 1 : 0, d_part, (unsigned long long*)d_counters);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    static_assert(kBucketCap == 2 * kHalfCap && kHalfCap == 2048, "polish variants");
+    hipLaunchKernelGGL((k_bucket_polish<2048, 0>), dim3((unsigned)NB), dim3(kBucketThreads), 0, st, d_start,
+                       nullptr, d_K, d_S, eps, d_out, base, is_f64 ? 1 : 0, d_part, (unsigned long long*)d_counters);
+    return hipGetLastError();
+}
+
+// The n_half ranges listed in d_halflist: the full-capacity variant.
+hipError_t launch_polish_half(const int64_t* d_start, const int32_t* d_halflist, int64_t n_half, const uint64_t* d_K,
+                              const uint32_t* d_S, int eps, uint64_t* d_out, int64_t base, bool is_f64,
+                              uint32_t* d_part, uint64_t* d_counters, hipStream_t st) {
+    if (n_half <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_bucket_polish<4096, 2048>), dim3((unsigned)n_half), dim3(kBucketThreads), 0, st, d_start,
+                       d_halflist, d_K, d_S, eps, d_out, base, is_f64 ? 1 : 0, d_part,
+                       (unsigned long long*)d_counters);
+    return hipGetLastError();
+}
+
+// The ranges' round counts into the counters (after both variants).
+hipError_t launch_sum_parts(const uint32_t* d_part, const uint32_t* d_cnt, int64_t NB, int eps, uint64_t* d_counters,
+                            hipStream_t st) {
+    if (NB <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(NB, 256, 256)), dim3(256), 0, st, d_part, d_cnt, NB, eps,
                        (unsigned long long*)d_counters);
     return hipGetLastError();

@@ -44,6 +44,7 @@ enum Counter : int {
     kCntPosErrSum = 25,   // double bits: sum |F n - p|
     kCntPosErrCnt = 26,
     kCntUnmappedNeg = 27, // keys with no slot whose order key has the top bit clear
+    kCntHalfFull = 28,    // ranges of more than half the LDS capacity (and at most all of it)
     kNumCounters = 32
 };
 
@@ -79,7 +80,7 @@ struct SortPlan {
     int64_t NB;        // buckets
     int64_t big_max;   // capacity for big buckets' slot histograms
     size_t off_counters, off_cnt, off_start, off_slots0, off_S0, off_K0, off_K1, off_phist, off_psums,
-        off_seglist, off_bigbucket, off_bigpref, off_part, off_zones, off_G, off_radix, off_big_hist, off_model,
+        off_seglist, off_bigbucket, off_halflist, off_bigpref, off_part, off_zones, off_G, off_radix, off_big_hist, off_model,
         total;
     size_t radix_bytes;
 };
