@@ -179,31 +179,45 @@ hipError_t launch_classify(const uint32_t* d_cnt, int64_t NB, int64_t big_max, i
 // ---------------------------------------------------------------------------
 // Dense ranges: k_s from their slot histograms.  Round r stores
 // min(k_s, r) - min(k_s, r - 1) keys of slot s and leaves max(0, k_s - r).
+// Sum of v over the workgroup's threads, one value per wave combined in LDS.
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
 __global__ void __launch_bounds__(256) k_big_counts(const uint32_t* __restrict__ hist, int64_t total, int eps,
                                                     unsigned long long* counters) {
-    __shared__ unsigned long long s_col[NNSORT_MAX_EPS], s_pl[NNSORT_MAX_EPS];
-    if (threadIdx.x < NNSORT_MAX_EPS) {
-        s_col[threadIdx.x] = 0;
-        s_pl[threadIdx.x] = 0;
-    }
-    __syncthreads();
+    __shared__ unsigned long long s_w[4][2 * NNSORT_MAX_EPS];
     unsigned long long col[NNSORT_MAX_EPS] = {0}, pl[NNSORT_MAX_EPS] = {0};
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
         uint32_t k = hist[i];
-        for (int r = 1; r <= eps; ++r) {
+#pragma unroll
+        for (int r = 1; r <= NNSORT_MAX_EPS; ++r) {
+            if (r > eps) break;
             col[r - 1] += k > (uint32_t)r ? k - r : 0;
             pl[r - 1] += k >= (uint32_t)r ? 1 : 0;
         }
     }
-    for (int r = 0; r < eps; ++r) {
-        atomicAdd(&s_col[r], col[r]);
-        atomicAdd(&s_pl[r], pl[r]);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int r = 0; r < NNSORT_MAX_EPS; ++r) {
+        if (r >= eps) break;
+        const unsigned long long a = wave_sum(col[r]), b = wave_sum(pl[r]);
+        if (lane == 0) {
+            s_w[w][r] = a;
+            s_w[w][NNSORT_MAX_EPS + r] = b;
+        }
     }
     __syncthreads();
     if (threadIdx.x < (unsigned)eps) {
-        atomicAdd(&counters[kCntCollided + threadIdx.x], s_col[threadIdx.x]);
-        atomicAdd(&counters[kCntPlaced + threadIdx.x], s_pl[threadIdx.x]);
+        const int r = threadIdx.x;
+        const unsigned long long a = s_w[0][r] + s_w[1][r] + s_w[2][r] + s_w[3][r];
+        const int q = NNSORT_MAX_EPS + r;
+        const unsigned long long b = s_w[0][q] + s_w[1][q] + s_w[2][q] + s_w[3][q];
+        if (a) atomicAdd(&counters[kCntCollided + r], a);
+        if (b) atomicAdd(&counters[kCntPlaced + r], b);
     }
 }
 
@@ -222,9 +236,7 @@ constexpr int kPartStride = 2 * NNSORT_MAX_EPS;
 
 __global__ void __launch_bounds__(256) k_sum_parts(const uint32_t* __restrict__ part, const uint32_t* __restrict__ cnt,
                                                    int64_t NB, int eps, unsigned long long* counters) {
-    __shared__ unsigned long long s_acc[kPartStride];
-    if (threadIdx.x < kPartStride) s_acc[threadIdx.x] = 0;
-    __syncthreads();
+    __shared__ unsigned long long s_w[4][kPartStride];
     unsigned long long acc[kPartStride] = {0};
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < NB; b += stride) {
@@ -235,14 +247,24 @@ __global__ void __launch_bounds__(256) k_sum_parts(const uint32_t* __restrict__ 
             acc[NNSORT_MAX_EPS + r] += part[b * kPartStride + NNSORT_MAX_EPS + r];
         }
     }
-    for (int r = 0; r < eps; ++r) {
-        if (acc[r]) atomicAdd(&s_acc[r], acc[r]);
-        if (acc[NNSORT_MAX_EPS + r]) atomicAdd(&s_acc[NNSORT_MAX_EPS + r], acc[NNSORT_MAX_EPS + r]);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int r = 0; r < NNSORT_MAX_EPS; ++r) {
+        if (r >= eps) break;
+        const unsigned long long a = wave_sum(acc[r]), b = wave_sum(acc[NNSORT_MAX_EPS + r]);
+        if (lane == 0) {
+            s_w[w][r] = a;
+            s_w[w][NNSORT_MAX_EPS + r] = b;
+        }
     }
     __syncthreads();
     if (threadIdx.x < (unsigned)eps) {
-        atomicAdd(&counters[kCntPlaced + threadIdx.x], s_acc[threadIdx.x]);
-        atomicAdd(&counters[kCntCollided + threadIdx.x], s_acc[NNSORT_MAX_EPS + threadIdx.x]);
+        const int r = threadIdx.x;
+        const unsigned long long a = s_w[0][r] + s_w[1][r] + s_w[2][r] + s_w[3][r];
+        const int q = NNSORT_MAX_EPS + r;
+        const unsigned long long b = s_w[0][q] + s_w[1][q] + s_w[2][q] + s_w[3][q];
+        if (a) atomicAdd(&counters[kCntPlaced + r], a);
+        if (b) atomicAdd(&counters[kCntCollided + r], b);
     }
 }
 
@@ -386,7 +408,7 @@ __device__ bool repair_range(BucketSmem<CAP>& sm, uint32_t cnt, int tid) {
 // range-partitioned order keys and slots (range b at [start[b], start[b+1]));
 // the range's keys are written as bit patterns to out[base + start[b] ...].
 template <int CAP, int LO>
-__global__ void __launch_bounds__(kBucketThreads) k_bucket_polish(
+__global__ void __launch_bounds__(kBucketThreads, CAP <= 2048 ? 7 : 4) k_bucket_polish(
     const int64_t* __restrict__ start, const int32_t* __restrict__ list, const uint64_t* __restrict__ K,
     const uint32_t* __restrict__ Sl, int eps, uint64_t* __restrict__ out, int64_t base, int is_f64,
     uint32_t* __restrict__ part, unsigned long long* counters) {

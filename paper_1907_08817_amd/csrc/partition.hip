@@ -50,21 +50,44 @@ __global__ void __launch_bounds__(256) k_check_slots(const uint32_t* __restrict_
 // per chunk and added to its histogram, for the round counts.
 constexpr int kChunk = 4096;
 
-// chunk_pref[i] = number of chunks of big ranges 0..i-1 (i = 0..big_count).
-__global__ void k_big_chunks(const int32_t* __restrict__ bigbucket, int64_t big_count,
-                             const int64_t* __restrict__ start, int64_t* chunk_pref, int64_t* gpref) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int64_t c = 0, g = 0;
-    for (int64_t i = 0; i < big_count; ++i) {
-        chunk_pref[i] = c;
-        gpref[i] = g;
-        int32_t b = bigbucket[i];
-        int64_t len = start[b + 1] - start[b];
-        c += (len + kChunk - 1) / kChunk;
-        g += len;
+// chunk_pref[i] = number of chunks of big ranges 0..i-1, gpref[i] = keys of
+// big ranges 0..i-1 (i = 0..big_count): one workgroup, 256 ranges at a time.
+__global__ void __launch_bounds__(256) k_big_chunks(const int32_t* __restrict__ bigbucket, int64_t big_count,
+                                                    const int64_t* __restrict__ start, int64_t* chunk_pref,
+                                                    int64_t* gpref) {
+    __shared__ int64_t s_c[256], s_g[256];
+    int64_t cbase = 0, gbase = 0;
+    for (int64_t i0 = 0; i0 < big_count; i0 += 256) {
+        const int64_t i = i0 + threadIdx.x;
+        int64_t len = 0;
+        if (i < big_count) {
+            const int32_t b = bigbucket[i];
+            len = start[b + 1] - start[b];
+        }
+        const int64_t nc = (len + kChunk - 1) / kChunk;
+        s_c[threadIdx.x] = nc;
+        s_g[threadIdx.x] = len;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            const int64_t yc = threadIdx.x >= (unsigned)o ? s_c[threadIdx.x - o] : 0;
+            const int64_t yg = threadIdx.x >= (unsigned)o ? s_g[threadIdx.x - o] : 0;
+            __syncthreads();
+            s_c[threadIdx.x] += yc;
+            s_g[threadIdx.x] += yg;
+            __syncthreads();
+        }
+        if (i < big_count) {
+            chunk_pref[i] = cbase + s_c[threadIdx.x] - nc;
+            gpref[i] = gbase + s_g[threadIdx.x] - len;
+        }
+        cbase += s_c[255];
+        gbase += s_g[255];
+        __syncthreads();
     }
-    chunk_pref[big_count] = c;
-    gpref[big_count] = g;
+    if (threadIdx.x == 0) {
+        chunk_pref[big_count] = cbase;
+        gpref[big_count] = gbase;
+    }
 }
 
 __global__ void __launch_bounds__(256) k_big_gather(const int32_t* __restrict__ bigbucket, int64_t big_count,
@@ -219,7 +242,7 @@ hipError_t launch_check_slots(const uint32_t* d_slots, int64_t n, int64_t S, uin
 
 hipError_t launch_big_chunks(const int32_t* d_bigbucket, int64_t big_count, const int64_t* d_start,
                              int64_t* d_chunk_pref, int64_t* d_gpref, hipStream_t st) {
-    hipLaunchKernelGGL(k_big_chunks, dim3(1), dim3(64), 0, st, d_bigbucket, big_count, d_start, d_chunk_pref, d_gpref);
+    hipLaunchKernelGGL(k_big_chunks, dim3(1), dim3(256), 0, st, d_bigbucket, big_count, d_start, d_chunk_pref, d_gpref);
     return hipGetLastError();
 }
 
