@@ -12,16 +12,34 @@ hipError_t fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
 
 constexpr int kHistThreads = 256;
 
+// Digit counts of all 8 byte positions.  High bytes are often the same for
+// every key of a wave (keys of similar magnitude); then one lane adds the
+// wave's count instead of 64 lanes hitting one LDS counter.
 __global__ void __launch_bounds__(kHistThreads) k_hist_all(const uint64_t* __restrict__ in, int64_t n,
                                                            int in_mode, unsigned long long* hist8) {
     __shared__ uint32_t h[8][256];
     for (int i = threadIdx.x; i < 8 * 256; i += kHistThreads) (&h[0][0])[i] = 0;
     __syncthreads();
+    const int lane = threadIdx.x & 63;
     int64_t stride = (int64_t)gridDim.x * kHistThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kHistThreads + threadIdx.x; i < n; i += stride) {
-        uint64_t k = to_order_key(in[i], in_mode);
+    for (int64_t base = (int64_t)blockIdx.x * kHistThreads; base < n; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        const bool valid = i < n;
+        const uint64_t k = valid ? to_order_key(in[i], in_mode) : 0;
+        const unsigned long long act = __ballot(valid);
+        const int leader = __ffsll((long long)act) - 1;
+        const uint64_t k0 = __shfl(k, leader < 0 ? 0 : leader);
 #pragma unroll
-        for (int p = 0; p < 8; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 255], 1u);
+        for (int p = 0; p < 8; ++p) {
+            const uint32_t d = (uint32_t)(k >> (8 * p)) & 255u;
+            const uint32_t d0 = (uint32_t)(k0 >> (8 * p)) & 255u;
+            const unsigned long long same = __ballot(valid && d == d0);
+            if (same == act) {
+                if (lane == leader) atomicAdd(&h[p][d0], (uint32_t)__popcll(act));
+            } else if (valid) {
+                atomicAdd(&h[p][d], 1u);
+            }
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < 8 * 256; i += kHistThreads) {
