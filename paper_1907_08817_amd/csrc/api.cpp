@@ -163,7 +163,7 @@ SortPlan plan_sort(int64_t n, double m) {
     p.off_K0 = take(nn * 8);
     p.off_K1 = take(nn * 8);
     p.off_phist = take(partition_hist_words(n) * 4);
-    p.off_psums = take(classify_ws_words(p.NB) * 8);
+    p.off_clsum = take(classify_ws_words(p.NB) * 8);
     p.off_seglist = take((size_t)p.NB * 4);
     p.off_bigbucket = take((size_t)p.big_max * 4);
     p.off_halflist = take((size_t)p.NB * 4);
@@ -266,7 +266,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     uint64_t* K0 = (uint64_t*)(ws + P.off_K0);
     uint64_t* K1 = (uint64_t*)(ws + P.off_K1);
     uint32_t* phist = (uint32_t*)(ws + P.off_phist);
-    uint64_t* clsum = (uint64_t*)(ws + P.off_psums);
+    uint64_t* clsum = (uint64_t*)(ws + P.off_clsum);
     int32_t* seglist = (int32_t*)(ws + P.off_seglist);
     int32_t* bigbucket = (int32_t*)(ws + P.off_bigbucket);
     int32_t* halflist = (int32_t*)(ws + P.off_halflist);

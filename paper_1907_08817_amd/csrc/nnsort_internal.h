@@ -10,15 +10,15 @@ namespace nns {
 
 constexpr uint32_t kUnmapped = 0xFFFFFFFFu;
 
-// Slot-range buckets: the sorting phase's slot array o_i is cut into ranges of
+// Slot ranges: the sorting phase's slot array o_i is cut into ranges of
 // kBucketSlots consecutive slots; the keys predicted into one range are made
-// contiguous by a stable partition, and a range of at most kBucketCap keys is
-// handled by one workgroup that runs every round and the polish in LDS.
+// contiguous by a partition on the range id, and a range of at most
+// kBucketCap keys is handled by one workgroup that runs every round and the
+// polish in LDS (a "dense" range, with more keys, takes the radix path).
 constexpr int kLogBucketSlots = 11;
 constexpr uint32_t kBucketSlots = 1u << kLogBucketSlots;
 constexpr uint32_t kBucketCap = 4096;
 constexpr int kBucketThreads = 256;
-constexpr int kItemsPerThread = kBucketCap / kBucketThreads;  // 16
 
 // Partition of keys by slot range: tiles of kPartTile keys in input order,
 // 256 digits per pass.
@@ -33,12 +33,12 @@ __device__ __forceinline__ uint32_t range_of(uint32_t slot, uint32_t NB) {
 enum Counter : int {
     kCntResorted = 0,     // ranges re-sorted whole after the tile merges
     kCntUnmapped = 1,     // keys with no slot
-    kCntCollided = 2,     // [2, 2 + 8): |c_r| for r = 1..8 (all buckets)
+    kCntCollided = 2,     // [2, 2 + 8): |c_r| for r = 1..8 (all ranges)
     kCntPlaced = 10,      // [10, 18): keys stored in o_r
-    kCntBigKeys = 18,     // keys of big buckets
+    kCntBigKeys = 18,     // keys of dense ranges
     kCntBigBuckets = 19,
     kCntBoundary = 21,    // keys inside boundary fix-up zones
-    kCntFallback = 22,    // nonzero: tile fix-up needs the full-sort fallback
+    kCntFallback = 22,    // nonzero: the boundary repair needs the full-sort fallback
     kCntBadSlot = 23,     // caller-given slot out of range
     kCntSegments = 24,    // non-empty slot ranges
     kCntPosErrSum = 25,   // double bits: sum |F n - p|
@@ -77,11 +77,10 @@ struct DevModel {
 struct SortPlan {
     int64_t n;
     int64_t S;         // slots
-    int64_t NB;        // buckets
-    int64_t big_max;   // capacity for big buckets' slot histograms
-    size_t off_counters, off_cnt, off_start, off_slots0, off_S0, off_K0, off_K1, off_phist, off_psums,
-        off_seglist, off_bigbucket, off_halflist, off_bigpref, off_part, off_zones, off_G, off_radix, off_big_hist, off_model,
-        total;
+    int64_t NB;        // slot ranges
+    int64_t big_max;   // most dense ranges possible (n / (kBucketCap + 1) + 1)
+    size_t off_counters, off_cnt, off_start, off_slots0, off_S0, off_K0, off_K1, off_phist, off_clsum, off_seglist,
+        off_bigbucket, off_halflist, off_bigpref, off_part, off_zones, off_G, off_radix, off_big_hist, off_model, total;
     size_t radix_bytes;
 };
 
