@@ -134,11 +134,18 @@ typedef struct {
     int64_t collided[NNSORT_MAX_EPS];
     int64_t placed[NNSORT_MAX_EPS];
     int64_t residue;
-    int64_t unmapped;        /* keys with no slot (non-finite) */
+    int64_t unmapped;        /* keys with no slot (F not a number, or a
+                                caller-given 0xFFFFFFFF) */
     int64_t big_buckets;     /* slot ranges too dense for one LDS tile */
     int64_t big_bucket_keys; /* keys sorted by the radix path for that reason */
     int64_t boundary_keys;   /* keys moved by the tile-boundary fix-up */
-    int32_t fallback;        /* 1 if the tile fix-up fell back to a full sort */
+    int32_t fallback;        /* 0: the boundary fix-up settled every overlap;
+                                1: overlaps beyond neighbouring ranges (or a
+                                zone over 4096 keys): the mapped keys were
+                                sorted whole by radix; 2: blocks were out of
+                                order after the fix-up (ranges far out of
+                                value order, keys without a slot that are not
+                                the extremes): the whole output was sorted */
     int32_t range_resorts;   /* slot ranges whose neighbour-tile merges did not
                                 settle and were re-sorted whole in LDS */
     double pos_err;          /* stats_level 2: mean |F(key) n - rank| / n */

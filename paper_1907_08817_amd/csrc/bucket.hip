@@ -698,6 +698,47 @@ __global__ void __launch_bounds__(256) k_boundary_merge(uint64_t* out, int is_f6
     }
 }
 
+// After the fix-up the output is a sequence of sorted blocks: the keys
+// without a slot below the mapped ones, each range's keys outside any zone,
+// each merged zone, the keys without a slot above the mapped ones.  It is
+// sorted iff every junction between adjacent blocks is.  The plan's test
+// (max of range k-1 <= min of range k+1) keeps zones from overlapping but does
+// not cover zones that end up side by side, or keys without a slot that are
+// not the extremes, so the junctions are checked here: one thread per range
+// (its first key, and both ends of the zone after it), one more for the start
+// of the keys without a slot above the mapped ones (at index back).
+__global__ void __launch_bounds__(256) k_junction_check(const uint64_t* __restrict__ out, int is_f64, int64_t base,
+                                                        const int64_t* __restrict__ start,
+                                                        const int32_t* __restrict__ seglist, int64_t K,
+                                                        const Zone* __restrict__ zones, int64_t n, int64_t back,
+                                                        unsigned long long* counters) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > K) return;
+    bool bad = false;
+    if (k == K) {
+        if (back > 0 && back < n) bad = out_key(out, is_f64, back - 1) > out_key(out, is_f64, back);
+    } else {
+        const int64_t p = base + start[seglist[k]];
+        if (p > 0) bad = out_key(out, is_f64, p - 1) > out_key(out, is_f64, p);
+        const Zone z = zones[k];
+        if (z.tail != 0 && z.head != 0) {
+            const int64_t zs = (int64_t)z.start, ze = zs + z.tail + z.head;
+            if (zs > 0) bad |= out_key(out, is_f64, zs - 1) > out_key(out, is_f64, zs);
+            if (ze < n) bad |= out_key(out, is_f64, ze - 1) > out_key(out, is_f64, ze);
+        }
+    }
+    if (bad) atomicAdd(&counters[kCntJunction], 1ull);
+}
+
+hipError_t launch_junction_check(const uint64_t* d_out, bool is_f64, int64_t base, const int64_t* d_start,
+                                 const int32_t* d_seglist, int64_t K, const void* d_zones, int64_t n, int64_t back,
+                                 uint64_t* d_counters, hipStream_t st) {
+    hipLaunchKernelGGL(k_junction_check, dim3((unsigned)((K + 1 + 255) / 256)), dim3(256), 0, st, d_out,
+                       is_f64 ? 1 : 0, base, d_start, d_seglist, K, (const Zone*)d_zones, n, back,
+                       (unsigned long long*)d_counters);
+    return hipGetLastError();
+}
+
 hipError_t launch_boundary_plan(const uint64_t* d_out, bool is_f64, int64_t base, const int64_t* d_start,
                                 const int32_t* d_seglist, int64_t K, void* d_zones, uint64_t* d_counters,
                                 hipStream_t st) {

@@ -45,6 +45,7 @@ enum Counter : int {
     kCntPosErrCnt = 26,
     kCntUnmappedNeg = 27, // keys with no slot whose order key has the top bit clear
     kCntHalfFull = 28,    // ranges of more than half the LDS capacity (and at most all of it)
+    kCntJunction = 29,    // nonzero: blocks out of order after the boundary fix-up
     kNumCounters = 32
 };
 
