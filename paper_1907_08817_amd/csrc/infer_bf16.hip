@@ -14,7 +14,7 @@
 //    Henry, Tang and Heinecke, 2019) while W2 itself is rounded to bfloat16;
 //  - the accumulators start at b2; lane (j, g) ends with hidden-2 units
 //    32 rb + 8 (v / 4) + 4 g + v % 4 (v = 0..15) of its key;
-//  - layer 3: relu, then the dot product with w3 accumulated in FP64 (each
+//  - layer 3: relu (on the bits), then the dot product with w3 accumulated in FP64 (each
 //    FP32 x FP32 product is exact there), the two halves' sums added in FP64,
 //    so that F keeps a resolution finer than one slot at n = 1e9.
 // Compiled with -ffp-contract=off.
@@ -38,6 +38,17 @@ __device__ __forceinline__ uint32_t pack_hi(float x, float y) {
 }
 
 __device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// relu as an integer max of the bit pattern: equal to z > 0 ? z : 0 for every
+// z that is not a NaN (negative values and -0 have the sign bit set).  One
+// instruction, where the float form costs two on matrix-core results (the
+// compiler first quiets a possible signalling NaN).  Inputs are translated
+// into [0, 1], so an activation is NaN only for a model with non-finite
+// weights or FP32 overflow.
+__device__ __forceinline__ float relu_bits(float z) {
+    const int b = __float_as_int(z);
+    return __int_as_float(b > 0 ? b : 0);
+}
 
 template <int H, int T>
 __global__ void __launch_bounds__(256, 3) k_infer_bf16(InferArgs a) {
@@ -152,7 +163,7 @@ __global__ void __launch_bounds__(256, 3) k_infer_bf16(InferArgs a) {
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                const float h2 = acc[rb][v] > 0.0f ? acc[rb][v] : 0.0f;
+                const float h2 = relu_bits(acc[rb][v]);
                 sum = __builtin_fma(w3g[16 * rb + v], (double)h2, sum);
             }
         const double F = sum + __shfl_xor(sum, 32);
