@@ -53,7 +53,11 @@ hipError_t launch_big_gather(const int32_t* d_bigbucket, int64_t big_count, int6
                              hipStream_t st);
 hipError_t launch_big_place(const int32_t* d_bigbucket, int64_t big_count, int64_t nchunks,
                             const int64_t* d_chunk_pref, const int64_t* d_gpref, const int64_t* d_start,
-                            const uint64_t* d_Gs, int64_t u_neg, uint64_t* d_out, bool is_f64, hipStream_t st);
+                            const uint64_t* d_Gs, const uint64_t* d_alt, bool seg_mode, int64_t u_neg,
+                            uint64_t* d_out, bool is_f64, hipStream_t st);
+int seg_rounds(int64_t max_len);
+hipError_t seg_sort(const int64_t* d_chunk_pref, const int64_t* d_gpref, int64_t nseg, int64_t nchunks,
+                    int rounds, uint64_t* d_G, uint64_t* d_tmp, hipStream_t st);
 hipError_t launch_count_neg(const uint64_t* d_K, const int64_t* d_start, uint32_t NB, int64_t n, uint64_t* d_count,
                             hipStream_t st);
 hipError_t launch_copy_u64(const uint64_t* d_in, uint64_t* d_out, int64_t n, hipStream_t st);
@@ -144,6 +148,10 @@ void to_dev_model(const nnsort_model* m, DevModel* d) {
 }  // namespace
 
 namespace nns {
+
+// Merge rounds of the range-by-range sort of dense ranges beyond which the
+// radix sort of the whole residue is used instead (ranges of up to 1M keys).
+constexpr int kSegMaxRounds = 8;
 
 SortPlan plan_sort(int64_t n, double m) {
     SortPlan p{};
@@ -357,12 +365,26 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     ev.mark(3);
 
     // ---- dense ranges and keys without a slot: conventional sort, placed ----
+    // Dense ranges up to kBigChunk << kSegMaxRounds keys: sorted range by
+    // range (chunks in LDS, then merge rounds), the keys without a slot by
+    // radix on their own.  Larger ones: one LSD radix sort of all of G, which
+    // then moves fewer bytes than the merge rounds.
     if (G_size > 0) {
-        NNS_HIP(radix_sort(G, G, G_size, 0, 0, radix_ws, P.radix_bytes, st));
-        NNS_HIP(launch_big_place(bigbucket, big_count, nchunks, chunk_pref, gpref, start, G, u_neg, out, is_f64,
-                                 st));
-        if (u_neg > 0) NNS_HIP(launch_convert(G, out, u_neg, 0, is_f64 ? 1 : 2, st));
+        const int rounds = seg_rounds((int64_t)c[kCntBigMax]);
+        const bool seg_mode = rounds <= kSegMaxRounds;
+        uint64_t* alt = which ? K0 : K1;  // the partition buffer that Ks is not in
+        if (seg_mode) {
+            NNS_HIP(seg_sort(chunk_pref, gpref, big_count, nchunks, rounds, G, alt, st));
+            if (unm > 0) NNS_HIP(radix_sort(G + big_keys, G + big_keys, unm, 0, 0, radix_ws, P.radix_bytes, st));
+        } else {
+            NNS_HIP(radix_sort(G, G, G_size, 0, 0, radix_ws, P.radix_bytes, st));
+        }
+        NNS_HIP(launch_big_place(bigbucket, big_count, nchunks, chunk_pref, gpref, start, G, alt, seg_mode, u_neg,
+                                 out, is_f64, st));
+        // sorted keys without a slot: those with the order key's top bit clear
+        // first (below every mapped key), the rest last
         const int64_t u_pos = unm - u_neg;
+        if (u_neg > 0) NNS_HIP(launch_convert(seg_mode ? G + big_keys : G, out, u_neg, 0, is_f64 ? 1 : 2, st));
         if (u_pos > 0) NNS_HIP(launch_convert(G + G_size - u_pos, out + n - u_pos, u_pos, 0, is_f64 ? 1 : 2, st));
     }
     ev.mark(4);

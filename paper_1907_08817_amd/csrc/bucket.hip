@@ -74,8 +74,9 @@ constexpr uint32_t kHalfCap = kBucketCap / 2;
 constexpr int kClsQ = 4;  // per block: non-empty, dense, dense keys, half-full
 
 __global__ void __launch_bounds__(256) k_cls_count(const uint32_t* __restrict__ cnt, int64_t NB,
-                                                   unsigned long long* bsum) {
+                                                   unsigned long long* bsum, unsigned long long* counters) {
     __shared__ unsigned long long s[kClsQ][4];
+    __shared__ uint32_t s_max[4];
     const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const uint32_t c = b < NB ? cnt[b] : 0;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -83,15 +84,27 @@ __global__ void __launch_bounds__(256) k_cls_count(const uint32_t* __restrict__ 
     unsigned long long bg = __popcll(__ballot(c > kBucketCap));
     unsigned long long md = __popcll(__ballot(c > kHalfCap && c <= kBucketCap));
     unsigned long long bk = c > kBucketCap ? c : 0;
+    uint32_t mx = c > kBucketCap ? c : 0;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) bk += __shfl_xor(bk, o);
+    for (int o = 32; o > 0; o >>= 1) {
+        bk += __shfl_xor(bk, o);
+        const uint32_t y = __shfl_xor(mx, o);
+        mx = y > mx ? y : mx;
+    }
     if (lane == 0) {
         s[0][w] = ne;
         s[1][w] = bg;
         s[2][w] = bk;
         s[3][w] = md;
+        s_max[w] = mx;
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t m01 = s_max[0] > s_max[1] ? s_max[0] : s_max[1];
+        const uint32_t m23 = s_max[2] > s_max[3] ? s_max[2] : s_max[3];
+        const uint32_t m = m01 > m23 ? m01 : m23;
+        if (m) atomicMax(&counters[kCntBigMax], (unsigned long long)m);
+    }
     if (threadIdx.x < kClsQ)
         bsum[blockIdx.x * kClsQ + threadIdx.x] =
             s[threadIdx.x][0] + s[threadIdx.x][1] + s[threadIdx.x][2] + s[threadIdx.x][3];
@@ -167,7 +180,8 @@ hipError_t launch_classify(const uint32_t* d_cnt, int64_t NB, int64_t big_max, i
                            hipStream_t st) {
     const int64_t nblk = (NB + 255) / 256;
     unsigned long long* bs = (unsigned long long*)d_bsum;
-    hipLaunchKernelGGL(k_cls_count, dim3((unsigned)nblk), dim3(256), 0, st, d_cnt, NB, bs);
+    hipLaunchKernelGGL(k_cls_count, dim3((unsigned)nblk), dim3(256), 0, st, d_cnt, NB, bs,
+                       (unsigned long long*)d_counters);
     hipLaunchKernelGGL(k_cls_scan, dim3(1), dim3(256), 0, st, bs, nblk, (unsigned long long*)d_counters);
     hipLaunchKernelGGL(k_cls_write, dim3((unsigned)nblk), dim3(256), 0, st, d_cnt, NB, big_max, bs, d_seglist,
                        d_bigbucket, d_halflist);

@@ -18,6 +18,8 @@ constexpr uint32_t kUnmapped = 0xFFFFFFFFu;
 constexpr int kLogBucketSlots = 11;
 constexpr uint32_t kBucketSlots = 1u << kLogBucketSlots;
 constexpr uint32_t kBucketCap = 4096;
+// dense ranges are gathered, sorted and placed in chunks of this many keys
+constexpr int kBigChunk = 4096;
 constexpr int kBucketThreads = 256;
 
 // Partition of keys by slot range: tiles of kPartTile keys in input order,
@@ -46,6 +48,7 @@ enum Counter : int {
     kCntUnmappedNeg = 27, // keys with no slot whose order key has the top bit clear
     kCntHalfFull = 28,    // ranges of more than half the LDS capacity (and at most all of it)
     kCntJunction = 29,    // nonzero: blocks out of order after the boundary fix-up
+    kCntBigMax = 30,      // keys in the largest dense range
     kNumCounters = 32
 };
 

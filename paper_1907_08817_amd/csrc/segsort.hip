@@ -1,0 +1,188 @@
+// Sort of the dense ranges' keys, range by range (the conventional sort of
+// the keys the LDS polish cannot hold; Sec. 2 sorts the last conflict array
+// conventionally, and the dense ranges' keys are the part of it that this
+// design routes here).  After the gather, G holds each dense range's order
+// keys contiguously: range id occupies G[gpref[id], gpref[id + 1]), cut into
+// chunks of kBigChunk keys (chunk_pref[id] = its first chunk).  Sorting each
+// segment on its own gives every range exactly its own keys in order, the
+// same state a small range reaches in LDS; the boundary check that follows
+// treats both alike.
+//
+//  1. k_seg_sort_chunk: every chunk sorted in LDS (bitonic network, one
+//     workgroup per chunk).
+//  2. k_seg_merge, once per round r = 0, 1, ...: in every segment longer
+//     than L = kBigChunk 2^r, the sorted runs of length L are merged in pairs
+//     (merge path: each workgroup writes one chunk of output; a wave finds
+//     where the chunk starts in the two runs by a 64-way search, then the
+//     chunk's inputs are staged in LDS and every thread merges 16 outputs).
+//     Round r reads one buffer and writes the other; a segment that takes R
+//     rounds ends in buffer R mod 2 (G for even R).
+#include "nnsort_internal.h"
+
+namespace nns {
+
+constexpr int kSortThreads = 512;
+constexpr int kMergeThreads = 256;
+constexpr int kMergePer = kBigChunk / kMergeThreads;  // outputs per thread
+
+// Segment of a chunk: the last id with chunk_pref[id] <= chunk.
+__device__ __forceinline__ int64_t seg_of_chunk(const int64_t* __restrict__ chunk_pref, int64_t nseg,
+                                                int64_t chunk) {
+    int64_t lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (chunk_pref[mid] <= chunk) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_seg_sort_chunk(const int64_t* __restrict__ chunk_pref,
+                                                                 const int64_t* __restrict__ gpref, int64_t nseg,
+                                                                 uint64_t* G) {
+    __shared__ uint64_t s[kBigChunk];
+    const int64_t chunk = blockIdx.x;
+    if (chunk >= chunk_pref[nseg]) return;  // the grid is an upper bound
+    const int64_t id = seg_of_chunk(chunk_pref, nseg, chunk);
+    const int64_t g0 = gpref[id], len = gpref[id + 1] - g0;
+    const int64_t c0 = (chunk - chunk_pref[id]) * kBigChunk;
+    const int cnt = (int)(len - c0 < kBigChunk ? len - c0 : kBigChunk);
+    uint64_t* p = G + g0 + c0;
+    const int tid = threadIdx.x;
+    // padding with the largest order key: a real key of that value is the
+    // same bit pattern, so the first cnt outputs are right either way
+    for (int i = tid; i < kBigChunk; i += kSortThreads) s[i] = i < cnt ? p[i] : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= kBigChunk; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int q = tid; q < kBigChunk / 2; q += kSortThreads) {
+                const int i = ((q & ~(j - 1)) << 1) | (q & (j - 1));  // lower index of pair q
+                const int l = i + j;
+                const uint64_t a = s[i], b = s[l];
+                const bool up = (i & k) == 0;
+                if ((a > b) == up) {
+                    s[i] = b;
+                    s[l] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = tid; i < cnt; i += kSortThreads) p[i] = s[i];
+}
+
+// Merge path, whole wave: the number of A's elements among the first d of
+// the merge of sorted A[0, na) and B[0, nb) (ties from A first).  That is the
+// first i in [max(0, d - nb), min(d, na)] where A[i] <= B[d - i - 1] fails;
+// the predicate holds on a prefix, so 64 probes per step narrow the interval
+// 65-fold.  Every probe index stays inside both arrays.
+__device__ int64_t split_wave(const uint64_t* __restrict__ A, int64_t na, const uint64_t* __restrict__ B,
+                              int64_t nb, int64_t d, int lane) {
+    int64_t lo = d > nb ? d - nb : 0;
+    int64_t hi = d < na ? d : na;
+    while (hi > lo) {
+        const int64_t w = hi - lo;
+        if (w <= 64) {
+            const bool p = lane < w && A[lo + lane] <= B[d - (lo + lane) - 1];
+            return lo + __popcll(__ballot(p));
+        }
+        const int64_t m = lo + (w * (lane + 1)) / 65;  // lo <= m < hi, increasing in lane
+        const int t = __popcll(__ballot(A[m] <= B[d - m - 1]));
+        const int64_t nlo = t > 0 ? lo + (w * t) / 65 + 1 : lo;
+        const int64_t nhi = t < 64 ? lo + (w * (t + 1)) / 65 : hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    return lo;
+}
+
+// Same in LDS, one thread.
+__device__ __forceinline__ int split_lds(const uint64_t* A, int na, const uint64_t* B, int nb, int d) {
+    int lo = d > nb ? d - nb : 0;
+    int hi = d < na ? d : na;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (A[mid] <= B[d - mid - 1]) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kMergeThreads) k_seg_merge(const int64_t* __restrict__ chunk_pref,
+                                                             const int64_t* __restrict__ gpref, int64_t nseg,
+                                                             int64_t L, const uint64_t* __restrict__ src,
+                                                             uint64_t* __restrict__ dst) {
+    __shared__ uint64_t s[kBigChunk];
+    __shared__ int64_t s_split[2];
+    const int64_t chunk = blockIdx.x;
+    if (chunk >= chunk_pref[nseg]) return;  // the grid is an upper bound
+    const int64_t id = seg_of_chunk(chunk_pref, nseg, chunk);
+    const int64_t g0 = gpref[id], len = gpref[id + 1] - g0;
+    if (len <= L) return;  // one run already: this segment is done
+    const int64_t c0 = (chunk - chunk_pref[id]) * kBigChunk;
+    const int64_t c1 = c0 + kBigChunk < len ? c0 + kBigChunk : len;
+    const int64_t pb = (c0 / (2 * L)) * (2 * L);  // first output of this chunk's pair of runs
+    const uint64_t* A = src + g0 + pb;
+    const int64_t na = len - pb < L ? len - pb : L;
+    const uint64_t* B = A + L;
+    int64_t nb = len - pb - L;
+    nb = nb < 0 ? 0 : (nb > L ? L : nb);
+    uint64_t* O = dst + g0 + pb;
+    const int64_t d0 = c0 - pb, d1 = c1 - pb;
+    const int tid = threadIdx.x;
+    if (nb == 0) {  // the segment's last run has no partner: carried over
+        for (int64_t e = d0 + tid; e < d1; e += kMergeThreads) O[e] = A[e];
+        return;
+    }
+    const int wv = tid >> 6, lane = tid & 63;
+    if (wv < 2) {
+        const int64_t sp = split_wave(A, na, B, nb, wv == 0 ? d0 : d1, lane);
+        if (lane == 0) s_split[wv] = sp;
+    }
+    __syncthreads();
+    const int64_t i0 = s_split[0], i1 = s_split[1];
+    const int la = (int)(i1 - i0), lb = (int)((d1 - i1) - (d0 - i0));
+    const uint64_t* Aw = A + i0;
+    const uint64_t* Bw = B + (d0 - i0);
+    for (int e = tid; e < la + lb; e += kMergeThreads) s[e] = e < la ? Aw[e] : Bw[e - la];
+    __syncthreads();
+    const int t0 = tid * kMergePer;
+    if (t0 >= la + lb) return;
+    const uint64_t* sa = s;
+    const uint64_t* sb = s + la;
+    int ia = split_lds(sa, la, sb, lb, t0);
+    int ib = t0 - ia;
+    const int t1 = t0 + kMergePer < la + lb ? t0 + kMergePer : la + lb;
+    for (int t = t0; t < t1; ++t) {
+        const bool takeA = ib >= lb || (ia < la && sa[ia] <= sb[ib]);
+        O[d0 + t] = takeA ? sa[ia] : sb[ib];
+        ia += takeA ? 1 : 0;
+        ib += takeA ? 0 : 1;
+    }
+}
+
+int seg_rounds(int64_t max_len) {
+    int r = 0;
+    for (int64_t L = kBigChunk; L < max_len; L <<= 1) ++r;
+    return r;
+}
+
+// Sorts every segment of G; tmp holds as many keys as G.  A segment of len
+// keys ends in (seg_rounds(len) odd ? tmp : G).
+hipError_t seg_sort(const int64_t* d_chunk_pref, const int64_t* d_gpref, int64_t nseg, int64_t nchunks,
+                    int rounds, uint64_t* d_G, uint64_t* d_tmp, hipStream_t st) {
+    if (nseg <= 0 || nchunks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_sort_chunk, dim3((unsigned)nchunks), dim3(kSortThreads), 0, st, d_chunk_pref, d_gpref,
+                       nseg, d_G);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    uint64_t* buf[2] = {d_G, d_tmp};
+    for (int r = 0; r < rounds; ++r) {
+        hipLaunchKernelGGL(k_seg_merge, dim3((unsigned)nchunks), dim3(kMergeThreads), 0, st, d_chunk_pref, d_gpref,
+                           nseg, (int64_t)kBigChunk << r, buf[r & 1], buf[(r + 1) & 1]);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace nns
