@@ -21,8 +21,9 @@
 //    neighbouring 8-key tiles, or re-sorted whole.
 // The output position of every range is known from the partition, so each
 // range writes its keys straight to their final place.  Ranges too dense for
-// LDS and keys with no slot go to a conventional radix sort (the residue
-// path).  k_boundary_* then checks every pair of neighbouring ranges and
+// LDS and keys with no slot go to a conventional sort (the residue path:
+// segsort.hip range by range, radix.hip for keys with no slot).
+// k_boundary_* then checks every pair of neighbouring ranges and
 // repairs overlaps (where f is not monotone across a range boundary) with an
 // in-place merge, or reports a fallback to a full sort.
 #include "nnsort_internal.h"
