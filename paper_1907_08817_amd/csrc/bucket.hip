@@ -290,7 +290,6 @@ size_t polish_part_words(int64_t NB) { return (size_t)NB * kPartStride; }
 // ---------------------------------------------------------------------------
 constexpr int kTile = 8;                 // keys per repair tile
 constexpr int kMaxTileRounds = 8;        // odd-even tile rounds before the whole-range re-sort
-constexpr int kSlotsPer = kBucketSlots / kBucketThreads;  // slots owned per thread (8)
 constexpr uint32_t kGroupMax = 32;       // larger slot groups are ordered by the whole-range re-sort
 
 __device__ __forceinline__ void cswap(uint64_t& a, uint64_t& b) {
@@ -339,14 +338,14 @@ __device__ __forceinline__ int merge_split(const uint64_t* a, int na, const uint
     return lo;
 }
 
-template <int CAP>
+template <int CAP, int NT>
 struct BucketSmem {
     uint64_t keys[CAP];
     // per slot, 16 bits: its key count, then its first position; slot 2w in
     // the low half of word w, slot 2w + 1 in the high half
     uint32_t off[kBucketSlots / 2];
-    uint32_t wsum[kBucketThreads / 64];
-    uint32_t red[(kBucketThreads / 64) * NNSORT_MAX_EPS];  // per-wave stored counts per round
+    uint32_t wsum[NT / 64];
+    uint32_t red[(NT / 64) * NNSORT_MAX_EPS];  // per-wave stored counts per round
     int flag;
 };
 
@@ -357,12 +356,12 @@ __device__ __forceinline__ uint32_t half_of(uint32_t word, uint32_t s) { return 
 // boundary is out of order (keys only move as far as f misplaced them), and a
 // bitonic sort of the whole range if that does not settle.  Returns true if
 // the bitonic sort ran.
-template <int CAP>
-__device__ bool repair_range(BucketSmem<CAP>& sm, uint32_t cnt, int tid) {
+template <int CAP, int NT>
+__device__ bool repair_range(BucketSmem<CAP, NT>& sm, uint32_t cnt, int tid) {
     const int ntiles = (int)((cnt + kTile - 1) / kTile);
-    for (int i = (int)cnt + tid; i < ntiles * kTile; i += kBucketThreads) sm.keys[i] = ~0ull;
+    for (int i = (int)cnt + tid; i < ntiles * kTile; i += NT) sm.keys[i] = ~0ull;
     __syncthreads();
-    for (int t = tid; t < ntiles; t += kBucketThreads) {
+    for (int t = tid; t < ntiles; t += NT) {
         uint64_t v[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) v[q] = sm.keys[t * 8 + q];
@@ -373,7 +372,7 @@ __device__ bool repair_range(BucketSmem<CAP>& sm, uint32_t cnt, int tid) {
     __syncthreads();
     for (int round = 0; round <= kMaxTileRounds; ++round) {
         int bad = 0;
-        for (int t = tid; t + 1 < ntiles; t += kBucketThreads)
+        for (int t = tid; t + 1 < ntiles; t += NT)
             bad |= sm.keys[t * 8 + 7] > sm.keys[t * 8 + 8] ? 1 : 0;
         if (bad) sm.flag = round + 2;
         __syncthreads();
@@ -382,7 +381,7 @@ __device__ bool repair_range(BucketSmem<CAP>& sm, uint32_t cnt, int tid) {
         if (f != round + 2) return false;
         if (round == kMaxTileRounds) break;
         const int parity = round & 1;
-        for (int p = tid; 2 * p + parity + 1 < ntiles; p += kBucketThreads) {
+        for (int p = tid; 2 * p + parity + 1 < ntiles; p += NT) {
             const int t0 = 2 * p + parity;
             uint64_t v[16];
 #pragma unroll
@@ -396,11 +395,11 @@ __device__ bool repair_range(BucketSmem<CAP>& sm, uint32_t cnt, int tid) {
     // f is far from monotone inside this range: bitonic sort of the range
     int npad = 8;
     while (npad < ntiles * 8) npad <<= 1;
-    for (int i = ntiles * 8 + tid; i < npad; i += kBucketThreads) sm.keys[i] = ~0ull;
+    for (int i = ntiles * 8 + tid; i < npad; i += NT) sm.keys[i] = ~0ull;
     __syncthreads();
     for (int kk = 2; kk <= npad; kk <<= 1) {
         for (int j = kk >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < npad; i += kBucketThreads) {
+            for (int i = tid; i < npad; i += NT) {
                 int l = i ^ j;
                 if (l > i) {
                     uint64_t a = sm.keys[i], c = sm.keys[l];
@@ -422,13 +421,14 @@ __device__ bool repair_range(BucketSmem<CAP>& sm, uint32_t cnt, int tid) {
 // capacity run in a variant with twice as many workgroups per CU).  K / Sl: the
 // range-partitioned order keys and slots (range b at [start[b], start[b+1]));
 // the range's keys are written as bit patterns to out[base + start[b] ...].
-template <int CAP, int LO>
-__global__ void __launch_bounds__(kBucketThreads, CAP <= 2048 ? 7 : 4) k_bucket_polish(
+template <int CAP, int LO, int NT>
+__global__ void __launch_bounds__(NT, CAP <= 2048 ? 7 : 4) k_bucket_polish(
     const int64_t* __restrict__ start, const int32_t* __restrict__ list, const uint64_t* __restrict__ K,
     const uint32_t* __restrict__ Sl, int eps, uint64_t* __restrict__ out, int64_t base, int is_f64,
     uint32_t* __restrict__ part, unsigned long long* counters) {
-    constexpr int kItems = CAP / kBucketThreads;
-    __shared__ BucketSmem<CAP> sm;
+    constexpr int kItems = CAP / NT;
+    constexpr int kSlotsPer = kBucketSlots / NT;  // slots owned per thread
+    __shared__ BucketSmem<CAP, NT> sm;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = tid >> 6;
@@ -444,8 +444,8 @@ __global__ void __launch_bounds__(kBucketThreads, CAP <= 2048 ? 7 : 4) k_bucket_
     uint32_t rank[kItems];
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        if (k * kBucketThreads >= (int)cnt) break;
-        const uint32_t e = tid + k * kBucketThreads;
+        if (k * NT >= (int)cnt) break;
+        const uint32_t e = tid + k * NT;
         key[k] = 0;
         sl[k] = 0;
         if (e < cnt) {
@@ -453,14 +453,14 @@ __global__ void __launch_bounds__(kBucketThreads, CAP <= 2048 ? 7 : 4) k_bucket_
             sl[k] = rs[e] & (kBucketSlots - 1);
         }
     }
-    for (int i = tid; i < (int)kBucketSlots / 2; i += kBucketThreads) sm.off[i] = 0;
+    for (int i = tid; i < (int)kBucketSlots / 2; i += NT) sm.off[i] = 0;
     if (tid == 0) sm.flag = 0;
     __syncthreads();
     // arrival rank of each key in its slot
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        if (k * kBucketThreads >= (int)cnt) break;
-        if (tid + k * kBucketThreads < cnt) {
+        if (k * NT >= (int)cnt) break;
+        if (tid + k * NT < cnt) {
             const uint32_t old = atomicAdd(&sm.off[sl[k] >> 1], 1u << ((sl[k] & 1u) * 16u));
             rank[k] = half_of(old, sl[k]);
         }
@@ -518,7 +518,7 @@ __global__ void __launch_bounds__(kBucketThreads, CAP <= 2048 ? 7 : 4) k_bucket_
         uint32_t stored = 0, cum = 0;
         for (int r = 0; r <= tid; ++r) {
             uint32_t p = 0;
-            for (int w = 0; w < kBucketThreads / 64; ++w) p += sm.red[w * NNSORT_MAX_EPS + r];
+            for (int w = 0; w < NT / 64; ++w) p += sm.red[w * NNSORT_MAX_EPS + r];
             cum += p;
             stored = p;
         }
@@ -531,8 +531,8 @@ __global__ void __launch_bounds__(kBucketThreads, CAP <= 2048 ? 7 : 4) k_bucket_
     uint32_t g0[kItems];
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        if (k * kBucketThreads >= (int)cnt) break;
-        if (tid + k * kBucketThreads < cnt) {
+        if (k * NT >= (int)cnt) break;
+        if (tid + k * NT < cnt) {
             g0[k] = half_of(sm.off[sl[k] >> 1], sl[k]);
             sm.keys[g0[k] + rank[k]] = key[k];
         }
@@ -545,8 +545,8 @@ __global__ void __launch_bounds__(kBucketThreads, CAP <= 2048 ? 7 : 4) k_bucket_
         // (key, arrival); groups hold about one key on average
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
-            if (k * kBucketThreads >= (int)cnt) break;
-            if (tid + k * kBucketThreads < cnt) {
+            if (k * NT >= (int)cnt) break;
+            if (tid + k * NT < cnt) {
                 const uint32_t s = sl[k];
                 const uint32_t g1 = s + 1 < kBucketSlots ? half_of(sm.off[(s + 1) >> 1], s + 1) : cnt;
                 const uint64_t me = key[k];
@@ -566,13 +566,13 @@ __global__ void __launch_bounds__(kBucketThreads, CAP <= 2048 ? 7 : 4) k_bucket_
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
-            if (k * kBucketThreads >= (int)cnt) break;
-            if (tid + k * kBucketThreads < cnt) sm.keys[rank[k]] = key[k];
+            if (k * NT >= (int)cnt) break;
+            if (tid + k * NT < cnt) sm.keys[rank[k]] = key[k];
         }
         __syncthreads();
         // descents remain only where f's slots jitter between neighbours
         int bad = 0;
-        for (uint32_t i = tid; i + 1 < cnt; i += kBucketThreads) bad |= sm.keys[i] > sm.keys[i + 1] ? 1 : 0;
+        for (uint32_t i = tid; i + 1 < cnt; i += NT) bad |= sm.keys[i] > sm.keys[i + 1] ? 1 : 0;
         if (bad) sm.flag = 1;
         __syncthreads();
         need_repair = sm.flag != 0;
@@ -583,7 +583,7 @@ __global__ void __launch_bounds__(kBucketThreads, CAP <= 2048 ? 7 : 4) k_bucket_
 
     // write the range's sorted keys to their final place
     uint64_t* o = out + base + s0;
-    for (uint32_t i = tid; i < cnt; i += kBucketThreads) o[i] = order_key_inverse(sm.keys[i], is_f64);
+    for (uint32_t i = tid; i < cnt; i += NT) o[i] = order_key_inverse(sm.keys[i], is_f64);
 }
 
 // Ranges of at most kHalfCap keys: one workgroup per range id (others exit
@@ -593,17 +593,19 @@ hipError_t launch_polish_small(const int64_t* d_start, int64_t NB, const uint64_
                                hipStream_t st) {
     if (NB <= 0) return hipSuccess;
     static_assert(kBucketCap == 2 * kHalfCap && kHalfCap == 2048, "polish variants");
-    hipLaunchKernelGGL((k_bucket_polish<2048, 0>), dim3((unsigned)NB), dim3(kBucketThreads), 0, st, d_start,
+    hipLaunchKernelGGL((k_bucket_polish<2048, 0, kBucketThreads>), dim3((unsigned)NB), dim3(kBucketThreads), 0, st, d_start,
                        nullptr, d_K, d_S, eps, d_out, base, is_f64 ? 1 : 0, d_part, (unsigned long long*)d_counters);
     return hipGetLastError();
 }
 
-// The n_half ranges listed in d_halflist: the full-capacity variant.
+// The n_half ranges listed in d_halflist: the full-capacity variant, with
+// twice the threads (its workgroups are few, so each one's latency counts).
+constexpr int kHalfThreads = 512;
 hipError_t launch_polish_half(const int64_t* d_start, const int32_t* d_halflist, int64_t n_half, const uint64_t* d_K,
                               const uint32_t* d_S, int eps, uint64_t* d_out, int64_t base, bool is_f64,
                               uint32_t* d_part, uint64_t* d_counters, hipStream_t st) {
     if (n_half <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_bucket_polish<4096, 2048>), dim3((unsigned)n_half), dim3(kBucketThreads), 0, st, d_start,
+    hipLaunchKernelGGL((k_bucket_polish<4096, 2048, kHalfThreads>), dim3((unsigned)n_half), dim3(kHalfThreads), 0, st, d_start,
                        d_halflist, d_K, d_S, eps, d_out, base, is_f64 ? 1 : 0, d_part,
                        (unsigned long long*)d_counters);
     return hipGetLastError();
