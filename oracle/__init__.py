@@ -219,6 +219,31 @@ def nnsort(x: np.ndarray, model: dict, m: float = 1.25, eps: int = 3, tau: int =
     return out.view(x.dtype), stats
 
 
+def cost_operations(n: int, collided, placed, extracted, theta: float) -> float:
+    """Operations of the procedure as Sec. 3 (Model Analysis) counts them,
+    summed iteration by iteration from sizes, T = s(n) + p(n):
+      s(n): iteration i feeds its input (n keys, then the conflict array left
+            by iteration i - 1) through f at theta operations per key, and the
+            last conflict array is sorted conventionally, |w| log2 |w|;
+      p(n): each out-of-order key of o_i is inserted at half the size of
+            iteration i's input; every other key of o_i, and every key of the
+            conflict array after iteration i, is appended once.
+    collided[i] = |c_{i+1}|, placed[i] = keys stored in o_{i+1},
+    extracted[i] = those out of order (this oracle's round statistics)."""
+    if n <= 1:
+        return 1.0
+    total = 0.0
+    w = float(n)  # input of the current iteration
+    for c, p, x in zip(collided, placed, extracted):
+        total += theta * w
+        total += x * w / 2.0
+        total += (p - x) + c
+        w = float(c)
+    if w > 0:
+        total += w * math.log2(w)
+    return total
+
+
 def pos_err(sorted_x: np.ndarray, model: dict, form: int = FORM_FP64) -> float:
     b, f = _bits(sorted_x)
     th = np.ascontiguousarray(model["theta"], np.float32)
