@@ -141,11 +141,11 @@ typedef struct {
     int64_t boundary_keys;   /* keys moved by the tile-boundary fix-up */
     int32_t fallback;        /* 0: the boundary fix-up settled every overlap;
                                 1: overlaps beyond neighbouring ranges (or a
-                                zone over 4096 keys): the mapped keys were
-                                sorted whole by radix; 2: blocks were out of
-                                order after the fix-up (ranges far out of
-                                value order, keys without a slot that are not
-                                the extremes): the whole output was sorted */
+                                zone over 4096 keys); 2: blocks out of order
+                                after the fix-up (ranges far out of value
+                                order, keys without a slot that are not the
+                                extremes).  In both cases the whole output
+                                was then sorted by radix. */
     int32_t range_resorts;   /* slot ranges whose neighbour-tile merges did not
                                 settle and were re-sorted whole in LDS */
     double pos_err;          /* stats_level 2: mean |F(key) n - rank| / n */

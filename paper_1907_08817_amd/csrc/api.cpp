@@ -33,10 +33,11 @@ hipError_t launch_sum_parts(const uint32_t* d_part, const uint32_t* d_cnt, int64
 hipError_t launch_boundary_plan(const uint64_t* d_out, bool is_f64, int64_t base, const int64_t* d_start,
                                 const int32_t* d_seglist, int64_t K, void* d_zones, uint64_t* d_counters,
                                 hipStream_t st);
-hipError_t launch_boundary_merge(uint64_t* d_out, bool is_f64, const void* d_zones, int64_t K, hipStream_t st);
+hipError_t launch_boundary_merge(uint64_t* d_out, bool is_f64, const void* d_zones, int64_t K,
+                                const uint64_t* d_counters, hipStream_t st);
 hipError_t launch_junction_check(const uint64_t* d_out, bool is_f64, int64_t base, const int64_t* d_start,
                                  const int32_t* d_seglist, int64_t K, const void* d_zones, int64_t n, int64_t back,
-                                 uint64_t* d_counters, hipStream_t st);
+                                 bool unmapped, uint64_t* d_counters, hipStream_t st);
 size_t zone_bytes();
 size_t partition_hist_words(int64_t n);
 hipError_t partition_by_range(const uint64_t* in_keys, const uint32_t* in_slots, int64_t n, uint32_t NB, bool is_f64,
@@ -390,27 +391,21 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     ev.mark(4);
 
     // ---- boundaries between neighbouring ranges ----
+    // The plan, the in-place merges (skipped on the device when the plan
+    // reports a fallback) and the junction check run back to back; the one
+    // read of the counters that ends the call decides whether the output must
+    // be sorted whole instead.
     NNS_HIP(launch_boundary_plan(out, is_f64, u_neg, start, seglist, nseg, zones, counters, st));
-    NNS_HIP(hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, st));
-    NNS_HIP(hipStreamSynchronize(st));
-    const int mode = is_f64 ? 1 : 2;
-    if (c[kCntFallback]) {
-        const int64_t len = first_unmapped;
-        if (P.radix_bytes < radix_ws_bytes(len)) return NNSORT_EINTERNAL;
-        NNS_HIP(radix_sort(out + u_neg, out + u_neg, len, mode, mode, radix_ws, P.radix_bytes, st));
-    } else if (c[kCntBoundary]) {
-        NNS_HIP(launch_boundary_merge(out, is_f64, zones, nseg, st));
-    }
-    // with no zone, no fallback and every key mapped, the plan has already
-    // seen each pair of neighbouring ranges in order
-    if (c[kCntBoundary] || c[kCntFallback] || unm > 0)
+    NNS_HIP(launch_boundary_merge(out, is_f64, zones, nseg, counters, st));
+    if (nseg > 0 || unm > 0)
         NNS_HIP(launch_junction_check(out, is_f64, u_neg, start, seglist, nseg, zones, n, u_neg + first_unmapped,
-                                      counters, st));
+                                      unm > 0, counters, st));
 
-    // ---- statistics (and the junction verdict) ----
+    // ---- statistics (and the verdict of the boundary checks) ----
     NNS_HIP(hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, st));
     NNS_HIP(hipStreamSynchronize(st));
-    if (c[kCntJunction]) {
+    if (c[kCntFallback] || c[kCntJunction]) {
+        const int mode = is_f64 ? 1 : 2;
         if (P.radix_bytes < radix_ws_bytes(n)) return NNSORT_EINTERNAL;
         NNS_HIP(radix_sort(out, out, n, mode, mode, radix_ws, P.radix_bytes, st));
         NNS_HIP(hipStreamSynchronize(st));
@@ -430,7 +425,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     S.big_buckets = big_count;
     S.big_bucket_keys = big_keys;
     S.boundary_keys = (int64_t)c[kCntBoundary];
-    S.fallback = c[kCntJunction] ? 2 : c[kCntFallback] ? 1 : 0;
+    S.fallback = c[kCntFallback] ? 1 : c[kCntJunction] ? 2 : 0;
     S.range_resorts = (int32_t)c[kCntResorted];
     if (stats && prm->stats_level >= 2 && model) {
         double* Fbuf = (double*)K1;  // partition storage is free now

@@ -686,11 +686,13 @@ __global__ void __launch_bounds__(256) k_boundary_plan(const uint64_t* __restric
 }
 
 // One workgroup per boundary: merge tail and head (adjacent in out) in place.
+// Skipped whole when the plan reported a fallback (zones may then overlap);
+// the host sorts the whole output instead.
 __global__ void __launch_bounds__(256) k_boundary_merge(uint64_t* out, int is_f64, const Zone* __restrict__ zones,
-                                                        int64_t K) {
+                                                        int64_t K, const unsigned long long* __restrict__ counters) {
     __shared__ uint64_t buf[kZoneMax];
     int64_t k = blockIdx.x;
-    if (k >= K) return;
+    if (k >= K || counters[kCntFallback] != 0) return;
     Zone z = zones[k];
     int total = (int)(z.tail + z.head);
     if (z.tail == 0 || z.head == 0 || total > kZoneMax) return;
@@ -723,14 +725,17 @@ __global__ void __launch_bounds__(256) k_boundary_merge(uint64_t* out, int is_f6
 // not cover zones that end up side by side, or keys without a slot that are
 // not the extremes, so the junctions are checked here: one thread per range
 // (its first key, and both ends of the zone after it), one more for the start
-// of the keys without a slot above the mapped ones (at index back).
+// of the keys without a slot above the mapped ones (at index back).  Nothing
+// to check after a fallback (the whole output gets sorted), or when there
+// was no zone and every key has a slot (the plan saw every pair of
+// neighbouring ranges in order).
 __global__ void __launch_bounds__(256) k_junction_check(const uint64_t* __restrict__ out, int is_f64, int64_t base,
                                                         const int64_t* __restrict__ start,
                                                         const int32_t* __restrict__ seglist, int64_t K,
                                                         const Zone* __restrict__ zones, int64_t n, int64_t back,
-                                                        unsigned long long* counters) {
+                                                        int unmapped, unsigned long long* counters) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > K) return;
+    if (k > K || counters[kCntFallback] != 0 || (counters[kCntBoundary] == 0 && !unmapped)) return;
     bool bad = false;
     if (k == K) {
         if (back > 0 && back < n) bad = out_key(out, is_f64, back - 1) > out_key(out, is_f64, back);
@@ -749,9 +754,9 @@ __global__ void __launch_bounds__(256) k_junction_check(const uint64_t* __restri
 
 hipError_t launch_junction_check(const uint64_t* d_out, bool is_f64, int64_t base, const int64_t* d_start,
                                  const int32_t* d_seglist, int64_t K, const void* d_zones, int64_t n, int64_t back,
-                                 uint64_t* d_counters, hipStream_t st) {
+                                 bool unmapped, uint64_t* d_counters, hipStream_t st) {
     hipLaunchKernelGGL(k_junction_check, dim3((unsigned)((K + 1 + 255) / 256)), dim3(256), 0, st, d_out,
-                       is_f64 ? 1 : 0, base, d_start, d_seglist, K, (const Zone*)d_zones, n, back,
+                       is_f64 ? 1 : 0, base, d_start, d_seglist, K, (const Zone*)d_zones, n, back, unmapped ? 1 : 0,
                        (unsigned long long*)d_counters);
     return hipGetLastError();
 }
@@ -765,10 +770,11 @@ hipError_t launch_boundary_plan(const uint64_t* d_out, bool is_f64, int64_t base
     return hipGetLastError();
 }
 
-hipError_t launch_boundary_merge(uint64_t* d_out, bool is_f64, const void* d_zones, int64_t K, hipStream_t st) {
+hipError_t launch_boundary_merge(uint64_t* d_out, bool is_f64, const void* d_zones, int64_t K,
+                                const uint64_t* d_counters, hipStream_t st) {
     if (K <= 1) return hipSuccess;
     hipLaunchKernelGGL(k_boundary_merge, dim3((unsigned)(K - 1)), dim3(256), 0, st, d_out, is_f64 ? 1 : 0,
-                       (const Zone*)d_zones, K - 1);
+                       (const Zone*)d_zones, K - 1, (const unsigned long long*)d_counters);
     return hipGetLastError();
 }
 
