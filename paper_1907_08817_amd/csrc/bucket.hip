@@ -291,6 +291,9 @@ size_t polish_part_words(int64_t NB) { return (size_t)NB * kPartStride; }
 constexpr int kTile = 8;                 // keys per repair tile
 constexpr int kMaxTileRounds = 8;        // odd-even tile rounds before the whole-range re-sort
 constexpr uint32_t kGroupMax = 32;       // larger slot groups are ordered by the whole-range re-sort
+// keys of a slot group compared per step: with about 0.8 keys per slot, 99%
+// of keys are in groups of at most 4
+constexpr int kGroupStep = 4;
 
 __device__ __forceinline__ void cswap(uint64_t& a, uint64_t& b) {
     uint64_t lo = a < b ? a : b;
@@ -552,12 +555,12 @@ __global__ void __launch_bounds__(NT, CAP <= 2048 ? 7 : 4) k_bucket_polish(
                 const uint64_t me = key[k];
                 const uint32_t mine = g0[k] + rank[k];
                 uint32_t pos = g0[k];
-                for (uint32_t j0 = g0[k]; j0 < g1; j0 += 8) {
-                    uint64_t y[8];
+                for (uint32_t j0 = g0[k]; j0 < g1; j0 += kGroupStep) {
+                    uint64_t y[kGroupStep];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) y[q] = j0 + q < g1 ? sm.keys[j0 + q] : ~0ull;
+                    for (int q = 0; q < kGroupStep; ++q) y[q] = j0 + q < g1 ? sm.keys[j0 + q] : ~0ull;
 #pragma unroll
-                    for (int q = 0; q < 8; ++q)
+                    for (int q = 0; q < kGroupStep; ++q)
                         pos += (y[q] < me || (y[q] == me && j0 + q < mine)) ? 1u : 0u;
                 }
                 rank[k] = pos;
@@ -570,20 +573,26 @@ __global__ void __launch_bounds__(NT, CAP <= 2048 ? 7 : 4) k_bucket_polish(
             if (tid + k * NT < cnt) sm.keys[rank[k]] = key[k];
         }
         __syncthreads();
-        // descents remain only where f's slots jitter between neighbours
+        // written out while checked for descents, which remain only where
+        // f's slots jitter between neighbours (such a range is repaired and
+        // written again below)
         int bad = 0;
-        for (uint32_t i = tid; i + 1 < cnt; i += NT) bad |= sm.keys[i] > sm.keys[i + 1] ? 1 : 0;
+        uint64_t* o = out + base + s0;
+        for (uint32_t i = tid; i < cnt; i += NT) {
+            const uint64_t v = sm.keys[i];
+            if (i + 1 < cnt) bad |= v > sm.keys[i + 1] ? 1 : 0;
+            o[i] = order_key_inverse(v, is_f64);
+        }
         if (bad) sm.flag = 1;
         __syncthreads();
         need_repair = sm.flag != 0;
     }
     if (need_repair) {
         if (repair_range(sm, cnt, tid) && tid == 0) atomicAdd(&counters[kCntResorted], 1ull);
+        // write the range's sorted keys to their final place
+        uint64_t* o = out + base + s0;
+        for (uint32_t i = tid; i < cnt; i += NT) o[i] = order_key_inverse(sm.keys[i], is_f64);
     }
-
-    // write the range's sorted keys to their final place
-    uint64_t* o = out + base + s0;
-    for (uint32_t i = tid; i < cnt; i += NT) o[i] = order_key_inverse(sm.keys[i], is_f64);
 }
 
 // Ranges of at most kHalfCap keys: one workgroup per range id (others exit
