@@ -694,35 +694,55 @@ __global__ void __launch_bounds__(256) k_boundary_plan(const uint64_t* __restric
     zones[k] = z;
 }
 
-// One workgroup per boundary: merge tail and head (adjacent in out) in place.
+// Boundaries kMergeSpan at a time per workgroup: its threads look at one
+// zone each, the non-empty zones (usually none) are listed in LDS, and the
+// workgroup merges each one's tail and head (adjacent in out) in place.
 // Skipped whole when the plan reported a fallback (zones may then overlap);
 // the host sorts the whole output instead.
-__global__ void __launch_bounds__(256) k_boundary_merge(uint64_t* out, int is_f64, const Zone* __restrict__ zones,
-                                                        int64_t K, const unsigned long long* __restrict__ counters) {
+constexpr int kMergeSpan = 256;
+
+__global__ void __launch_bounds__(kMergeSpan) k_boundary_merge(uint64_t* out, int is_f64,
+                                                               const Zone* __restrict__ zones, int64_t K,
+                                                               const unsigned long long* __restrict__ counters) {
     __shared__ uint64_t buf[kZoneMax];
-    int64_t k = blockIdx.x;
-    if (k >= K || counters[kCntFallback] != 0) return;
-    Zone z = zones[k];
-    int total = (int)(z.tail + z.head);
-    if (z.tail == 0 || z.head == 0 || total > kZoneMax) return;
-    for (int i = threadIdx.x; i < total; i += blockDim.x) buf[i] = out_key(out, is_f64, z.start + i);
+    __shared__ int s_list[kMergeSpan];
+    __shared__ int s_n;
+    if (counters[kCntFallback] != 0) return;
+    if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
-    const uint64_t* a = buf;
-    const uint64_t* b = buf + z.tail;
-    int na = z.tail, nb = z.head;
-    int per = (total + blockDim.x - 1) / blockDim.x;
-    int d0 = threadIdx.x * per;
-    if (d0 < total) {
-        int ia = merge_split(a, na, b, nb, d0);
-        int ib = d0 - ia;
-        int d1 = d0 + per < total ? d0 + per : total;
-        for (int d = d0; d < d1; ++d) {
-            bool takeA = ib >= nb || (ia < na && a[ia] <= b[ib]);
-            uint64_t v = takeA ? a[ia] : b[ib];
-            ia += takeA ? 1 : 0;
-            ib += takeA ? 0 : 1;
-            out[z.start + d] = order_key_inverse(v, is_f64);
+    {
+        const int64_t k = (int64_t)blockIdx.x * kMergeSpan + threadIdx.x;
+        if (k < K) {
+            const Zone z = zones[k];
+            if (z.tail != 0 && z.head != 0 && z.tail + z.head <= (uint32_t)kZoneMax)
+                s_list[atomicAdd(&s_n, 1)] = (int)threadIdx.x;
         }
+    }
+    __syncthreads();
+    const int nz = s_n;
+    for (int e = 0; e < nz; ++e) {
+        const Zone z = zones[(int64_t)blockIdx.x * kMergeSpan + s_list[e]];
+        const int total = (int)(z.tail + z.head);
+        for (int i = threadIdx.x; i < total; i += kMergeSpan) buf[i] = out_key(out, is_f64, z.start + i);
+        __syncthreads();
+        const uint64_t* a = buf;
+        const uint64_t* b = buf + z.tail;
+        const int na = z.tail, nb = z.head;
+        const int per = (total + kMergeSpan - 1) / kMergeSpan;
+        const int d0 = threadIdx.x * per;
+        if (d0 < total) {
+            int ia = merge_split(a, na, b, nb, d0);
+            int ib = d0 - ia;
+            const int d1 = d0 + per < total ? d0 + per : total;
+            for (int d = d0; d < d1; ++d) {
+                const bool takeA = ib >= nb || (ia < na && a[ia] <= b[ib]);
+                const uint64_t v = takeA ? a[ia] : b[ib];
+                ia += takeA ? 1 : 0;
+                ib += takeA ? 0 : 1;
+                out[z.start + d] = order_key_inverse(v, is_f64);
+            }
+        }
+        __syncthreads();  // buf is refilled for the next zone
     }
 }
 
@@ -782,8 +802,8 @@ hipError_t launch_boundary_plan(const uint64_t* d_out, bool is_f64, int64_t base
 hipError_t launch_boundary_merge(uint64_t* d_out, bool is_f64, const void* d_zones, int64_t K,
                                 const uint64_t* d_counters, hipStream_t st) {
     if (K <= 1) return hipSuccess;
-    hipLaunchKernelGGL(k_boundary_merge, dim3((unsigned)(K - 1)), dim3(256), 0, st, d_out, is_f64 ? 1 : 0,
-                       (const Zone*)d_zones, K - 1, (const unsigned long long*)d_counters);
+    hipLaunchKernelGGL(k_boundary_merge, dim3((unsigned)((K - 1 + kMergeSpan - 1) / kMergeSpan)), dim3(kMergeSpan),
+                       0, st, d_out, is_f64 ? 1 : 0, (const Zone*)d_zones, K - 1, (const unsigned long long*)d_counters);
     return hipGetLastError();
 }
 
