@@ -78,17 +78,23 @@ __global__ void __launch_bounds__(256, 3) k_infer_bf16(InferArgs a) {
     const int j = lane & 31;
     const int g = lane >> 5;
 
-    // A operands: W2 rows 32 rb + j, columns 16 s + 8 g + t, rounded to bf16.
-    u32x4 A[RB][KS];
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
+    // A operands: W2 rows 32 rb + j, columns 16 s + 8 g + t, rounded to bf16,
+    // staged in LDS per (rb, s, lane) and read back before each product, so
+    // that they do not hold 32 VGPRs for the whole kernel (more waves per SIMD
+    // to cover latency)
+    __shared__ u32x4 s_A[RB][KS][64];
+    {
+        const int wv = threadIdx.x >> 6;
+        for (int idx = wv; idx < RB * KS; idx += 4) {
+            const int rb = idx / KS, s = idx % KS;
             const float* row = m->w2 + (32 * rb + j) * H + 16 * s + 8 * g;
+            u32x4 a;
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                A[rb][s][q] = bf16_rne_bits(row[2 * q]) | (bf16_rne_bits(row[2 * q + 1]) << 16);
+            for (int q = 0; q < 4; ++q) a[q] = bf16_rne_bits(row[2 * q]) | (bf16_rne_bits(row[2 * q + 1]) << 16);
+            s_A[rb][s][lane] = a;
         }
+    }
+    __syncthreads();
     const float b3 = m->b3;
     const double lo = m->lo, inv = m->inv_range;
     const float* __restrict__ w1g = s_w1 + 8 * g;
@@ -145,7 +151,7 @@ __global__ void __launch_bounds__(256, 3) k_infer_bf16(InferArgs a) {
             }
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
-                const bf16x8 av = as_bf16x8(A[rb][s]);
+                const bf16x8 av = as_bf16x8(s_A[rb][s][lane]);
                 acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, as_bf16x8(B0), acc[rb], 0, 0, 0);
                 if (T >= 2)
                     acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, as_bf16x8(B1), acc[rb], 0, 0, 0);

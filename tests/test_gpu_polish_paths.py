@@ -223,3 +223,44 @@ def test_model_dense_ranges_and_unmapped_keys():
     for k in ("rounds", "collided", "placed", "residue"):
         assert st[k] == ost[k], (k, st[k], ost[k])
     assert st["big_buckets"] >= 2 and st["unmapped"] > 0
+
+
+# ---------------------------------------------------------------------------
+# dense ranges: lengths at the merge-run boundaries, and a range too long for
+# the range-by-range merge (then all of the residue goes through one radix sort)
+# ---------------------------------------------------------------------------
+def slots_for_range_sizes(x, sizes, seed):
+    """Range b (in value order) gets sizes[b] keys at random slots of that
+    range; the rest of the keys spread one per slot after them."""
+    r = ranks(x)
+    rng = np.random.default_rng(seed)
+    edges = np.concatenate([[0], np.cumsum(sizes)])
+    s = np.empty(x.size, np.int64)
+    for b in range(len(sizes)):
+        sel = (r >= edges[b]) & (r < edges[b + 1])
+        s[sel] = b * RANGE_SLOTS + rng.integers(0, RANGE_SLOTS, int(sel.sum()))
+    rest = r >= edges[-1]
+    s[rest] = len(sizes) * RANGE_SLOTS + (r[rest] - edges[-1])
+    assert s.max() < O.num_slots(x.size)
+    return s
+
+
+@pytest.mark.parametrize("sizes", [[4097, 8192, 8193, 12288, 16385, 65537], [5000] * 7 + [40_000, 100]])
+def test_dense_ranges_at_run_boundaries(sizes):
+    x = W.gauss_mix(400_000, seed=28)
+    s = slots_for_range_sizes(x, sizes, seed=len(sizes))
+    cnt = range_counts(s)
+    st = sort_slots(x, s)
+    assert st["big_buckets"] == int((cnt > CAP).sum())
+    assert st["big_bucket_keys"] == int(cnt[cnt > CAP].sum())
+    assert st["fallback"] == 0
+
+
+def test_dense_range_too_long_for_merging():
+    """One range of 1.2M keys (beyond 4096 * 2^8): the residue is sorted by
+    one radix pass sequence over all of it, beside two ordinary dense ranges."""
+    x = np.concatenate([W.uniform(1_400_000, seed=29), W.edge_keys(seed=29)])
+    s = slots_for_range_sizes(x, [6000, 1_200_000, 9000], seed=3)
+    st = sort_slots(x, s)
+    assert st["big_buckets"] == 3 and st["big_bucket_keys"] == 1_215_000
+    assert st["fallback"] == 0
