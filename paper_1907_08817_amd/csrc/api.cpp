@@ -15,7 +15,7 @@ namespace nns {
 // launchers defined in the .hip translation units
 hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
-hipError_t launch_classify(const uint32_t* d_cnt, int64_t NB, int64_t big_max, int32_t* d_seglist,
+hipError_t launch_classify(const int64_t* d_start, uint32_t* d_cnt, int64_t NB, int64_t big_max, int32_t* d_seglist,
                            int32_t* d_bigbucket, int32_t* d_halflist, uint64_t* d_bsum, uint64_t* d_counters,
                            hipStream_t st);
 size_t classify_ws_words(int64_t NB);
@@ -44,7 +44,7 @@ hipError_t partition_by_range(const uint64_t* in_keys, const uint32_t* in_slots,
                               uint64_t* K0, uint32_t* S0, uint64_t* K1, uint32_t* S1, uint32_t* blockhist,
                               int* which, hipStream_t st);
 hipError_t launch_range_bounds(const uint32_t* d_sorted_slots, int64_t n, uint32_t NB, int64_t* d_start,
-                               uint32_t* d_cnt, hipStream_t st);
+                               hipStream_t st);
 hipError_t launch_check_slots(const uint32_t* d_slots, int64_t n, int64_t S, uint64_t* d_bad, hipStream_t st);
 hipError_t launch_big_chunks(const int32_t* d_bigbucket, int64_t big_count, const int64_t* d_start,
                              int64_t* d_chunk_pref, int64_t* d_gpref, hipStream_t st);
@@ -327,14 +327,13 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
                                st));
     const uint64_t* Ks = which ? K1 : K0;
     const uint32_t* Ss = which ? slots0 : S0;
-    NNS_HIP(launch_range_bounds(Ss, n, NB, start, cnt, st));
-    NNS_HIP(launch_classify(cnt, P.NB, P.big_max, seglist, bigbucket, halflist, clsum, counters, st));
+    NNS_HIP(launch_range_bounds(Ss, n, NB, start, st));
+    NNS_HIP(launch_classify(start, cnt, P.NB, P.big_max, seglist, bigbucket, halflist, clsum, counters, st));
     NNS_HIP(launch_count_neg(Ks, start, NB, n, counters + kCntUnmappedNeg, st));
     uint64_t c[kNumCounters];
-    int64_t first_unmapped = 0;
     NNS_HIP(hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, st));
-    NNS_HIP(hipMemcpyAsync(&first_unmapped, start + NB, 8, hipMemcpyDeviceToHost, st));
     NNS_HIP(hipStreamSynchronize(st));
+    const int64_t first_unmapped = (int64_t)c[kCntFirstUnmapped];
     if (c[kCntBadSlot]) return NNSORT_EINVAL;
     const int64_t big_count = (int64_t)c[kCntBigBuckets];
     const int64_t big_keys = (int64_t)c[kCntBigKeys];

@@ -74,12 +74,14 @@ __device__ __forceinline__ uint32_t below_in_wave(unsigned long long m) {
 constexpr uint32_t kHalfCap = kBucketCap / 2;
 constexpr int kClsQ = 4;  // per block: non-empty, dense, dense keys, half-full
 
-__global__ void __launch_bounds__(256) k_cls_count(const uint32_t* __restrict__ cnt, int64_t NB,
+// Also stores each range's key count, cnt[b] = start[b + 1] - start[b].
+__global__ void __launch_bounds__(256) k_cls_count(const int64_t* __restrict__ start, int64_t NB, uint32_t* cnt,
                                                    unsigned long long* bsum, unsigned long long* counters) {
     __shared__ unsigned long long s[kClsQ][4];
     __shared__ uint32_t s_max[4];
     const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const uint32_t c = b < NB ? cnt[b] : 0;
+    const uint32_t c = b < NB ? (uint32_t)(start[b + 1] - start[b]) : 0;
+    if (b < NB) cnt[b] = c;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     unsigned long long ne = __popcll(__ballot(c != 0));
     unsigned long long bg = __popcll(__ballot(c > kBucketCap));
@@ -111,8 +113,11 @@ __global__ void __launch_bounds__(256) k_cls_count(const uint32_t* __restrict__ 
             s[threadIdx.x][0] + s[threadIdx.x][1] + s[threadIdx.x][2] + s[threadIdx.x][3];
 }
 
-// Exclusive scan of the per-block counts (in place); totals to the counters.
+// Exclusive scan of the per-block counts (in place); totals to the counters,
+// with the first position of the keys without a slot (start[NB]), so that one
+// copy brings everything the host needs.
 __global__ void __launch_bounds__(256) k_cls_scan(unsigned long long* bsum, int64_t nblk,
+                                                  const int64_t* __restrict__ start, int64_t NB,
                                                   unsigned long long* counters) {
     __shared__ unsigned long long s[kClsQ][256];
     const int t = threadIdx.x;
@@ -138,6 +143,7 @@ __global__ void __launch_bounds__(256) k_cls_scan(unsigned long long* bsum, int6
             bsum[i * kClsQ + q] = run[q];
             run[q] += v;
         }
+    if (t == 0) counters[kCntFirstUnmapped] = (unsigned long long)start[NB];
     if (t == 255) {
         counters[kCntSegments] = s[0][255];
         counters[kCntBigBuckets] = s[1][255];
@@ -176,14 +182,14 @@ __global__ void __launch_bounds__(256) k_cls_write(const uint32_t* __restrict__ 
 
 size_t classify_ws_words(int64_t NB) { return (size_t)((NB + 255) / 256) * kClsQ; }
 
-hipError_t launch_classify(const uint32_t* d_cnt, int64_t NB, int64_t big_max, int32_t* d_seglist,
+hipError_t launch_classify(const int64_t* d_start, uint32_t* d_cnt, int64_t NB, int64_t big_max, int32_t* d_seglist,
                            int32_t* d_bigbucket, int32_t* d_halflist, uint64_t* d_bsum, uint64_t* d_counters,
                            hipStream_t st) {
     const int64_t nblk = (NB + 255) / 256;
     unsigned long long* bs = (unsigned long long*)d_bsum;
-    hipLaunchKernelGGL(k_cls_count, dim3((unsigned)nblk), dim3(256), 0, st, d_cnt, NB, bs,
+    hipLaunchKernelGGL(k_cls_count, dim3((unsigned)nblk), dim3(256), 0, st, d_start, NB, d_cnt, bs,
                        (unsigned long long*)d_counters);
-    hipLaunchKernelGGL(k_cls_scan, dim3(1), dim3(256), 0, st, bs, nblk, (unsigned long long*)d_counters);
+    hipLaunchKernelGGL(k_cls_scan, dim3(1), dim3(256), 0, st, bs, nblk, d_start, NB, (unsigned long long*)d_counters);
     hipLaunchKernelGGL(k_cls_write, dim3((unsigned)nblk), dim3(256), 0, st, d_cnt, NB, big_max, bs, d_seglist,
                        d_bigbucket, d_halflist);
     return hipGetLastError();

@@ -49,6 +49,7 @@ enum Counter : int {
     kCntHalfFull = 28,    // ranges of more than half the LDS capacity (and at most all of it)
     kCntJunction = 29,    // nonzero: blocks out of order after the boundary fix-up
     kCntBigMax = 30,      // keys in the largest dense range
+    kCntFirstUnmapped = 31,  // position of the first key without a slot after the partition
     kNumCounters = 32
 };
 

@@ -29,11 +29,6 @@ __global__ void __launch_bounds__(256) k_range_bounds(const uint32_t* __restrict
     start[r] = lo;
 }
 
-__global__ void __launch_bounds__(256) k_range_counts(const int64_t* __restrict__ start, uint32_t NB, uint32_t* cnt) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < (int64_t)NB) cnt[r] = (uint32_t)(start[r + 1] - start[r]);
-}
-
 __global__ void __launch_bounds__(256) k_check_slots(const uint32_t* __restrict__ s, int64_t n, int64_t S,
                                                      unsigned long long* bad) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -235,11 +230,10 @@ hipError_t partition_by_range(const uint64_t* in_keys, const uint32_t* in_slots,
 }
 
 hipError_t launch_range_bounds(const uint32_t* d_sorted_slots, int64_t n, uint32_t NB, int64_t* d_start,
-                               uint32_t* d_cnt, hipStream_t st) {
+                               hipStream_t st) {
     int64_t m = (int64_t)NB + 2;
     hipLaunchKernelGGL(k_range_bounds, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, d_sorted_slots, n, NB,
                        d_start);
-    hipLaunchKernelGGL(k_range_counts, dim3((unsigned)((NB + 255) / 256 + 1)), dim3(256), 0, st, d_start, NB, d_cnt);
     return hipGetLastError();
 }
 
