@@ -137,7 +137,7 @@ typedef struct {
     int64_t unmapped;        /* keys with no slot (F not a number, or a
                                 caller-given 0xFFFFFFFF) */
     int64_t big_buckets;     /* slot ranges too dense for one LDS tile */
-    int64_t big_bucket_keys; /* keys sorted by the radix path for that reason */
+    int64_t big_bucket_keys; /* keys sorted by the residue path for that reason */
     int64_t boundary_keys;   /* keys moved by the tile-boundary fix-up */
     int32_t fallback;        /* 0: the boundary fix-up settled every overlap;
                                 1: overlaps beyond neighbouring ranges (or a

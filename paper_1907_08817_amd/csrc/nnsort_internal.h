@@ -14,7 +14,7 @@ constexpr uint32_t kUnmapped = 0xFFFFFFFFu;
 // kBucketSlots consecutive slots; the keys predicted into one range are made
 // contiguous by a partition on the range id, and a range of at most
 // kBucketCap keys is handled by one workgroup that runs every round and the
-// polish in LDS (a "dense" range, with more keys, takes the radix path).
+// polish in LDS (a "dense" range, with more keys, takes the residue path).
 constexpr int kLogBucketSlots = 11;
 constexpr uint32_t kBucketSlots = 1u << kLogBucketSlots;
 constexpr uint32_t kBucketCap = 4096;

@@ -134,7 +134,7 @@ def gpu_sort_slots(x, slots, **kw):
 
 
 def test_constant_slot_worst_case():
-    """Every key in one slot: the densest range goes through the radix path
+    """Every key in one slot: the densest range goes through the residue path
     and each round stores one key (|c_r| = n - r)."""
     x = W.uniform(300_000, seed=1)
     slots = np.full(x.size, 12345, np.uint32)

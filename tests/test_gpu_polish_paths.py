@@ -10,13 +10,13 @@ show the branch ran:
   - slots shuffled inside each range: the whole-range re-sort;
   - slot groups larger than the group-rank limit;
   - ranges of up to half the LDS capacity, of up to all of it, and denser
-    ones (radix path) side by side;
+    ones (residue path) side by side;
   - slots scrambled across ranges: the full-sort fallback;
   - ranges whose key sets are out of value order, and keys without a slot
     that are not the extremes: overlaps the neighbour merges cannot settle;
   - NaNs, infinities, signed zeros and subnormals in dense and small ranges;
   - the model path with dense ranges and keys without a slot sharing the
-    radix path.
+    residue path.
 """
 import numpy as np
 import pytest
@@ -115,7 +115,7 @@ def test_large_slot_groups(group):
 
 
 # ---------------------------------------------------------------------------
-# the two LDS variants and the radix path side by side
+# the two LDS variants and the residue path side by side
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("jitter", [0, 1])
 def test_density_mix(jitter):
@@ -209,7 +209,7 @@ def test_edge_keys_in_every_path(layout):
 def test_model_dense_ranges_and_unmapped_keys():
     """F = relu(relu(xhat)) on xhat = (x + 1) / 2: keys below -1 all take slot
     0 and keys above 1 the last slot (two dense ranges); NaNs and infinities
-    have no slot.  Both kinds meet in the radix path."""
+    have no slot.  Both kinds meet in the residue path."""
     x = np.concatenate([np.random.default_rng(7).standard_normal(200_000)] +
                        [W.edge_keys(seed=s) for s in range(10)])
     th = np.zeros(O.num_params(1), np.float32)
