@@ -372,22 +372,32 @@ __global__ void __launch_bounds__(256) k_bwd_sample(const float* __restrict__ th
 
 // Batch reductions: block c sums samples [c*chunk, (c+1)*chunk) into its row
 // of `part` (P floats): dW2_ij = sum dz2_i h1_j, dw3_i = sum g h2_i,
-// db2 = sum dz2, dw1_j = sum dz1_j x, db1 = sum dz1, db3 = sum g.
-constexpr int kRedChunk = 512;
+// db2 = sum dz2, dw1_j = sum dz1_j x, db1 = sum dz1, db3 = sum g.  dW2 is a
+// product [H x chunk] x [chunk x H]: each thread keeps a T x T tile of it in
+// registers (T = 4 at H = 64), fed from samples staged in LDS 32 at a time,
+// two 16-byte LDS reads per sample for T^2 FMAs.  Every sum runs over the
+// samples in order, so the result does not depend on scheduling.
+constexpr int kRedChunk = 256;
 constexpr int kRedSub = 32;
 template <int H>
 __global__ void __launch_bounds__(256) k_bwd_reduce(const double* __restrict__ x, int64_t B,
                                                     const float* __restrict__ saved, const float* __restrict__ d,
                                                     const float* __restrict__ gF, float* part) {
     constexpr int P = H * H + 4 * H + 1;
-    constexpr int PER = (H * H + 255) / 256;
-    __shared__ float sh1[kRedSub][H];
-    __shared__ float sdz2[kRedSub][H];
+    constexpr int T = H >= 64 ? 4 : (H >= 32 ? 2 : 1);  // tile edge
+    constexpr int NBK = H / T;                          // tiles per dimension (<= 16)
+    static_assert(NBK * NBK <= 256, "one tile per thread");
+    __shared__ __align__(16) float sh1[kRedSub][H];
+    __shared__ __align__(16) float sdz2[kRedSub][H];
     __shared__ float sx[kRedSub], sg[kRedSub];
     const int tid = threadIdx.x;
-    float acc[PER];
+    const bool tile_on = tid < NBK * NBK;
+    const int i0 = (tid / NBK) * T, j0 = (tid % NBK) * T;
+    float acc[T][T];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) acc[q] = 0.0f;
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+        for (int c = 0; c < T; ++c) acc[a][c] = 0.0f;
     float accv = 0.0f;   // one of the 4H vector gradients per thread (tid < 4H)
     float accb3 = 0.0f;  // db3, thread 0
     const int64_t c0 = (int64_t)blockIdx.x * kRedChunk;
@@ -404,14 +414,18 @@ __global__ void __launch_bounds__(256) k_bwd_reduce(const double* __restrict__ x
             sg[tid] = b < B ? gF[b] : 0.0f;
         }
         __syncthreads();
+        if (tile_on) {
+            for (int r = 0; r < kRedSub; ++r) {
+                float u[T], w[T];
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            int e = tid + q * 256;
-            if (e < H * H) {
-                int i = e / H, j = e % H;
-                float a = acc[q];
-                for (int r = 0; r < kRedSub; ++r) a = __builtin_fmaf(sdz2[r][i], sh1[r][j], a);
-                acc[q] = a;
+                for (int a = 0; a < T; ++a) {
+                    u[a] = sdz2[r][i0 + a];
+                    w[a] = sh1[r][j0 + a];
+                }
+#pragma unroll
+                for (int a = 0; a < T; ++a)
+#pragma unroll
+                    for (int c = 0; c < T; ++c) acc[a][c] = __builtin_fmaf(u[a], w[c], acc[a][c]);
             }
         }
         if (tid == 0)
@@ -436,10 +450,11 @@ __global__ void __launch_bounds__(256) k_bwd_reduce(const double* __restrict__ x
         __syncthreads();
     }
     float* row = part + (int64_t)blockIdx.x * P;
+    if (tile_on) {
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        int e = tid + q * 256;
-        if (e < H * H) row[2 * H + e] = acc[q];
+        for (int a = 0; a < T; ++a)
+#pragma unroll
+            for (int c = 0; c < T; ++c) row[2 * H + (i0 + a) * H + (j0 + c)] = acc[a][c];
     }
     if (tid < 4 * H) {
         int p;
@@ -451,12 +466,23 @@ __global__ void __launch_bounds__(256) k_bwd_reduce(const double* __restrict__ x
     if (tid == 0) row[4 * H + H * H] = accb3;
 }
 
+// Column sums of `part` (rows x P), in a fixed order: 32 columns per block,
+// eight groups of rows summed side by side, then the eight group sums in order.
 __global__ void __launch_bounds__(256) k_sum_rows(const float* __restrict__ part, int rows, int P, float* out) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    float s = 0.0f;
-    for (int r = 0; r < rows; ++r) s += part[(int64_t)r * P + p];
-    out[p] = s;
+    __shared__ float s[8][32];
+    const int c = threadIdx.x & 31, grp = threadIdx.x >> 5;
+    const int p = blockIdx.x * 32 + c;
+    float acc = 0.0f;
+    if (p < P)
+        for (int r = grp; r < rows; r += 8) acc += part[(int64_t)r * P + p];
+    s[grp][c] = acc;
+    __syncthreads();
+    if (grp == 0 && p < P) {
+        float t = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) t += s[q][c];
+        out[p] = t;
+    }
 }
 
 // Keep the parameters with the lowest batch loss seen so far (the loss of a
@@ -598,7 +624,7 @@ static hipError_t bwd_h(const float* th, const double* x, int64_t B, const float
     int rows = (int)((B + kRedChunk - 1) / kRedChunk);
     hipLaunchKernelGGL(k_bwd_sample<H>, dim3(nblk(B, 256)), dim3(256), 0, st, th, B, saved, gF, d);
     hipLaunchKernelGGL(k_bwd_reduce<H>, dim3(rows), dim3(256), 0, st, x, B, saved, d, gF, part);
-    hipLaunchKernelGGL(k_sum_rows, dim3(nblk(P, 256)), dim3(256), 0, st, part, rows, P, gtheta);
+    hipLaunchKernelGGL(k_sum_rows, dim3((P + 31) / 32), dim3(256), 0, st, part, rows, P, gtheta);
     return hipGetLastError();
 }
 
