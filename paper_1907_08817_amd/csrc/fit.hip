@@ -281,13 +281,15 @@ __global__ void __launch_bounds__(256) k_fwd(const float* __restrict__ th, const
         h1[j] = z > 0.0f ? z : 0.0f;
     }
     float p = th[4 * H + H * H], s = 0.0f;
-    float* sh1 = saved ? saved + b * (2 * H) : nullptr;
+    // saved activations unit-major, saved[u * B + b] (h1 then h2): the
+    // threads of a wave write consecutive addresses
+    float* sh1 = saved ? saved + b : nullptr;
     for (int i = 0; i < H; ++i) {
         float z = b2[i];
 #pragma unroll
         for (int j = 0; j < H; ++j) z = __builtin_fmaf(W2[i * H + j], h1[j], z);
         float h2 = z > 0.0f ? z : 0.0f;
-        if (sh1) sh1[H + i] = h2;
+        if (sh1) sh1[(int64_t)(H + i) * B] = h2;
         float pr = w3[i] * h2;
         float r = __builtin_fmaf(w3[i], h2, -pr);
         float q;
@@ -296,7 +298,7 @@ __global__ void __launch_bounds__(256) k_fwd(const float* __restrict__ th, const
     }
     if (sh1) {
 #pragma unroll
-        for (int j = 0; j < H; ++j) sh1[j] = h1[j];
+        for (int j = 0; j < H; ++j) sh1[(int64_t)j * B] = h1[j];
     }
     F[b] = p + s;
 }
@@ -345,7 +347,8 @@ __global__ void k_loss_final(const float* __restrict__ partial, int nb, int64_t 
 
 // ---- backward ----
 // Per sample: dz2_i = g w3_i [h2_i > 0]; dz1_j = [h1_j > 0] sum_i dz2_i W2_ij.
-// Writes d = (dz1[H], dz2[H]) per sample next to the saved (h1, h2).
+// Writes d = (dz1[H], dz2[H]) per sample, unit-major like the saved (h1, h2):
+// d[u * B + b].
 template <int H>
 __global__ void __launch_bounds__(256) k_bwd_sample(const float* __restrict__ th, int64_t B,
                                                     const float* __restrict__ saved,
@@ -354,20 +357,20 @@ __global__ void __launch_bounds__(256) k_bwd_sample(const float* __restrict__ th
     if (b >= B) return;
     const float* W2 = th + 2 * H;
     const float* w3 = th + 3 * H + H * H;
-    const float* h = saved + b * (2 * H);
+    const float* h = saved + b;
     float g = gF[b];
     float dz2[H];
 #pragma unroll
-    for (int i = 0; i < H; ++i) dz2[i] = h[H + i] > 0.0f ? g * w3[i] : 0.0f;
-    float* o = d + b * (2 * H);
+    for (int i = 0; i < H; ++i) dz2[i] = h[(int64_t)(H + i) * B] > 0.0f ? g * w3[i] : 0.0f;
+    float* o = d + b;
     for (int j = 0; j < H; ++j) {
         float acc = 0.0f;
 #pragma unroll
         for (int i = 0; i < H; ++i) acc = __builtin_fmaf(dz2[i], W2[i * H + j], acc);
-        o[j] = h[j] > 0.0f ? acc : 0.0f;
+        o[(int64_t)j * B] = h[(int64_t)j * B] > 0.0f ? acc : 0.0f;
     }
 #pragma unroll
-    for (int i = 0; i < H; ++i) o[H + i] = dz2[i];
+    for (int i = 0; i < H; ++i) o[(int64_t)(H + i) * B] = dz2[i];
 }
 
 // Batch reductions: block c sums samples [c*chunk, (c+1)*chunk) into its row
@@ -389,6 +392,7 @@ __global__ void __launch_bounds__(256) k_bwd_reduce(const double* __restrict__ x
     static_assert(NBK * NBK <= 256, "one tile per thread");
     __shared__ __align__(16) float sh1[kRedSub][H];
     __shared__ __align__(16) float sdz2[kRedSub][H];
+    __shared__ float sh2[kRedSub][H], sdz1[kRedSub][H];
     __shared__ float sx[kRedSub], sg[kRedSub];
     const int tid = threadIdx.x;
     const bool tile_on = tid < NBK * NBK;
@@ -402,11 +406,15 @@ __global__ void __launch_bounds__(256) k_bwd_reduce(const double* __restrict__ x
     float accb3 = 0.0f;  // db3, thread 0
     const int64_t c0 = (int64_t)blockIdx.x * kRedChunk;
     for (int64_t s0 = c0; s0 < c0 + kRedChunk && s0 < B; s0 += kRedSub) {
+        // unit-major sources: consecutive threads read consecutive samples
         for (int e = tid; e < kRedSub * H; e += 256) {
-            int r = e / H, c = e % H;
+            int r = e % kRedSub, c = e / kRedSub;
             int64_t b = s0 + r;
-            sh1[r][c] = b < B ? saved[b * (2 * H) + c] : 0.0f;
-            sdz2[r][c] = b < B ? d[b * (2 * H) + H + c] : 0.0f;
+            const bool ok = b < B;
+            sh1[r][c] = ok ? saved[(int64_t)c * B + b] : 0.0f;
+            sh2[r][c] = ok ? saved[(int64_t)(H + c) * B + b] : 0.0f;
+            sdz1[r][c] = ok ? d[(int64_t)c * B + b] : 0.0f;
+            sdz2[r][c] = ok ? d[(int64_t)(H + c) * B + b] : 0.0f;
         }
         if (tid < kRedSub) {
             int64_t b = s0 + tid;
@@ -436,13 +444,13 @@ __global__ void __launch_bounds__(256) k_bwd_reduce(const double* __restrict__ x
                 if (b >= B) break;
                 float v;
                 if (tid < H) {  // dw1_j = dz1_j x
-                    v = d[b * (2 * H) + tid] * sx[r];
+                    v = sdz1[r][tid] * sx[r];
                 } else if (tid < 2 * H) {  // db1_j = dz1_j
-                    v = d[b * (2 * H) + tid - H];
+                    v = sdz1[r][tid - H];
                 } else if (tid < 3 * H) {  // db2_i = dz2_i
                     v = sdz2[r][tid - 2 * H];
                 } else {  // dw3_i = g h2_i
-                    v = sg[r] * saved[b * (2 * H) + H + (tid - 3 * H)];
+                    v = sg[r] * sh2[r][tid - 3 * H];
                 }
                 accv += v;
             }
