@@ -124,6 +124,10 @@ def main():
     else:
         k = o ^ top
     sorted_ok = bool((k[1:] >= k[:-1]).all().item())
+    # model quality, outside the timed region: mean |F(key) n - rank| / n
+    # over the sorted output, with F from the timed form's map kernel
+    _, st2 = run_sort(nn.sort_params(form=form_code, bf16_terms=args.bf16_terms, stats_level=2))
+    pos_err = {"form": st2["pos_err"]}
 
     # roofline of the dominant kernel: the model map (inference + hand-off)
     k1_ms = float(np.mean(infer_ms))
@@ -166,6 +170,8 @@ def main():
         context["fp32_form_ms"] = round(fp32_ms, 3)
         context["fp32_infer_ms"] = round(st32["t_infer_ms"], 3)
         context["bf16_vs_fp32"] = round(fp32_ms / ms_per_step, 3)
+        _, st32 = run_sort(nn.sort_params(form=nn.FORM_FP32, stats_level=2))
+        pos_err["fp32_form"] = st32["pos_err"]
         # full-n GPU LSD radix sort
         rws = nn.alloc_workspace(nn._lib().nnsort_radix_workspace_size(n), dev)
         nn.nnsort_radix_sort(keys, out=out, ws=rws)
@@ -224,6 +230,7 @@ def main():
         "rounds": stats["rounds"],
         "collided_frac": [round(v / n, 5) for v in c],
         "residue_frac": round(ct / n, 5),
+        "pos_err": {k: float(f"{v:.5g}") for k, v in pos_err.items()},
         "boundary_keys": stats["boundary_keys"],
         "fallback": stats["fallback"], "range_resorts": stats["range_resorts"],
         "big_bucket_keys": stats["big_bucket_keys"],

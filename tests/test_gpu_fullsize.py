@@ -125,6 +125,10 @@ def test_fullsize_matches_oracle(cfg):
     assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
     for k in ("rounds", "collided", "placed", "residue"):
         assert st[k] == ost[k], (k, st[k], ost[k])
+    # mean |F n - rank| / n: the FP32 form's F is the oracle's bit for bit,
+    # so only the order of the sum differs
+    pe = O.pos_err(ref, md, O.FORM_FP32C)
+    assert abs(st["pos_err"] - pe) <= 1e-9 * pe + 1e-15, (st["pos_err"], pe)
     assert 0.0 <= st["pos_err"] < 0.05
 
 
@@ -194,6 +198,19 @@ def test_fullsize_gauss_mix_1e8_bf16():
     d = np.abs(got - ref)
     assert np.all(d[okm] <= bound[okm] + 1e-300), float(np.max(d[okm] / bound[okm]))
     assert 0.0 <= st["pos_err"] < 0.05
+    # model quality, reported: mean |F n - rank| / n of the map kernel (over
+    # every key) beside the FP64 model and the FP64 model with W2 rounded to
+    # bf16 (over every 1000th sorted position).  The map kernel's F stays
+    # within the bound above of the bf16-W2 model's, so the two means differ
+    # by little more than the sampling.
+    pos = np.arange(0, x.size, 1000)
+    xo = out[torch.from_numpy(pos).to(DEV)].cpu().numpy()
+    xh, okm = O.translate(xo, md["lo"], md["inv_range"])
+    est = {f: float(np.mean(np.abs(O.eval_F(xh[okm], md, f) * x.size - pos[okm]))) / x.size
+           for f in (O.FORM_FP64, O.FORM_BF16W)}
+    print(f"pos_err: map kernel {st['pos_err']:.6g}, FP64 model {est[O.FORM_FP64]:.6g}, "
+          f"FP64 model with bf16 W2 {est[O.FORM_BF16W]:.6g}")
+    assert abs(st["pos_err"] - est[O.FORM_BF16W]) <= 0.05 * est[O.FORM_BF16W] + 1e-6
 
 
 # ---------------------------------------------------------------------------
