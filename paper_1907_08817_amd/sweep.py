@@ -7,7 +7,8 @@
 
 params: one device-fitted model, then sorts with eps = 1..5 (eps = 1 is a
 single mapping round, the SageDB-style one-pass use of the model), m in
-{1.0, 1.25, 1.5, 2.0} and tau in {0, 1024, 1e6}; per setting the rounds run,
+{1.0, 1.25, 1.5, 2.0}, tau in {0, 1024, 1e6} and, for the BF16 form, 1..3 bf16
+terms per activation; per setting the rounds run,
 the conflict array after each round as a fraction of n, and the time of each
 phase (Sec. 4, Exp-4: the number of iterations; Sec. 3: the relaxation factor
 m trades slots for conflicts).
@@ -85,6 +86,21 @@ def sweep_params(args, torch, dev):
                           "rounds": st["rounds"], "conflict_frac": [round(c / n, 5) for c in st["collided"][:st["rounds"]]],
                           "residue_frac": round(st["residue"] / n, 5), "ms": round(ms, 3),
                           "gkeys_s": round(n / ms / 1e6, 3), "phases": _phases(st)}), flush=True)
+    if fc != FORM_BF16:
+        return
+    # the number of bf16 terms each hidden activation is split into: 1 is a
+    # plain bf16 activation, 3 carries all 24 bits of the FP32 value
+    for terms in (1, 2, 3):
+        sp = sort_params(form=fc, bf16_terms=terms, stats_level=2)
+        _, st2 = nnsort_sort_with_model(model, keys, out=out, sp=sp, ws=ws)
+        sp = sort_params(form=fc, bf16_terms=terms, stats_level=1)
+        ms, (_, st) = _timed(lambda: nnsort_sort_with_model(model, keys, out=out, sp=sp, ws=ws), args.reps, torch)
+        print(json.dumps({"sweep": "params", "workload": args.workload, "n": n, "bf16_terms": terms,
+                          "pos_err": float(f"{st2['pos_err']:.5g}"), "rounds": st["rounds"],
+                          "conflict_frac": [round(c / n, 5) for c in st["collided"][:st["rounds"]]],
+                          "residue_frac": round(st["residue"] / n, 5), "fallback": st["fallback"],
+                          "ms": round(ms, 3), "gkeys_s": round(n / ms / 1e6, 3), "phases": _phases(st)}),
+              flush=True)
 
 
 def sweep_shift(args, torch, dev):
