@@ -115,3 +115,15 @@ def test_parameter_names_are_checked():
     with pytest.raises(TypeError):
         nn.fit_params(delta=0.1)
     assert nn.fit_params(huber_delta=0.25).huber_delta == 0.25
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU: asked for more it exits with a message
+    before touching any device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
