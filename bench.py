@@ -172,6 +172,21 @@ def main():
         context["bf16_vs_fp32"] = round(fp32_ms / ms_per_step, 3)
         _, st32 = run_sort(nn.sort_params(form=nn.FORM_FP32, stats_level=2))
         pos_err["fp32_form"] = st32["pos_err"]
+        # piecewise-linear form on the same weights
+        sppw = nn.sort_params(form=nn.FORM_PWL, stats_level=1)
+        run_sort(sppw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, stpw = run_sort(sppw)
+        torch.cuda.synchronize()
+        pw_ms = (time.perf_counter() - t0) * 1e3 / reps
+        context["pwl_form_gkeys"] = round(n / (pw_ms * 1e-3) / 1e9, 3)
+        context["pwl_form_ms"] = round(pw_ms, 3)
+        context["pwl_infer_ms"] = round(stpw["t_infer_ms"], 3)
+        context["pwl_collided_frac"] = [round(v / n, 5) for v in stpw["collided"]]
+        _, stpw = run_sort(nn.sort_params(form=nn.FORM_PWL, stats_level=2))
+        pos_err["pwl_form"] = stpw["pos_err"]
         # full-n GPU LSD radix sort
         rws = nn.alloc_workspace(nn._lib().nnsort_radix_workspace_size(n), dev)
         nn.nnsort_radix_sort(keys, out=out, ws=rws)

@@ -55,7 +55,7 @@ typedef enum {
     NNSORT_EINTERNAL = -6    /* a device-side consistency check failed */
 } nnsort_status;
 
-typedef enum { NNSORT_FORM_FP32 = 0, NNSORT_FORM_BF16 = 1 } nnsort_form;
+typedef enum { NNSORT_FORM_FP32 = 0, NNSORT_FORM_BF16 = 1, NNSORT_FORM_PWL = 2 } nnsort_form;
 
 /* Parameters of the sorting procedure (Sec. 2, Procedure NN-sort).
  *  m          relaxation factor; slots = round(F * m * n), S = round(m n) + 1
@@ -65,8 +65,12 @@ typedef enum { NNSORT_FORM_FP32 = 0, NNSORT_FORM_BF16 = 1 } nnsort_form;
  *  tau        a round runs only while the conflict array holds more than tau
  *             keys; n <= tau sorts conventionally.
  *  form       model inference arithmetic: NNSORT_FORM_FP32 (FP32 vector ALU,
- *             one fixed operation order) or NNSORT_FORM_BF16 (hidden layer on
- *             bf16 matrix cores, FP32 accumulation).
+ *             one fixed operation order), NNSORT_FORM_BF16 (hidden layer on
+ *             bf16 matrix cores, FP32 accumulation) or NNSORT_FORM_PWL (the
+ *             FP64 model through its piecewise-linear form: a one-input ReLU
+ *             network is affine between at most (H + 1)^2 breakpoints, which
+ *             the call computes from the weights on the device; each key then
+ *             costs a search among the breakpoints and one FP64 fma).
  *  bf16_terms number of bf16 terms each hidden-1 activation is split into
  *             for the matrix product (1..3).
  *  stats_level 0: none; 1: round counts and phase times; 2: also the mean
@@ -203,7 +207,8 @@ int nnsort_sort(const void* d_in, void* d_out, int64_t n, nnsort_dtype dtype,
  * normalised position, as a double; NaN for unmappable keys) and its slot
  * round(F m n) clamped to [0, m n] (0xFFFFFFFF for unmappable keys).  Either
  * output may be NULL.  d_ws must hold nnsort_model_device_bytes() bytes (the
- * device copy of the model).  Synchronises the stream. */
+ * device copy of the model, and the piecewise-linear form's table).
+ * Synchronises the stream. */
 size_t nnsort_model_device_bytes(void);
 int nnsort_predict(const nnsort_model* model, const void* d_in, int64_t n, nnsort_dtype dtype,
                    const nnsort_sort_params* params, uint32_t* d_slots, double* d_F, void* d_ws,

@@ -23,7 +23,7 @@ NNSORT_ABI_VERSION = 1
 MAX_HIDDEN = 64
 MAX_EPS = 8
 F64, U64 = 0, 1
-FORM_FP32, FORM_BF16 = 0, 1
+FORM_FP32, FORM_BF16, FORM_PWL = 0, 1, 2
 STATUS = {0: "OK", -1: "EINVAL", -2: "EWORKSPACE", -3: "EHIP", -4: "EMODEL", -5: "EIO", -6: "EINTERNAL"}
 
 

@@ -101,6 +101,10 @@ int fail_hip(hipError_t e, const char* where) {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Device copy of the model, followed by the piecewise-linear form's table.
+size_t model_region_bytes() { return align256(sizeof(DevModel)) + align256(sizeof(PwlTable)); }
+PwlTable* pwl_table_of(void* model_region) { return (PwlTable*)((char*)model_region + align256(sizeof(DevModel))); }
+
 int64_t num_slots(int64_t n, double m) {
     double M = m * (double)n;
     double t = std::trunc(M);
@@ -113,7 +117,7 @@ bool valid_sort_params(const nnsort_sort_params* p, int64_t n) {
     if (!(p->m > 0.0) || !std::isfinite(p->m)) return false;
     if (p->eps < 1 || p->eps > NNSORT_MAX_EPS) return false;
     if (p->tau < 0) return false;
-    if (p->form != NNSORT_FORM_FP32 && p->form != NNSORT_FORM_BF16) return false;
+    if (p->form != NNSORT_FORM_FP32 && p->form != NNSORT_FORM_BF16 && p->form != NNSORT_FORM_PWL) return false;
     if (p->bf16_terms < 1 || p->bf16_terms > 3) return false;
     if (n >= (int64_t)0xFFFFFFFF) return false;
     if (p->m * (double)n >= 4294967294.0) return false;
@@ -184,7 +188,7 @@ SortPlan plan_sort(int64_t n, double m) {
     p.off_zones = take((size_t)p.NB * zone_bytes());
     p.off_G = take(nn * 8);
     p.off_big_hist = take((size_t)p.big_max * kBucketSlots * 4);
-    p.off_model = take(sizeof(DevModel));
+    p.off_model = take(model_region_bytes());
     p.radix_bytes = radix_ws_bytes(n);
     p.off_radix = take(p.radix_bytes);
     p.total = o;
@@ -304,6 +308,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     // ---- input phase + map: a slot per key ----
     InferArgs ia{};
     ia.model = dmodel;
+    ia.pwl = pwl_table_of(dmodel);
     ia.in = (const uint64_t*)d_in;
     ia.n = n;
     ia.is_f64 = is_f64 ? 1 : 0;
@@ -667,7 +672,7 @@ int nnsort_workspace_size(int64_t n, nnsort_dtype dtype, const nnsort_sort_param
         SortPlan P = plan_sort(n, sp->m);
         need = P.total > need ? P.total : need;
     }
-    need = need > align256(sizeof(DevModel)) ? need : align256(sizeof(DevModel));
+    need = need > model_region_bytes() ? need : model_region_bytes();
     if (fp) {
         if (!valid_fit_params(fp)) return NNSORT_EINVAL;
         FitPlan F = plan_fit(n > 0 ? n : 1, fp);
@@ -729,7 +734,7 @@ int nnsort_sort(const void* d_in, void* d_out, int64_t n, nnsort_dtype dtype, co
     return NNSORT_OK;
 }
 
-size_t nnsort_model_device_bytes(void) { return align256(sizeof(DevModel)); }
+size_t nnsort_model_device_bytes(void) { return model_region_bytes(); }
 
 int nnsort_predict(const nnsort_model* model, const void* d_in, int64_t n, nnsort_dtype dtype,
                    const nnsort_sort_params* params, uint32_t* d_slots, double* d_F, void* d_ws, size_t ws_bytes,
@@ -738,7 +743,7 @@ int nnsort_predict(const nnsort_model* model, const void* d_in, int64_t n, nnsor
     if (rc) return rc;
     if (n < 0 || (n > 0 && !d_in) || !valid_sort_params(params, n)) return NNSORT_EINVAL;
     if (dtype != NNSORT_F64 && dtype != NNSORT_U64) return NNSORT_EINVAL;
-    if (!d_ws || ws_bytes < sizeof(DevModel)) return NNSORT_EWORKSPACE;
+    if (!d_ws || ws_bytes < model_region_bytes()) return NNSORT_EWORKSPACE;
     if (n == 0) return NNSORT_OK;
     hipStream_t st = (hipStream_t)stream;
     DevModel hm;
@@ -746,6 +751,7 @@ int nnsort_predict(const nnsort_model* model, const void* d_in, int64_t n, nnsor
     NNS_HIP(hipMemcpyAsync(d_ws, &hm, sizeof(hm), hipMemcpyHostToDevice, st));
     InferArgs ia{};
     ia.model = (const DevModel*)d_ws;
+    ia.pwl = pwl_table_of(d_ws);
     ia.in = (const uint64_t*)d_in;
     ia.n = n;
     ia.is_f64 = dtype == NNSORT_F64;

@@ -93,8 +93,34 @@ SortPlan plan_sort(int64_t n, double m);
 size_t radix_ws_bytes(int64_t n);
 
 // ---- launchers (each returns hipError_t of its launch) ----
+// The model compiled into its piecewise-linear form (a network with one
+// input and ReLU units is affine between breakpoints): each layer-1 unit
+// switches at one input, which cuts [0, 1] into at most H + 1 intervals; on
+// each interval every layer-2 unit is affine, z2 = A x + B, and changes sign
+// at most once inside it.  F is affine on each resulting piece:
+// F(x) = Fq[q] + alpha[q] (x - xq[q]) for the last q with xq[q] <= x.
+// Built on the device for every call that uses the form; the map kernel
+// indexes the pieces by kPwlGrid cells of [0, 1] to bracket its search.
+constexpr int kPwlMaxIntervals = NNSORT_MAX_HIDDEN + 1;
+constexpr int kPwlMaxPieces = kPwlMaxIntervals * (NNSORT_MAX_HIDDEN + 1);
+constexpr int kPwlGrid = 1024;
+struct PwlTable {
+    int32_t nint;     // layer-1 intervals
+    int32_t npieces;  // pieces in all
+    double edge[kPwlMaxIntervals + 1];
+    int32_t nroots[kPwlMaxIntervals];  // layer-2 sign changes inside each interval
+    double A[kPwlMaxIntervals][NNSORT_MAX_HIDDEN];
+    double B[kPwlMaxIntervals][NNSORT_MAX_HIDDEN];
+    double sub[kPwlMaxIntervals][NNSORT_MAX_HIDDEN + 2];  // sorted piece edges per interval
+    double xq[kPwlMaxPieces];
+    double alpha[kPwlMaxPieces];
+    double Fq[kPwlMaxPieces];
+};
+static_assert(kPwlMaxPieces < 65536, "piece index is 16-bit");
+
 struct InferArgs {
     const DevModel* model;
+    PwlTable* pwl;  // the piecewise-linear form's table (that form only)
     const uint64_t* in;
     int64_t n;
     int is_f64;

@@ -52,13 +52,15 @@ def mag_bf16(model, xh):
     return np.abs(b3) + a2 @ np.abs(w3)
 
 
-def run_config(cfg, stats_level=2):
+def run_config(cfg, stats_level=2, form_code=None):
     name, n, H, form, frac = W.CONFIGS[cfg]
     x = W.make(name, n)
     is_f64 = x.dtype == np.float64
     keys = torch.from_numpy(x if is_f64 else x.view(np.int64)).to(DEV)
     dt = nn.F64 if is_f64 else nn.U64
-    sp = nn.sort_params(form=nn.FORM_BF16 if form == "bf16" else nn.FORM_FP32, stats_level=stats_level)
+    if form_code is None:
+        form_code = nn.FORM_BF16 if form == "bf16" else nn.FORM_FP32
+    sp = nn.sort_params(form=form_code, stats_level=stats_level)
     fp = nn.fit_params(hidden=H, sample_frac=frac)
     ws = nn.alloc_workspace(nn.workspace_size(n, dt, sp, fp), DEV)
     model = nn.nnsort_fit(keys, fp, ws=ws)
@@ -211,6 +213,32 @@ def test_fullsize_gauss_mix_1e8_bf16():
     print(f"pos_err: map kernel {st['pos_err']:.6g}, FP64 model {est[O.FORM_FP64]:.6g}, "
           f"FP64 model with bf16 W2 {est[O.FORM_BF16W]:.6g}")
     assert abs(st["pos_err"] - est[O.FORM_BF16W]) <= 0.05 * est[O.FORM_BF16W] + 1e-6
+
+
+# ---------------------------------------------------------------------------
+# the same 1e8 Gaussian mixture through the piecewise-linear form
+# ---------------------------------------------------------------------------
+def test_fullsize_gauss_mix_1e8_pwl():
+    x, keys, out, model, sp, st = run_config("gauss_mix_1e8_bf16_h64", form_code=nn.FORM_PWL)
+    check_sorted_permutation(keys, out, True)
+    check_sampled_ranks(x, out, True, 24)
+    check_round_counts(model, keys, sp, st)
+    md = nn.model_to_dict(model)
+    idx, xs = sample_keys(x, 100_000)
+    _, F = nn.nnsort_predict(model, keys, sp, want_slots=False)
+    got = F[torch.from_numpy(idx).to(DEV)].cpu().numpy()
+    xh, okm = O.translate(xs, md["lo"], md["inv_range"])
+    ref = O.eval_F(xh, md, O.FORM_FP64)
+    # both sides round sums of terms bounded by the un-cancelled magnitude
+    H = md["H"]
+    th = md["theta"].astype(np.float64)
+    w1, b1 = th[:H], th[H:2 * H]
+    W2 = th[2 * H:2 * H + H * H].reshape(H, H)
+    b2, w3, b3 = th[2 * H + H * H:3 * H + H * H], th[3 * H + H * H:4 * H + H * H], th[-1]
+    mag = abs(b3) + float(np.abs(w3) @ (np.abs(b2) + np.abs(W2) @ (np.abs(w1) + np.abs(b1))))
+    bound = (4 * H + 16) * 2.0 ** -53 * mag
+    assert np.all(np.abs(got[okm] - ref[okm]) <= bound), float(np.max(np.abs(got[okm] - ref[okm])) / bound)
+    assert 0.0 <= st["pos_err"] < 0.05
 
 
 # ---------------------------------------------------------------------------
