@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="gauss_mix_1e8_bf16_h64")
     ap.add_argument("--n", type=int, default=0, help="override the key count (testing only)")
+    ap.add_argument("--form", choices=["config", "bf16", "fp32", "pwl"], default="config",
+                    help="map form; 'config' takes the workload's (bf16 for the headline workload)")
     ap.add_argument("--bf16-terms", type=int, default=3)
     ap.add_argument("--no-context", action="store_true", help="skip FP32/radix/CPU context legs")
     ap.add_argument("--cpu-sample", type=int, default=20_000_000)
@@ -80,6 +82,8 @@ def main():
     from paper_1907_08817_amd import workloads as W
 
     name, n_cfg, H, form, frac = W.CONFIGS[args.workload]
+    if args.form != "config":
+        form = args.form
     n = args.n or n_cfg
     t0 = time.time()
     x = W.make(name, n)
@@ -89,7 +93,7 @@ def main():
     out = torch.empty_like(keys)
     dt = nn.F64 if x.dtype == np.float64 else nn.U64
 
-    form_code = nn.FORM_BF16 if form == "bf16" else nn.FORM_FP32
+    form_code = {"bf16": nn.FORM_BF16, "fp32": nn.FORM_FP32, "pwl": nn.FORM_PWL}[form]
     sp = nn.sort_params(form=form_code, bf16_terms=args.bf16_terms, stats_level=1)
     fp = nn.fit_params(hidden=H, sample_frac=frac)
     ws = nn.alloc_workspace(nn.workspace_size(n, dt, sp, fp), dev)
@@ -124,25 +128,39 @@ def main():
     else:
         k = o ^ top
     sorted_ok = bool((k[1:] >= k[:-1]).all().item())
-    # model quality, outside the timed region: mean |F(key) n - rank| / n
-    # over the sorted output, with F from the timed form's map kernel
-    _, st2 = run_sort(nn.sort_params(form=form_code, bf16_terms=args.bf16_terms, stats_level=2))
-    pos_err = {"form": st2["pos_err"]}
+    # model quality, outside the timed region (a context leg: its extra map
+    # launch writes F instead of slots): mean |F(key) n - rank| / n over the
+    # sorted output, with F from the timed form's map kernel
+    pos_err = {}
+    if not args.no_context:
+        _, st2 = run_sort(nn.sort_params(form=form_code, bf16_terms=args.bf16_terms, stats_level=2))
+        pos_err["form"] = st2["pos_err"]
 
     # roofline of the dominant kernel: the model map (inference + hand-off)
     k1_ms = float(np.mean(infer_ms))
     flop_per_key = 2 * (2 * H + H * H)
     achieved_tflops = flop_per_key * n / (k1_ms * 1e-3) / 1e12
-    kname = f"k_infer_bf16<{64 if H > 32 else 32},{args.bf16_terms}>" if form == "bf16" else \
-        f"k_infer_fp32<{64 if H > 32 else 32}>"
-    ksha = src_sha(["paper_1907_08817_amd/csrc/infer_bf16.hip" if form == "bf16" else
-                    "paper_1907_08817_amd/csrc/infer.hip", "paper_1907_08817_amd/csrc/infer_common.h"])
-    traffic = load_traffic(kname, ksha)
-    peak = BF16_PEAK_TFLOPS if form == "bf16" else FP32_VALU_PEAK_TFLOPS
-    roofline = {"bound": "mfma" if form == "bf16" else "alu", "kernel": kname,
-                "achieved": round(achieved_tflops, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved_tflops / peak, 5), "traffic": traffic,
-                "flop_per_key": flop_per_key, "keys_per_launch": n, "avg_launch_ms": round(k1_ms, 4)}
+    if form == "pwl":
+        # HBM-bound: 8 bytes read and a 4-byte slot written per key; the map
+        # time includes the two launches that compile the pieces
+        kname = "k_infer_pwl"
+        traffic = load_traffic(kname, src_sha(["paper_1907_08817_amd/csrc/infer_pwl.hip",
+                                               "paper_1907_08817_amd/csrc/infer_common.h"]))
+        achieved_gbs = 12 * n / (k1_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 5), "traffic": traffic,
+                    "bytes_per_key": 12, "keys_per_launch": n, "avg_launch_ms": round(k1_ms, 4)}
+    else:
+        kname = f"k_infer_bf16<{64 if H > 32 else 32},{args.bf16_terms}>" if form == "bf16" else \
+            f"k_infer_fp32<{64 if H > 32 else 32}>"
+        ksha = src_sha(["paper_1907_08817_amd/csrc/infer_bf16.hip" if form == "bf16" else
+                        "paper_1907_08817_amd/csrc/infer.hip", "paper_1907_08817_amd/csrc/infer_common.h"])
+        traffic = load_traffic(kname, ksha)
+        peak = BF16_PEAK_TFLOPS if form == "bf16" else FP32_VALU_PEAK_TFLOPS
+        roofline = {"bound": "mfma" if form == "bf16" else "alu", "kernel": kname,
+                    "achieved": round(achieved_tflops, 3), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(achieved_tflops / peak, 5), "traffic": traffic,
+                    "flop_per_key": flop_per_key, "keys_per_launch": n, "avg_launch_ms": round(k1_ms, 4)}
 
     # whole-sort algorithmic HBM bytes: keys read, placed keys written/read,
     # conflict (key, slot) pairs written/read, residue radix passes, output
@@ -169,9 +187,10 @@ def main():
         context["fp32_form_gkeys"] = round(n / (fp32_ms * 1e-3) / 1e9, 3)
         context["fp32_form_ms"] = round(fp32_ms, 3)
         context["fp32_infer_ms"] = round(st32["t_infer_ms"], 3)
-        context["bf16_vs_fp32"] = round(fp32_ms / ms_per_step, 3)
+        context[f"{form}_vs_fp32"] = round(fp32_ms / ms_per_step, 3)
         _, st32 = run_sort(nn.sort_params(form=nn.FORM_FP32, stats_level=2))
         pos_err["fp32_form"] = st32["pos_err"]
+    if not args.no_context and form != "pwl":
         # piecewise-linear form on the same weights
         sppw = nn.sort_params(form=nn.FORM_PWL, stats_level=1)
         run_sort(sppw)
@@ -187,6 +206,7 @@ def main():
         context["pwl_collided_frac"] = [round(v / n, 5) for v in stpw["collided"]]
         _, stpw = run_sort(nn.sort_params(form=nn.FORM_PWL, stats_level=2))
         pos_err["pwl_form"] = stpw["pos_err"]
+    if not args.no_context:
         # full-n GPU LSD radix sort
         rws = nn.alloc_workspace(nn._lib().nnsort_radix_workspace_size(n), dev)
         nn.nnsort_radix_sort(keys, out=out, ws=rws)
@@ -209,7 +229,7 @@ def main():
         m = min(args.cpu_sample, n)
         xs = x[:m]
         mdict = nn.model_to_dict(model)
-        formc = oracle.FORM_BF16W if form == "bf16" else oracle.FORM_FP32C
+        formc = {"bf16": oracle.FORM_BF16W, "fp32": oracle.FORM_FP32C, "pwl": oracle.FORM_FP64}[form]
         t0 = time.perf_counter()
         oracle.nnsort(xs, mdict, form=formc)
         cpu_s = time.perf_counter() - t0
@@ -229,11 +249,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16" if form == "bf16" else "fp32",
+        "dtype": {"bf16": "bf16", "fp32": "fp32", "pwl": "f64"}[form],
         "data": "synthetic",
         "config": {"workload": args.workload, "distribution": name, "n": n,
                    "keys": "f64" if dt == nn.F64 else "u64", "hidden": H,
-                   "form": f"bf16x{args.bf16_terms}" if form == "bf16" else "fp32",
+                   "form": {"bf16": f"bf16x{args.bf16_terms}", "fp32": "fp32", "pwl": "piecewise-linear f64"}[form],
                    "m": 1.25, "eps": 3, "tau": 1024, "fit": f"device, {frac:g} sample, 200 Adam steps, "
                                                           "outside the timed region"},
         "roofline": roofline,

@@ -48,7 +48,7 @@ typedef enum { NNSORT_F64 = 0, NNSORT_U64 = 1 } nnsort_dtype;
 typedef enum {
     NNSORT_OK = 0,
     NNSORT_EINVAL = -1,      /* bad argument (null pointer, size, range) */
-    NNSORT_EWORKSPACE = -2,  /* workspace smaller than nnsort_workspace_size() */
+    NNSORT_EWORKSPACE = -2,  /* workspace smaller than nnsort_workspace_size(), or not 256-byte aligned */
     NNSORT_EHIP = -3,        /* a HIP runtime call failed */
     NNSORT_EMODEL = -4,      /* malformed model (hidden width, version) */
     NNSORT_EIO = -5,         /* model file could not be read or written */
@@ -207,8 +207,8 @@ int nnsort_sort(const void* d_in, void* d_out, int64_t n, nnsort_dtype dtype,
  * normalised position, as a double; NaN for unmappable keys) and its slot
  * round(F m n) clamped to [0, m n] (0xFFFFFFFF for unmappable keys).  Either
  * output may be NULL.  d_ws must hold nnsort_model_device_bytes() bytes (the
- * device copy of the model, and the piecewise-linear form's table).
- * Synchronises the stream. */
+ * device copy of the model, and the piecewise-linear form's table), aligned
+ * to 256 bytes (EWORKSPACE otherwise).  Synchronises the stream. */
 size_t nnsort_model_device_bytes(void);
 int nnsort_predict(const nnsort_model* model, const void* d_in, int64_t n, nnsort_dtype dtype,
                    const nnsort_sort_params* params, uint32_t* d_slots, double* d_F, void* d_ws,

@@ -272,7 +272,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     }
 
     SortPlan P = plan_sort(n, prm->m);
-    if (!d_ws || ws_bytes < P.total) return NNSORT_EWORKSPACE;
+    if (!d_ws || ws_bytes < P.total || ((uintptr_t)d_ws & 255u)) return NNSORT_EWORKSPACE;
     char* ws = (char*)d_ws;
     uint64_t* counters = (uint64_t*)(ws + P.off_counters);
     uint32_t* cnt = (uint32_t*)(ws + P.off_cnt);
@@ -743,7 +743,7 @@ int nnsort_predict(const nnsort_model* model, const void* d_in, int64_t n, nnsor
     if (rc) return rc;
     if (n < 0 || (n > 0 && !d_in) || !valid_sort_params(params, n)) return NNSORT_EINVAL;
     if (dtype != NNSORT_F64 && dtype != NNSORT_U64) return NNSORT_EINVAL;
-    if (!d_ws || ws_bytes < model_region_bytes()) return NNSORT_EWORKSPACE;
+    if (!d_ws || ws_bytes < model_region_bytes() || ((uintptr_t)d_ws & 255u)) return NNSORT_EWORKSPACE;
     if (n == 0) return NNSORT_OK;
     hipStream_t st = (hipStream_t)stream;
     DevModel hm;
@@ -866,7 +866,7 @@ const char* nnsort_strerror(int status) {
     switch (status) {
     case NNSORT_OK: return "ok";
     case NNSORT_EINVAL: return "invalid argument";
-    case NNSORT_EWORKSPACE: return "workspace too small";
+    case NNSORT_EWORKSPACE: return "workspace too small or not 256-byte aligned";
     case NNSORT_EHIP: return g_last_error[0] ? g_last_error : "HIP runtime error";
     case NNSORT_EMODEL: return "malformed model";
     case NNSORT_EIO: return "model file I/O error";

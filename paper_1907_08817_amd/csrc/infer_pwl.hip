@@ -21,21 +21,37 @@
 
 namespace nns {
 
+template <int H>
 __global__ void __launch_bounds__(64) k_pwl_intervals(const DevModel* __restrict__ m, PwlTable* __restrict__ t) {
+    __shared__ double s_w1[64], s_b1[64];
     __shared__ double s_c[64];
     __shared__ int s_ok[64];
     __shared__ double s_e[kPwlMaxIntervals + 1];
-    const int H = m->H;
     const int lane = threadIdx.x;
+    // W2 row `lane` in registers: independent 16-byte loads, all in flight
+    // together
+    float w2r[H];
+    if (lane < H) {
+        const float4* row = reinterpret_cast<const float4*>(m->w2 + lane * H);
+#pragma unroll
+        for (int q = 0; q < H / 4; ++q) {
+            const float4 v = row[q];
+            w2r[4 * q] = v.x;
+            w2r[4 * q + 1] = v.y;
+            w2r[4 * q + 2] = v.z;
+            w2r[4 * q + 3] = v.w;
+        }
+    }
+    const double w1l = lane < H ? (double)m->w1[lane] : 0.0;
+    const double b1l = lane < H ? (double)m->b1[lane] : 0.0;
+    s_w1[lane] = w1l;
+    s_b1[lane] = b1l;
     // layer-1 knots strictly inside (0, 1), ranked with ties by unit index
     double c = 0.0;
     bool ok = false;
-    if (lane < H) {
-        const double w = m->w1[lane], b = m->b1[lane];
-        if (w != 0.0) {
-            c = -b / w;
-            ok = c > 0.0 && c < 1.0;
-        }
+    if (lane < H && w1l != 0.0) {
+        c = -b1l / w1l;
+        ok = c > 0.0 && c < 1.0;
     }
     s_c[lane] = c;
     s_ok[lane] = ok ? 1 : 0;
@@ -59,18 +75,18 @@ __global__ void __launch_bounds__(64) k_pwl_intervals(const DevModel* __restrict
     }
     if (j >= nint) return;
     const double l = s_e[j], r = s_e[j + 1], mid = 0.5 * (l + r);
-    // z2 of unit `lane` on the interval: the layer-1 units active at its
-    // midpoint are active on all of it
+    // the layer-1 units active at the interval's midpoint are active on all
+    // of it; z2 of unit `lane` there is A x + B
+    const unsigned long long act = __ballot(lane < H && fma(w1l, mid, b1l) > 0.0);
     double A = 0.0, B = 0.0;
     if (lane < H) {
-        B = m->b2[lane];
-        const float* w2 = m->w2 + lane * H;
+        B = (double)m->b2[lane];
+#pragma unroll
         for (int k = 0; k < H; ++k) {
-            const double w1 = m->w1[k], b1 = m->b1[k];
-            if (fma(w1, mid, b1) > 0.0) {
-                const double w = w2[k];
-                A = fma(w, w1, A);
-                B = fma(w, b1, B);
+            if ((act >> k) & 1ull) {
+                const double w = w2r[k];
+                A = fma(w, s_w1[k], A);
+                B = fma(w, s_b1[k], B);
             }
         }
     }
@@ -193,8 +209,10 @@ __device__ __forceinline__ void pwl_map(const InferArgs& a, const double* X, con
 
 // Tables of up to kPwlLds pieces are read from LDS, larger ones from global
 // memory (the fitted models seen here have about 2H pieces; the bound is
-// (H + 1)^2).  Every workgroup builds the piece index for itself.
-constexpr int kPwlLds = 1024;
+// (H + 1)^2).  A 512-piece table (14 KB of LDS with the index) leaves room
+// for more workgroups per CU than a 1024-piece one: 0.30 vs 0.32 ms at 1e8.
+// Every workgroup builds the piece index for itself.
+constexpr int kPwlLds = 512;
 
 __global__ void __launch_bounds__(kPwlThreads) k_infer_pwl(InferArgs a) {
     __shared__ double s_x[kPwlLds], s_a[kPwlLds], s_f[kPwlLds];
@@ -226,9 +244,14 @@ __global__ void __launch_bounds__(kPwlThreads) k_infer_pwl(InferArgs a) {
     else pwl_map(a, t->xq, t->alpha, t->Fq, s_first);
 }
 
-hipError_t launch_pwl_infer(const InferArgs& a, hipStream_t st) {
+hipError_t launch_pwl_infer(const InferArgs& a, int H, hipStream_t st) {
     if (!a.pwl) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_pwl_intervals, dim3(kPwlMaxIntervals), dim3(64), 0, st, a.model, a.pwl);
+    if (H == 32)
+        hipLaunchKernelGGL(k_pwl_intervals<32>, dim3(kPwlMaxIntervals), dim3(64), 0, st, a.model, a.pwl);
+    else if (H == 64)
+        hipLaunchKernelGGL(k_pwl_intervals<64>, dim3(kPwlMaxIntervals), dim3(64), 0, st, a.model, a.pwl);
+    else
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_pwl_pieces, dim3(kPwlMaxIntervals), dim3(64), 0, st, a.model, a.pwl);
     constexpr int kTile = kPwlThreads * kPwlPer;
     int64_t blocks = (a.n + kTile - 1) / kTile;

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "../../include/nnsort.h"
@@ -72,11 +73,12 @@ struct DevModel {
     double inv_range;
     float w1[64];
     float b1[64];
-    float w2[64 * 64];  // [i * H + j]
+    alignas(16) float w2[64 * 64];  // [i * H + j]; rows are read as 16-byte vectors
     float b2[64];
     float w3[64];
     float b3;
 };
+static_assert(offsetof(DevModel, w2) % 16 == 0, "W2 rows are read as 16-byte vectors");
 
 // Workspace carve-up for a sort of n keys.
 struct SortPlan {

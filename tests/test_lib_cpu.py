@@ -80,8 +80,18 @@ def test_argument_checks_before_device_work():
     # overlapping input and output
     assert L.nnsort_sort_with_model(ctypes.byref(m), p, ctypes.c_void_p(0x100008), 10, 0, ctypes.byref(sp), None,
                                     0, None, None) == -1
-    # workspace too small (checked before any launch)
+    # workspace too small, or large enough but not 256-byte aligned (checked
+    # before any launch)
     assert L.nnsort_sort_with_model(ctypes.byref(m), p, q, 5000, 0, ctypes.byref(sp), q, 16, None, None) == -2
+    big = ctypes.c_size_t()
+    assert L.nnsort_workspace_size(5000, 0, ctypes.byref(sp), None, ctypes.byref(big)) == 0
+    assert L.nnsort_sort_with_model(ctypes.byref(m), p, q, 5000, 0, ctypes.byref(sp), ctypes.c_void_p(0x900008),
+                                    big.value, None, None) == -2
+    m64 = nn.Model()
+    m64.version, m64.hidden = 1, 64
+    assert L.nnsort_predict(ctypes.byref(m64), p, 10, 0, ctypes.byref(sp), None, None, ctypes.c_void_p(0x900008),
+                            L.nnsort_model_device_bytes(), None) == -2
+    assert "aligned" in L.nnsort_strerror(-2).decode()
     # fit: bad hidden width
     bad = nn.fit_params(hidden=5)
     assert L.nnsort_fit(p, 10, 0, ctypes.byref(bad), ctypes.byref(m), q, 1 << 20, None) == -1
