@@ -69,7 +69,8 @@ hipError_t launch_sample(const void* d_in, int64_t n, bool is_f64, uint64_t seed
 hipError_t launch_make_xy(const uint64_t* d_sorted, int64_t k, bool is_f64, double lo, double inv, double* d_x,
                           float* d_y, hipStream_t st);
 hipError_t launch_init(float* d_theta, int H, int init, uint64_t seed, const double* d_x, int64_t k,
-                       int64_t* d_knots, hipStream_t st);
+                       int64_t* d_knots, void* d_knotws, hipStream_t st);
+size_t knot_ws_bytes();
 hipError_t launch_batch(const double* d_x, const float* d_y, int64_t k, uint64_t seed, int64_t step, int64_t B,
                         double* d_bx, float* d_by, hipStream_t st);
 size_t mlp_backward_ws_floats(int H, int64_t B);
@@ -465,7 +466,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
 struct FitPlan {
     int64_t k, B;
     int H;
-    size_t off_init, off_Fs, off_dis, off_best, off_knots, off_sample, off_count, off_x, off_y, off_bx, off_by, off_F, off_gF, off_saved, off_bws, off_theta,
+    size_t off_init, off_Fs, off_dis, off_best, off_knots, off_knotws, off_sample, off_count, off_x, off_y, off_bx, off_by, off_F, off_gF, off_saved, off_bws, off_theta,
         off_grad, off_m1, off_m2, off_loss, off_lpart, off_radix, total;
 };
 
@@ -503,6 +504,7 @@ FitPlan plan_fit(int64_t n, const nnsort_fit_params* fp) {
     p.off_loss = take(64);
     p.off_lpart = take(loss_ws_floats() * 4);
     p.off_knots = take((NNSORT_MAX_HIDDEN + 1) * 8);
+    p.off_knotws = take(knot_ws_bytes());
     p.off_best = take((size_t)(P + 64) * 4);
     p.off_init = take((size_t)P * 4);
     p.off_Fs = take((size_t)p.k * 4);
@@ -585,7 +587,7 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
     double lo = value_of(ends[0]), hi = value_of(ends[1]);
     double inv = hi > lo ? 1.0 / (hi - lo) : 0.0;
     NNS_HIP(launch_make_xy(sample, (int64_t)k2, is_f64, lo, inv, x, y, st));
-    NNS_HIP(launch_init(theta, H, fp->init, fp->seed, x, (int64_t)k2, knots, st));
+    NNS_HIP(launch_init(theta, H, fp->init, fp->seed, x, (int64_t)k2, knots, ws + P.off_knotws, st));
     NNS_HIP(hipMemsetAsync(m1, 0, (size_t)Pn * 4, st));
     NNS_HIP(hipMemsetAsync(m2, 0, (size_t)Pn * 4, st));
     NNS_HIP(hipMemcpyAsync(best, theta, (size_t)Pn * 4, hipMemcpyDeviceToDevice, st));

@@ -84,37 +84,38 @@ __global__ void __launch_bounds__(256) k_make_xy(const uint64_t* __restrict__ so
 // the chord between its ends, at the farthest point, until H pieces.  Ties:
 // larger deviation first, then the smaller start / smaller point index.  A
 // piece with < 3 points, zero width, or no point more than 1/k off its chord
-// is final.  One workgroup; every piece scan is a block-wide arg-max.
-constexpr int kKnotThreads = 1024;
+// is final.
+// Each split rescans only the two new pieces.  A scan is spread over
+// kKnotBlocks workgroups per piece, each keeping its first largest deviation
+// (the reduction prefers the larger deviation, then the smaller index, so
+// the result is the first maximum whatever the split into blocks); one small
+// workgroup then applies the split and picks the next piece.  The host
+// launches the scan/update pair H times; once no piece can be split, both
+// return at once.
+constexpr int kKnotBlocks = 256;
+constexpr int kKnotThreads = 256;
+
+struct KnotWork {
+    int32_t np, best, done, pad;
+    int64_t ra[2], rb[2];  // the two pieces the next scan covers
+    int64_t pa[NNSORT_MAX_HIDDEN], pb[NNSORT_MAX_HIDDEN], pj[NNSORT_MAX_HIDDEN];
+    double pd[NNSORT_MAX_HIDDEN];
+    double part_d[2][kKnotBlocks];
+    int64_t part_j[2][kKnotBlocks];
+};
+
+size_t knot_ws_bytes() { return sizeof(KnotWork); }
 
 __device__ __forceinline__ double rank_of(int64_t j, int64_t k) { return ((double)j + 0.5) / (double)k; }
 
-// Block-wide: (max deviation, first index) over points a+1 .. b-1 of piece (a, b).
-__device__ void piece_dev(const double* __restrict__ x, int64_t k, int64_t a, int64_t b, double* s_d,
-                          int64_t* s_j, double& out_d, int64_t& out_j) {
-    double best = -1.0;
-    int64_t bj = -1;
-    const double xa = x[a], xb = x[b];
-    if (b - a >= 2 && xb != xa) {
-        const double ya = rank_of(a, k), yb = rank_of(b, k);
-        for (int64_t j = a + 1 + threadIdx.x; j < b; j += kKnotThreads) {
-            double lin = ya + ((yb - ya) * (x[j] - xa)) / (xb - xa);
-            double d = fabs(rank_of(j, k) - lin);
-            if (d > best) {
-                best = d;
-                bj = j;
-            }
-        }
-    }
-    s_d[threadIdx.x] = best;
-    s_j[threadIdx.x] = bj;
-    __syncthreads();
+// (d, j) pairs: larger deviation wins, then the smaller valid index.
+__device__ __forceinline__ void arg_max_reduce(double* s_d, int64_t* s_j) {
     for (int off = kKnotThreads / 2; off > 0; off >>= 1) {
         if (threadIdx.x < (unsigned)off) {
-            double d2 = s_d[threadIdx.x + off];
-            int64_t j2 = s_j[threadIdx.x + off];
-            double d1 = s_d[threadIdx.x];
-            int64_t j1 = s_j[threadIdx.x];
+            const double d2 = s_d[threadIdx.x + off];
+            const int64_t j2 = s_j[threadIdx.x + off];
+            const double d1 = s_d[threadIdx.x];
+            const int64_t j1 = s_j[threadIdx.x];
             if (d2 > d1 || (d2 == d1 && j2 >= 0 && (j1 < 0 || j2 < j1))) {
                 s_d[threadIdx.x] = d2;
                 s_j[threadIdx.x] = j2;
@@ -122,79 +123,134 @@ __device__ void piece_dev(const double* __restrict__ x, int64_t k, int64_t a, in
         }
         __syncthreads();
     }
-    out_d = s_d[0];
-    out_j = s_j[0];
-    if (!(out_d > 1.0 / (double)k)) {  // within one rank step of linear: final
-        out_d = 0.0;
-        out_j = -1;
-    }
-    __syncthreads();
 }
 
-__global__ void __launch_bounds__(kKnotThreads) k_greedy_knots(const double* __restrict__ x, int64_t k, int H,
-                                                               int64_t* knots) {
+__global__ void k_knot_start(int64_t k, KnotWork* w) {
+    if (threadIdx.x != 0) return;
+    w->np = 0;
+    w->best = -1;
+    w->done = 0;
+    w->ra[0] = 0;
+    w->rb[0] = k - 1;
+    w->ra[1] = 0;  // no second piece in the first scan
+    w->rb[1] = 0;
+}
+
+// Block blockIdx.x's share of the points a+1 .. b-1 of piece r = blockIdx.y.
+__global__ void __launch_bounds__(kKnotThreads) k_knot_scan(const double* __restrict__ x, int64_t k, KnotWork* w) {
     __shared__ double s_d[kKnotThreads];
     __shared__ int64_t s_j[kKnotThreads];
-    __shared__ int64_t pa[64], pb[64], pj[64];
-    __shared__ double pd[64];
-    __shared__ int np_, best_;
-    double d;
-    int64_t j;
-    piece_dev(x, k, 0, k - 1, s_d, s_j, d, j);
+    if (w->done) return;
+    const int r = blockIdx.y;
+    const int64_t a = w->ra[r], b = w->rb[r];
+    double best = -1.0;
+    int64_t bj = -1;
+    if (b - a >= 2) {
+        const double xa = x[a], xb = x[b];
+        if (xb != xa) {
+            const double ya = rank_of(a, k), yb = rank_of(b, k);
+            const int64_t stride = (int64_t)gridDim.x * kKnotThreads;
+            for (int64_t j = a + 1 + (int64_t)blockIdx.x * kKnotThreads + threadIdx.x; j < b; j += stride) {
+                const double lin = ya + ((yb - ya) * (x[j] - xa)) / (xb - xa);
+                const double d = fabs(rank_of(j, k) - lin);
+                if (d > best) {
+                    best = d;
+                    bj = j;
+                }
+            }
+        }
+    }
+    s_d[threadIdx.x] = best;
+    s_j[threadIdx.x] = bj;
+    __syncthreads();
+    arg_max_reduce(s_d, s_j);
     if (threadIdx.x == 0) {
-        pa[0] = 0;
-        pb[0] = k - 1;
-        pd[0] = d;
-        pj[0] = j;
-        np_ = 1;
+        w->part_d[r][blockIdx.x] = s_d[0];
+        w->part_j[r][blockIdx.x] = s_j[0];
+    }
+}
+
+// Apply the scan's result (the first piece, or the split of the chosen one)
+// and choose the next piece to split.
+__global__ void __launch_bounds__(kKnotBlocks) k_knot_update(int64_t k, int H, KnotWork* w) {
+    static_assert(kKnotBlocks == kKnotThreads, "one thread per scan block");
+    __shared__ double s_d[kKnotThreads];
+    __shared__ int64_t s_j[kKnotThreads];
+    __shared__ double r_d[2];
+    __shared__ int64_t r_j[2];
+    if (w->done) return;
+    for (int r = 0; r < 2; ++r) {
+        s_d[threadIdx.x] = w->part_d[r][threadIdx.x];
+        s_j[threadIdx.x] = w->part_j[r][threadIdx.x];
+        __syncthreads();
+        arg_max_reduce(s_d, s_j);
+        if (threadIdx.x == 0) {
+            double d = s_d[0];
+            int64_t j = s_j[0];
+            if (!(d > 1.0 / (double)k)) {  // within one rank step of linear: final
+                d = 0.0;
+                j = -1;
+            }
+            r_d[r] = d;
+            r_j[r] = j;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    int np = w->np;
+    if (np == 0) {
+        w->pa[0] = 0;
+        w->pb[0] = k - 1;
+        w->pd[0] = r_d[0];
+        w->pj[0] = r_j[0];
+        np = 1;
+    } else {
+        const int bst = w->best;
+        const int64_t b = w->pb[bst], sj = w->pj[bst];
+        w->pb[bst] = sj;
+        w->pd[bst] = r_d[0];
+        w->pj[bst] = r_j[0];
+        w->pa[np] = sj;
+        w->pb[np] = b;
+        w->pd[np] = r_d[1];
+        w->pj[np] = r_j[1];
+        ++np;
+    }
+    w->np = np;
+    int best = -1;
+    if (np < H) {
+        for (int i = 0; i < np; ++i) {
+            if (w->pj[i] < 0 || !(w->pd[i] > 0.0)) continue;
+            if (best < 0 || w->pd[i] > w->pd[best] || (w->pd[i] == w->pd[best] && w->pa[i] < w->pa[best])) best = i;
+        }
+    }
+    w->best = best;
+    if (best < 0) {
+        w->done = 1;
+    } else {
+        w->ra[0] = w->pa[best];
+        w->rb[0] = w->pj[best];
+        w->ra[1] = w->pj[best];
+        w->rb[1] = w->pb[best];
+    }
+}
+
+// Starts in ascending order (they are distinct: each piece begins where its
+// left neighbour ends), then the last sample index.  One thread per piece
+// (128 threads cover the H + 1 <= 65 outputs).
+__global__ void __launch_bounds__(128) k_knot_finish(int64_t k, int H, const KnotWork* __restrict__ w,
+                                                     int64_t* knots) {
+    __shared__ int64_t s_st[NNSORT_MAX_HIDDEN];
+    const int n = w->np;
+    const int t = threadIdx.x;
+    if (t < n) {
+        const int64_t v = w->pa[t];
+        int r = 0;
+        for (int i = 0; i < n; ++i) r += w->pa[i] < v ? 1 : 0;
+        s_st[r] = v;
     }
     __syncthreads();
-    while (np_ < H) {
-        if (threadIdx.x == 0) {
-            int best = -1;
-            for (int i = 0; i < np_; ++i) {
-                if (pj[i] < 0 || !(pd[i] > 0.0)) continue;
-                if (best < 0 || pd[i] > pd[best] || (pd[i] == pd[best] && pa[i] < pa[best])) best = i;
-            }
-            best_ = best;
-        }
-        __syncthreads();
-        const int best = best_;
-        if (best < 0) break;
-        const int64_t a = pa[best], b = pb[best], sj = pj[best];
-        double d1, d2;
-        int64_t j1, j2;
-        piece_dev(x, k, a, sj, s_d, s_j, d1, j1);
-        piece_dev(x, k, sj, b, s_d, s_j, d2, j2);
-        if (threadIdx.x == 0) {
-            pb[best] = sj;
-            pd[best] = d1;
-            pj[best] = j1;
-            int n = np_;
-            pa[n] = sj;
-            pb[n] = b;
-            pd[n] = d2;
-            pj[n] = j2;
-            np_ = n + 1;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        // starts in ascending order, then the last sample index
-        int n = np_;
-        int64_t st[64];
-        for (int i = 0; i < n; ++i) st[i] = pa[i];
-        for (int i = 1; i < n; ++i) {
-            int64_t v = st[i];
-            int q = i - 1;
-            while (q >= 0 && st[q] > v) {
-                st[q + 1] = st[q];
-                --q;
-            }
-            st[q + 1] = v;
-        }
-        for (int i = 0; i <= H; ++i) knots[i] = i < n ? st[i] : k - 1;
-    }
+    if (t <= H) knots[t] = t < n ? s_st[t] : k - 1;
 }
 
 __global__ void k_quantile_knots(int64_t k, int H, int64_t* knots) {
@@ -284,17 +340,28 @@ __global__ void __launch_bounds__(256) k_fwd(const float* __restrict__ th, const
     // saved activations unit-major, saved[u * B + b] (h1 then h2): the
     // threads of a wave write consecutive addresses
     float* sh1 = saved ? saved + b : nullptr;
-    for (int i = 0; i < H; ++i) {
-        float z = b2[i];
+    // four outputs at a time: their FMA chains are independent, which keeps
+    // the ALU busy at one wave per SIMD; each z_i still sums over j in order
+    static_assert(H % 4 == 0, "outputs in groups of four");
+    for (int i0 = 0; i0 < H; i0 += 4) {
+        float z[4];
 #pragma unroll
-        for (int j = 0; j < H; ++j) z = __builtin_fmaf(W2[i * H + j], h1[j], z);
-        float h2 = z > 0.0f ? z : 0.0f;
-        if (sh1) sh1[(int64_t)(H + i) * B] = h2;
-        float pr = w3[i] * h2;
-        float r = __builtin_fmaf(w3[i], h2, -pr);
-        float q;
-        p = two_sum_f(p, pr, q);
-        s = s + (q + r);
+        for (int q = 0; q < 4; ++q) z[q] = b2[i0 + q];
+#pragma unroll
+        for (int j = 0; j < H; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) z[q] = __builtin_fmaf(W2[(i0 + q) * H + j], h1[j], z[q]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = i0 + q;
+            float h2 = z[q] > 0.0f ? z[q] : 0.0f;
+            if (sh1) sh1[(int64_t)(H + i) * B] = h2;
+            float pr = w3[i] * h2;
+            float r = __builtin_fmaf(w3[i], h2, -pr);
+            float e;
+            p = two_sum_f(p, pr, e);
+            s = s + (e + r);
+        }
     }
     if (sh1) {
 #pragma unroll
@@ -337,10 +404,14 @@ __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ F, const
     if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
 }
 
-__global__ void k_loss_final(const float* __restrict__ partial, int nb, int64_t B, float* loss_out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+__global__ void __launch_bounds__(kLossBlocks) k_loss_final(const float* __restrict__ partial, int nb, int64_t B,
+                                                          float* loss_out) {
+    __shared__ float s_p[kLossBlocks];
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) s_p[i] = partial[i];  // nb <= kLossBlocks
+    __syncthreads();
+    if (threadIdx.x == 0) {
         float s = 0.0f;
-        for (int i = 0; i < nb; ++i) s += partial[i];
+        for (int i = 0; i < nb; ++i) s += s_p[i];
         loss_out[0] = s / (float)B;
     }
 }
@@ -363,6 +434,8 @@ __global__ void __launch_bounds__(256) k_bwd_sample(const float* __restrict__ th
 #pragma unroll
     for (int i = 0; i < H; ++i) dz2[i] = h[(int64_t)(H + i) * B] > 0.0f ? g * w3[i] : 0.0f;
     float* o = d + b;
+    // (four interleaved j chains, or W2 rows into H accumulators with i fully
+    // unrolled, measured slower: 50 and 57 us against 45 at a 65,536 batch)
     for (int j = 0; j < H; ++j) {
         float acc = 0.0f;
 #pragma unroll
@@ -380,7 +453,7 @@ __global__ void __launch_bounds__(256) k_bwd_sample(const float* __restrict__ th
 // registers (T = 4 at H = 64), fed from samples staged in LDS 32 at a time,
 // two 16-byte LDS reads per sample for T^2 FMAs.  Every sum runs over the
 // samples in order, so the result does not depend on scheduling.
-constexpr int kRedChunk = 256;
+constexpr int kRedChunk = 64;  // 1024 workgroups at a 65,536 batch (256-sample chunks: 1 per CU)
 constexpr int kRedSub = 32;
 template <int H>
 __global__ void __launch_bounds__(256) k_bwd_reduce(const double* __restrict__ x, int64_t B,
@@ -481,8 +554,10 @@ __global__ void __launch_bounds__(256) k_sum_rows(const float* __restrict__ part
     const int c = threadIdx.x & 31, grp = threadIdx.x >> 5;
     const int p = blockIdx.x * 32 + c;
     float acc = 0.0f;
-    if (p < P)
+    if (p < P) {
+#pragma unroll 8
         for (int r = grp; r < rows; r += 8) acc += part[(int64_t)r * P + p];
+    }
     s[grp][c] = acc;
     __syncthreads();
     if (grp == 0 && p < P) {
@@ -585,10 +660,16 @@ hipError_t launch_make_xy(const uint64_t* d_sorted, int64_t k, bool is_f64, doub
 }
 
 hipError_t launch_init(float* d_theta, int H, int init, uint64_t seed, const double* d_x, int64_t k,
-                       int64_t* d_knots, hipStream_t st) {
-    if (init == 1)
-        hipLaunchKernelGGL(k_greedy_knots, dim3(1), dim3(kKnotThreads), 0, st, d_x, k, H, d_knots);
-    else if (init == 2)
+                       int64_t* d_knots, void* d_knotws, hipStream_t st) {
+    if (init == 1) {
+        KnotWork* w = (KnotWork*)d_knotws;
+        hipLaunchKernelGGL(k_knot_start, dim3(1), dim3(64), 0, st, k, w);
+        for (int it = 0; it < H; ++it) {  // the first piece, then at most H - 1 splits
+            hipLaunchKernelGGL(k_knot_scan, dim3(kKnotBlocks, 2), dim3(kKnotThreads), 0, st, d_x, k, w);
+            hipLaunchKernelGGL(k_knot_update, dim3(1), dim3(kKnotBlocks), 0, st, k, H, w);
+        }
+        hipLaunchKernelGGL(k_knot_finish, dim3(1), dim3(128), 0, st, k, H, (const KnotWork*)w, d_knots);
+    } else if (init == 2)
         hipLaunchKernelGGL(k_quantile_knots, dim3(1), dim3(128), 0, st, k, H, d_knots);
     hipLaunchKernelGGL(k_init, dim3(nblk(H * H + 4 * H + 1, 256)), dim3(256), 0, st, d_theta, H, init, seed,
                        d_x, k, (const int64_t*)d_knots);
@@ -652,7 +733,7 @@ size_t loss_ws_floats() { return kLossBlocks; }
 hipError_t launch_loss_grad(const float* d_F, const float* d_y, int64_t B, int loss, float delta, float* d_gF,
                             float* d_loss, float* d_partial, hipStream_t st) {
     hipLaunchKernelGGL(k_loss, dim3(kLossBlocks), dim3(256), 0, st, d_F, d_y, B, loss, delta, d_gF, d_partial);
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, d_partial, kLossBlocks, B, d_loss);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kLossBlocks), 0, st, d_partial, kLossBlocks, B, d_loss);
     return hipGetLastError();
 }
 

@@ -288,6 +288,19 @@ def test_fit_init_matches_oracle(init, H):
     assert np.array_equal(got["theta"], ref["theta"])
 
 
+@pytest.mark.parametrize("name", ["zipf_u64", "gauss_mix"])
+def test_fit_init_greedy_knots_large_sample(name):
+    """Greedy knots over a 10^5-point sample (the scan spread over many
+    workgroups; zipf has long runs of equal keys, hence zero-width pieces):
+    identical weights at step 0."""
+    x = W.make(name, 1_000_000)
+    fp = nn.fit_params(hidden=64, sample_frac=0.1, steps=0, init=1, seed=5)
+    got = nn.model_to_dict(nn.nnsort_fit(to_dev(x), fp))
+    ref = O.fit(x, H=64, sample_frac=0.1, steps=0, init=1, seed=5)
+    assert got["lo"] == ref["lo"] and got["inv_range"] == ref["inv_range"]
+    assert np.array_equal(got["theta"], ref["theta"])
+
+
 def test_fit_loss_tracks_oracle():
     x = W.uniform(100_000, seed=8)
     fp = nn.fit_params(hidden=16, sample_frac=0.2, batch=2048, steps=30, init=0, lr=1e-2, seed=3)
