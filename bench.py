@@ -234,6 +234,17 @@ def main():
         oracle.nnsort(xs, mdict, form=formc)
         cpu_s = time.perf_counter() - t0
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        # a conventional host sort of the same sample (numpy's introsort, one
+        # thread), with the host's CPU model
+        t0 = time.perf_counter()
+        np.sort(xs, kind="quicksort")
+        context["host_sort_gkeys"] = round(m / (time.perf_counter() - t0) / 1e9, 5)
+        context["host_sort"] = "numpy quicksort (introsort), 1 thread, same sample"
+        try:
+            context["host_cpu"] = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo")
+                                       if l.startswith("model name"))
+        except (OSError, StopIteration):
+            context["host_cpu"] = None
         cpu = {"value": round(m / cpu_s / 1e9, 6), "unit": "Gkeys/s", "cores": cores, "kind": "oracle",
                "sample": f"first {m} keys of the same workload, same model, FP64 bf16-W2 evaluator; "
                          f"{cpu_s:.1f} s"}
