@@ -8,8 +8,8 @@
 // same state a small range reaches in LDS; the boundary check that follows
 // treats both alike.
 //
-//  1. k_seg_sort_chunk: every chunk sorted in LDS (bitonic network, one
-//     workgroup per chunk).
+//  1. k_seg_sort_chunk: every chunk sorted in LDS (8 keys per thread by a
+//     sorting network, then 9 levels of merge path; one workgroup per chunk).
 //  2. k_seg_merge, once per round r = 0, 1, ...: in every segment longer
 //     than L = kBigChunk 2^r, the sorted runs of length L are merged in pairs
 //     (merge path: each workgroup writes one chunk of output; a wave finds
@@ -35,40 +35,6 @@ __device__ __forceinline__ int64_t seg_of_chunk(const int64_t* __restrict__ chun
         else hi = mid - 1;
     }
     return lo;
-}
-
-__global__ void __launch_bounds__(kSortThreads) k_seg_sort_chunk(const int64_t* __restrict__ chunk_pref,
-                                                                 const int64_t* __restrict__ gpref, int64_t nseg,
-                                                                 uint64_t* G) {
-    __shared__ uint64_t s[kBigChunk];
-    const int64_t chunk = blockIdx.x;
-    if (chunk >= chunk_pref[nseg]) return;  // the grid is an upper bound
-    const int64_t id = seg_of_chunk(chunk_pref, nseg, chunk);
-    const int64_t g0 = gpref[id], len = gpref[id + 1] - g0;
-    const int64_t c0 = (chunk - chunk_pref[id]) * kBigChunk;
-    const int cnt = (int)(len - c0 < kBigChunk ? len - c0 : kBigChunk);
-    uint64_t* p = G + g0 + c0;
-    const int tid = threadIdx.x;
-    // padding with the largest order key: a real key of that value is the
-    // same bit pattern, so the first cnt outputs are right either way
-    for (int i = tid; i < kBigChunk; i += kSortThreads) s[i] = i < cnt ? p[i] : ~0ull;
-    __syncthreads();
-    for (int k = 2; k <= kBigChunk; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int q = tid; q < kBigChunk / 2; q += kSortThreads) {
-                const int i = ((q & ~(j - 1)) << 1) | (q & (j - 1));  // lower index of pair q
-                const int l = i + j;
-                const uint64_t a = s[i], b = s[l];
-                const bool up = (i & k) == 0;
-                if ((a > b) == up) {
-                    s[i] = b;
-                    s[l] = a;
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int i = tid; i < cnt; i += kSortThreads) p[i] = s[i];
 }
 
 // Merge path, whole wave: the number of A's elements among the first d of
@@ -106,6 +72,76 @@ __device__ __forceinline__ int split_lds(const uint64_t* A, int na, const uint64
         else hi = mid;
     }
     return lo;
+}
+
+// Block merge sort of one chunk.  Each thread sorts 8 keys in registers
+// with a 19-comparator network (Batcher's odd-even merge sort for 8 inputs);
+// then runs of 8, 16, ..., 2048 keys are merged in pairs in LDS: at every
+// level a thread finds where its 8 outputs start in its pair of runs (merge
+// path, ties from the left run) and merges them in registers.  Global memory
+// is read and written in wave-contiguous order through LDS.
+constexpr int kSortPer = kBigChunk / kSortThreads;  // 8
+static_assert(kSortPer == 8, "the register network sorts 8 keys");
+
+__device__ __forceinline__ void cswap(uint64_t& a, uint64_t& b) {
+    const uint64_t lo = a < b ? a : b;
+    b = a < b ? b : a;
+    a = lo;
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_seg_sort_chunk(const int64_t* __restrict__ chunk_pref,
+                                                                 const int64_t* __restrict__ gpref, int64_t nseg,
+                                                                 uint64_t* G) {
+    __shared__ uint64_t s[kBigChunk];
+    const int64_t chunk = blockIdx.x;
+    if (chunk >= chunk_pref[nseg]) return;  // the grid is an upper bound
+    const int64_t id = seg_of_chunk(chunk_pref, nseg, chunk);
+    const int64_t g0 = gpref[id], len = gpref[id + 1] - g0;
+    const int64_t c0 = (chunk - chunk_pref[id]) * kBigChunk;
+    const int cnt = (int)(len - c0 < kBigChunk ? len - c0 : kBigChunk);
+    uint64_t* p = G + g0 + c0;
+    const int tid = threadIdx.x;
+    // padding with the largest order key: a real key of that value is the
+    // same bit pattern, so the first cnt outputs are right either way
+    for (int i = tid; i < kBigChunk; i += kSortThreads) s[i] = i < cnt ? p[i] : ~0ull;
+    __syncthreads();
+    const int base = tid * kSortPer;
+    uint64_t v[kSortPer];
+#pragma unroll
+    for (int r = 0; r < kSortPer; ++r) v[r] = s[base + r];
+    cswap(v[0], v[2]); cswap(v[1], v[3]); cswap(v[4], v[6]); cswap(v[5], v[7]);
+    cswap(v[0], v[4]); cswap(v[1], v[5]); cswap(v[2], v[6]); cswap(v[3], v[7]);
+    cswap(v[0], v[1]); cswap(v[2], v[3]); cswap(v[4], v[5]); cswap(v[6], v[7]);
+    cswap(v[2], v[4]); cswap(v[3], v[5]);
+    cswap(v[1], v[4]); cswap(v[3], v[6]);
+    cswap(v[1], v[2]); cswap(v[3], v[4]); cswap(v[5], v[6]);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortPer; ++r) s[base + r] = v[r];
+    __syncthreads();
+    for (int run = kSortPer; run < kBigChunk; run <<= 1) {
+        const int pb = base & ~(2 * run - 1);  // this thread's pair of runs
+        const uint64_t* A = s + pb;
+        const uint64_t* Bq = A + run;
+        const int d = base - pb;
+        int ia = split_lds(A, run, Bq, run, d);
+        int ib = d - ia;
+#pragma unroll
+        for (int r = 0; r < kSortPer; ++r) {
+            // both heads read in bounds (an exhausted run's last key, unused)
+            const uint64_t a = A[ia < run ? ia : run - 1];
+            const uint64_t b = Bq[ib < run ? ib : run - 1];
+            const bool takeA = ib >= run || (ia < run && a <= b);
+            v[r] = takeA ? a : b;
+            ia += takeA ? 1 : 0;
+            ib += takeA ? 0 : 1;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kSortPer; ++r) s[base + r] = v[r];
+        __syncthreads();
+    }
+    for (int i = tid; i < cnt; i += kSortThreads) p[i] = s[i];
 }
 
 __global__ void __launch_bounds__(kMergeThreads) k_seg_merge(const int64_t* __restrict__ chunk_pref,
