@@ -56,18 +56,34 @@ def src_sha(paths):
     return h.hexdigest()
 
 
-def load_traffic(kernel: str, sha: str):
-    """Measured HBM bytes per launch of `kernel` from the committed counter
-    summary, or None when absent or taken on a different kernel source."""
+def load_counters(kernel: str, sha: str) -> dict:
+    """The committed counter record of `kernel` (HBM bytes and VALU
+    instructions per launch), or {} when absent or taken on a different
+    kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
-        return None
+        return {}
     e = d.get(kernel)
     if not e or e.get("source_sha256") != sha:
+        return {}
+    return e
+
+
+# VALU issue: a wave64 vector instruction occupies its SIMD for 4 cycles
+# (16 lanes per cycle, FP32 and FP64 alike); 256 CUs x 4 SIMDs at 2.4 GHz.
+SIMDS, CLOCK_HZ, CYCLES_PER_VALU = 1024, 2.4e9, 4
+
+
+def valu_issue(counters: dict, launch_ms: float):
+    """Time the kernel's counted VALU instructions need at full issue rate,
+    and its share of the measured launch time."""
+    insts = counters.get("valu_insts_per_launch")
+    if not insts:
         return None
-    return e.get("bytes_per_launch")
+    ms = insts * CYCLES_PER_VALU / (SIMDS * CLOCK_HZ) * 1e3
+    return {"valu_insts": insts, "issue_ms": round(ms, 4), "frac": round(ms / launch_ms, 4)}
 
 
 def main():
@@ -144,23 +160,28 @@ def main():
         # HBM-bound: 8 bytes read and a 4-byte slot written per key; the map
         # time includes the two launches that compile the pieces
         kname = "k_infer_pwl"
-        traffic = load_traffic(kname, src_sha(["paper_1907_08817_amd/csrc/infer_pwl.hip",
-                                               "paper_1907_08817_amd/csrc/infer_common.h"]))
+        ctr = load_counters(kname, src_sha(["paper_1907_08817_amd/csrc/infer_pwl.hip",
+                                            "paper_1907_08817_amd/csrc/infer_common.h"]))
         achieved_gbs = 12 * n / (k1_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 5), "traffic": traffic,
-                    "bytes_per_key": 12, "keys_per_launch": n, "avg_launch_ms": round(k1_ms, 4)}
+                    "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 5),
+                    "traffic": ctr.get("bytes_per_launch"), "bytes_per_key": 12, "keys_per_launch": n,
+                    "avg_launch_ms": round(k1_ms, 4), "valu_issue": valu_issue(ctr, k1_ms)}
     else:
         kname = f"k_infer_bf16<{64 if H > 32 else 32},{args.bf16_terms}>" if form == "bf16" else \
             f"k_infer_fp32<{64 if H > 32 else 32}>"
         ksha = src_sha(["paper_1907_08817_amd/csrc/infer_bf16.hip" if form == "bf16" else
                         "paper_1907_08817_amd/csrc/infer.hip", "paper_1907_08817_amd/csrc/infer_common.h"])
-        traffic = load_traffic(kname, ksha)
+        ctr = load_counters(kname, ksha)
         peak = BF16_PEAK_TFLOPS if form == "bf16" else FP32_VALU_PEAK_TFLOPS
+        # the matrix-core roofline the metric names, and beside it the vector
+        # issue bound that actually limits this kernel (from the committed
+        # instruction count and the live launch time)
         roofline = {"bound": "mfma" if form == "bf16" else "alu", "kernel": kname,
                     "achieved": round(achieved_tflops, 3), "peak": peak, "unit": "TFLOP/s",
-                    "frac": round(achieved_tflops / peak, 5), "traffic": traffic,
-                    "flop_per_key": flop_per_key, "keys_per_launch": n, "avg_launch_ms": round(k1_ms, 4)}
+                    "frac": round(achieved_tflops / peak, 5), "traffic": ctr.get("bytes_per_launch"),
+                    "flop_per_key": flop_per_key, "keys_per_launch": n, "avg_launch_ms": round(k1_ms, 4),
+                    "valu_issue": valu_issue(ctr, k1_ms)}
 
     # whole-sort algorithmic HBM bytes: keys read, placed keys written/read,
     # conflict (key, slot) pairs written/read, residue radix passes, output
