@@ -54,11 +54,11 @@ hipError_t launch_big_gather(const int32_t* d_bigbucket, int64_t big_count, int6
                              hipStream_t st);
 hipError_t launch_big_place(const int32_t* d_bigbucket, int64_t big_count, int64_t nchunks,
                             const int64_t* d_chunk_pref, const int64_t* d_gpref, const int64_t* d_start,
-                            const uint64_t* d_Gs, const uint64_t* d_alt, bool seg_mode, int64_t u_neg,
+                            const uint64_t* d_Gs, const uint64_t* d_alt, bool seg_mode, int64_t run0, int64_t u_neg,
                             uint64_t* d_out, bool is_f64, hipStream_t st);
-int seg_rounds(int64_t max_len);
+int seg_rounds(int64_t max_len, int64_t run0);
 hipError_t seg_sort(const int64_t* d_chunk_pref, const int64_t* d_gpref, int64_t nseg, int64_t nchunks,
-                    int rounds, uint64_t* d_G, uint64_t* d_tmp, hipStream_t st);
+                    int rounds, int64_t run0, uint64_t* d_G, uint64_t* d_tmp, hipStream_t st);
 hipError_t launch_count_neg(const uint64_t* d_K, const int64_t* d_start, uint32_t NB, int64_t n, uint64_t* d_count,
                             hipStream_t st);
 hipError_t launch_copy_u64(const uint64_t* d_in, uint64_t* d_out, int64_t n, hipStream_t st);
@@ -158,6 +158,7 @@ namespace nns {
 // Merge rounds of the range-by-range sort of dense ranges beyond which the
 // radix sort of the whole residue is used instead (ranges of up to 1M keys).
 constexpr int kSegMaxRounds = 8;
+constexpr int64_t kWideRunKeys = (int64_t)1 << 22;  // dense keys above which runs start at kSortRun
 
 SortPlan plan_sort(int64_t n, double m) {
     SortPlan p{};
@@ -371,21 +372,24 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     ev.mark(3);
 
     // ---- dense ranges and keys without a slot: conventional sort, placed ----
-    // Dense ranges up to kBigChunk << kSegMaxRounds keys: sorted range by
+    // Dense ranges up to run0 << kSegMaxRounds keys: sorted range by
     // range (chunks in LDS, then merge rounds), the keys without a slot by
     // radix on their own.  Larger ones: one LSD radix sort of all of G, which
     // then moves fewer bytes than the merge rounds.
     if (G_size > 0) {
-        const int rounds = seg_rounds((int64_t)c[kCntBigMax]);
+        // sorted runs of two chunks once the dense keys fill the GPU with
+        // such runs (the longer runs save a merge round), of one otherwise
+        const int64_t run0 = big_keys > kWideRunKeys ? (int64_t)kSortRun : (int64_t)kBigChunk;
+        const int rounds = seg_rounds((int64_t)c[kCntBigMax], run0);
         const bool seg_mode = rounds <= kSegMaxRounds;
         uint64_t* alt = which ? K0 : K1;  // the partition buffer that Ks is not in
         if (seg_mode) {
-            NNS_HIP(seg_sort(chunk_pref, gpref, big_count, nchunks, rounds, G, alt, st));
+            NNS_HIP(seg_sort(chunk_pref, gpref, big_count, nchunks, rounds, run0, G, alt, st));
             if (unm > 0) NNS_HIP(radix_sort(G + big_keys, G + big_keys, unm, 0, 0, radix_ws, P.radix_bytes, st));
         } else {
             NNS_HIP(radix_sort(G, G, G_size, 0, 0, radix_ws, P.radix_bytes, st));
         }
-        NNS_HIP(launch_big_place(bigbucket, big_count, nchunks, chunk_pref, gpref, start, G, alt, seg_mode, u_neg,
+        NNS_HIP(launch_big_place(bigbucket, big_count, nchunks, chunk_pref, gpref, start, G, alt, seg_mode, run0, u_neg,
                                  out, is_f64, st));
         // sorted keys without a slot: those with the order key's top bit clear
         // first (below every mapped key), the rest last

@@ -21,6 +21,9 @@ constexpr uint32_t kBucketSlots = 1u << kLogBucketSlots;
 constexpr uint32_t kBucketCap = 4096;
 // dense ranges are gathered, sorted and placed in chunks of this many keys
 constexpr int kBigChunk = 4096;
+// the chunk sort leaves sorted runs of this many keys (two chunks), which the
+// merge rounds then double
+constexpr int kSortRun = 2 * kBigChunk;
 constexpr int kBucketThreads = 256;
 
 // Partition of keys by slot range: tiles of kPartTile keys in input order,

@@ -131,8 +131,8 @@ __global__ void __launch_bounds__(256) k_big_place(const int32_t* __restrict__ b
                                                    const int64_t* __restrict__ chunk_pref,
                                                    const int64_t* __restrict__ gpref,
                                                    const int64_t* __restrict__ start, const uint64_t* __restrict__ Gs,
-                                                   const uint64_t* __restrict__ alt, int seg_mode, int64_t u_neg,
-                                                   uint64_t* __restrict__ out, int is_f64) {
+                                                   const uint64_t* __restrict__ alt, int seg_mode, int64_t run0,
+                                                   int64_t u_neg, uint64_t* __restrict__ out, int is_f64) {
     const int64_t chunk = blockIdx.x;
     if (chunk >= chunk_pref[big_count]) return;  // the grid is an upper bound
     int64_t lo = 0, hi = big_count - 1;
@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(256) k_big_place(const int32_t* __restrict__ b
     const uint64_t* src;
     if (seg_mode) {
         int rounds = 0;
-        for (int64_t L = kBigChunk; L < len; L <<= 1) ++rounds;
+        for (int64_t L = run0; L < len; L <<= 1) ++rounds;  // run0: the chunk sort's run length
         src = ((rounds & 1) ? alt : Gs) + gpref[id];
     } else {
         src = Gs + u_neg + gpref[id];
@@ -264,11 +264,11 @@ hipError_t launch_big_gather(const int32_t* d_bigbucket, int64_t big_count, int6
 
 hipError_t launch_big_place(const int32_t* d_bigbucket, int64_t big_count, int64_t nchunks,
                             const int64_t* d_chunk_pref, const int64_t* d_gpref, const int64_t* d_start,
-                            const uint64_t* d_Gs, const uint64_t* d_alt, bool seg_mode, int64_t u_neg,
-                            uint64_t* d_out, bool is_f64, hipStream_t st) {
+                            const uint64_t* d_Gs, const uint64_t* d_alt, bool seg_mode, int64_t run0,
+                            int64_t u_neg, uint64_t* d_out, bool is_f64, hipStream_t st) {
     if (nchunks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_big_place, dim3((unsigned)nchunks), dim3(256), 0, st, d_bigbucket, big_count, d_chunk_pref,
-                       d_gpref, d_start, d_Gs, d_alt, seg_mode ? 1 : 0, u_neg, d_out, is_f64 ? 1 : 0);
+                       d_gpref, d_start, d_Gs, d_alt, seg_mode ? 1 : 0, run0, u_neg, d_out, is_f64 ? 1 : 0);
     return hipGetLastError();
 }
 

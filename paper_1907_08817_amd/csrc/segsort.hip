@@ -8,10 +8,11 @@
 // same state a small range reaches in LDS; the boundary check that follows
 // treats both alike.
 //
-//  1. k_seg_sort_chunk: every chunk sorted in LDS (8 keys per thread by a
-//     sorting network, then 9 levels of merge path; one workgroup per chunk).
+//  1. k_seg_sort_chunk: every run of run0 keys (one chunk, or two once the
+//     dense keys are many) sorted in LDS (8 keys per thread by a sorting
+//     network, then levels of merge path; one workgroup per run).
 //  2. k_seg_merge, once per round r = 0, 1, ...: in every segment longer
-//     than L = kBigChunk 2^r, the sorted runs of length L are merged in pairs
+//     than L = run0 2^r, the sorted runs of length L are merged in pairs
 //     (merge path: each workgroup writes one chunk of output; a wave finds
 //     where the chunk starts in the two runs by a 64-way search, then the
 //     chunk's inputs are staged in LDS and every thread merges 16 outputs).
@@ -21,7 +22,6 @@
 
 namespace nns {
 
-constexpr int kSortThreads = 512;
 constexpr int kMergeThreads = 256;
 constexpr int kMergePer = kBigChunk / kMergeThreads;  // outputs per thread
 
@@ -74,14 +74,15 @@ __device__ __forceinline__ int split_lds(const uint64_t* A, int na, const uint64
     return lo;
 }
 
-// Block merge sort of one chunk.  Each thread sorts 8 keys in registers
+// Block merge sort of one run of RUN keys (RUN / kBigChunk chunks, starting at
+// a chunk whose index in its segment is a multiple of that).  Each thread
+// sorts 8 keys in registers
 // with a 19-comparator network (Batcher's odd-even merge sort for 8 inputs);
-// then runs of 8, 16, ..., 2048 keys are merged in pairs in LDS: at every
+// then runs of 8, 16, ..., RUN / 2 keys are merged in pairs in LDS: at every
 // level a thread finds where its 8 outputs start in its pair of runs (merge
 // path, ties from the left run) and merges them in registers.  Global memory
 // is read and written in wave-contiguous order through LDS.
-constexpr int kSortPer = kBigChunk / kSortThreads;  // 8
-static_assert(kSortPer == 8, "the register network sorts 8 keys");
+constexpr int kSortPer = 8;
 
 __device__ __forceinline__ void cswap(uint64_t& a, uint64_t& b) {
     const uint64_t lo = a < b ? a : b;
@@ -89,21 +90,26 @@ __device__ __forceinline__ void cswap(uint64_t& a, uint64_t& b) {
     a = lo;
 }
 
-__global__ void __launch_bounds__(kSortThreads) k_seg_sort_chunk(const int64_t* __restrict__ chunk_pref,
-                                                                 const int64_t* __restrict__ gpref, int64_t nseg,
-                                                                 uint64_t* G) {
-    __shared__ uint64_t s[kBigChunk];
+template <int RUN>
+__global__ void __launch_bounds__(RUN / kSortPer) k_seg_sort_chunk(const int64_t* __restrict__ chunk_pref,
+                                                                  const int64_t* __restrict__ gpref, int64_t nseg,
+                                                                  uint64_t* G) {
+    constexpr int kThreads = RUN / kSortPer;
+    constexpr int kChunksPerRun = RUN / kBigChunk;
+    static_assert(RUN % kBigChunk == 0 && RUN <= 8192, "a run of whole chunks, in at most 64 KB of LDS");
+    __shared__ uint64_t s[RUN];
     const int64_t chunk = blockIdx.x;
     if (chunk >= chunk_pref[nseg]) return;  // the grid is an upper bound
     const int64_t id = seg_of_chunk(chunk_pref, nseg, chunk);
+    if ((chunk - chunk_pref[id]) % kChunksPerRun) return;  // sorted with the chunk before it
     const int64_t g0 = gpref[id], len = gpref[id + 1] - g0;
     const int64_t c0 = (chunk - chunk_pref[id]) * kBigChunk;
-    const int cnt = (int)(len - c0 < kBigChunk ? len - c0 : kBigChunk);
+    const int cnt = (int)(len - c0 < RUN ? len - c0 : RUN);
     uint64_t* p = G + g0 + c0;
     const int tid = threadIdx.x;
     // padding with the largest order key: a real key of that value is the
     // same bit pattern, so the first cnt outputs are right either way
-    for (int i = tid; i < kBigChunk; i += kSortThreads) s[i] = i < cnt ? p[i] : ~0ull;
+    for (int i = tid; i < RUN; i += kThreads) s[i] = i < cnt ? p[i] : ~0ull;
     __syncthreads();
     const int base = tid * kSortPer;
     uint64_t v[kSortPer];
@@ -119,7 +125,7 @@ __global__ void __launch_bounds__(kSortThreads) k_seg_sort_chunk(const int64_t* 
 #pragma unroll
     for (int r = 0; r < kSortPer; ++r) s[base + r] = v[r];
     __syncthreads();
-    for (int run = kSortPer; run < kBigChunk; run <<= 1) {
+    for (int run = kSortPer; run < RUN; run <<= 1) {
         const int pb = base & ~(2 * run - 1);  // this thread's pair of runs
         const uint64_t* A = s + pb;
         const uint64_t* Bq = A + run;
@@ -141,7 +147,7 @@ __global__ void __launch_bounds__(kSortThreads) k_seg_sort_chunk(const int64_t* 
         for (int r = 0; r < kSortPer; ++r) s[base + r] = v[r];
         __syncthreads();
     }
-    for (int i = tid; i < cnt; i += kSortThreads) p[i] = s[i];
+    for (int i = tid; i < cnt; i += kThreads) p[i] = s[i];
 }
 
 __global__ void __launch_bounds__(kMergeThreads) k_seg_merge(const int64_t* __restrict__ chunk_pref,
@@ -197,25 +203,31 @@ __global__ void __launch_bounds__(kMergeThreads) k_seg_merge(const int64_t* __re
     }
 }
 
-int seg_rounds(int64_t max_len) {
+int seg_rounds(int64_t max_len, int64_t run0) {
     int r = 0;
-    for (int64_t L = kBigChunk; L < max_len; L <<= 1) ++r;
+    for (int64_t L = run0; L < max_len; L <<= 1) ++r;
     return r;
 }
 
 // Sorts every segment of G; tmp holds as many keys as G.  A segment of len
-// keys ends in (seg_rounds(len) odd ? tmp : G).
+// keys ends in (seg_rounds(len, run0) odd ? tmp : G).
 hipError_t seg_sort(const int64_t* d_chunk_pref, const int64_t* d_gpref, int64_t nseg, int64_t nchunks,
-                    int rounds, uint64_t* d_G, uint64_t* d_tmp, hipStream_t st) {
+                    int rounds, int64_t run0, uint64_t* d_G, uint64_t* d_tmp, hipStream_t st) {
     if (nseg <= 0 || nchunks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_sort_chunk, dim3((unsigned)nchunks), dim3(kSortThreads), 0, st, d_chunk_pref, d_gpref,
-                       nseg, d_G);
+    if (run0 == kSortRun)
+        hipLaunchKernelGGL(k_seg_sort_chunk<kSortRun>, dim3((unsigned)nchunks), dim3(kSortRun / kSortPer), 0, st,
+                           d_chunk_pref, d_gpref, nseg, d_G);
+    else if (run0 == kBigChunk)
+        hipLaunchKernelGGL(k_seg_sort_chunk<kBigChunk>, dim3((unsigned)nchunks), dim3(kBigChunk / kSortPer), 0, st,
+                           d_chunk_pref, d_gpref, nseg, d_G);
+    else
+        return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     uint64_t* buf[2] = {d_G, d_tmp};
     for (int r = 0; r < rounds; ++r) {
         hipLaunchKernelGGL(k_seg_merge, dim3((unsigned)nchunks), dim3(kMergeThreads), 0, st, d_chunk_pref, d_gpref,
-                           nseg, (int64_t)kBigChunk << r, buf[r & 1], buf[(r + 1) & 1]);
+                           nseg, run0 << r, buf[r & 1], buf[(r + 1) & 1]);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

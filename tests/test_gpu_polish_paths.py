@@ -245,7 +245,8 @@ def slots_for_range_sizes(x, sizes, seed):
     return s
 
 
-@pytest.mark.parametrize("sizes", [[4097, 8192, 8193, 12288, 16385, 65537], [5000] * 7 + [40_000, 100]])
+@pytest.mark.parametrize("sizes", [[4097, 8192, 8193, 12288, 16385, 65537], [5000] * 7 + [40_000, 100],
+                                   [16383, 16384, 24577, 32769, 49152, 131073]])
 def test_dense_ranges_at_run_boundaries(sizes):
     x = W.gauss_mix(400_000, seed=28)
     s = slots_for_range_sizes(x, sizes, seed=len(sizes))
@@ -263,4 +264,35 @@ def test_dense_range_too_long_for_merging():
     s = slots_for_range_sizes(x, [6000, 1_200_000, 9000], seed=3)
     st = sort_slots(x, s)
     assert st["big_buckets"] == 3 and st["big_bucket_keys"] == 1_215_000
+    assert st["fallback"] == 0
+
+
+def test_dense_range_longest_merged():
+    """One range of exactly 4096 * 2^8 keys: 8 merge rounds, the most the
+    range-by-range path takes."""
+    x = W.uniform(1_100_000, seed=30)
+    s = slots_for_range_sizes(x, [1_048_576, 7000], seed=4)
+    st = sort_slots(x, s)
+    assert st["big_buckets"] == 2 and st["big_bucket_keys"] == 1_055_576
+    assert st["fallback"] == 0
+
+
+# More than 4M dense keys: the chunk sort leaves runs of two chunks (8192
+# keys), so the merge rounds start there and reach 8192 * 2^8 keys.
+def test_many_dense_keys_wide_runs():
+    """Ranges of 1.7M, 2^20 + 1 (an odd chunk count) and 1.5M keys."""
+    x = W.uniform(4_400_000, seed=31)
+    s = slots_for_range_sizes(x, [1_700_000, 1_048_577, 1_500_000, 9000], seed=5)
+    st = sort_slots(x, s)
+    assert st["big_buckets"] == 4 and st["big_bucket_keys"] == 4_257_577
+    assert st["fallback"] == 0
+
+
+def test_many_dense_keys_range_too_long_for_wide_runs():
+    """With wide runs a range of 2.2M keys (beyond 8192 * 2^8) sends the
+    residue to one radix pass sequence."""
+    x = W.uniform(4_500_000, seed=32)
+    s = slots_for_range_sizes(x, [2_200_000, 2_100_000, 5000], seed=6)
+    st = sort_slots(x, s)
+    assert st["big_buckets"] == 3 and st["big_bucket_keys"] == 4_305_000
     assert st["fallback"] == 0
