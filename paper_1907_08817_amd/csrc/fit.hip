@@ -417,47 +417,23 @@ __global__ void __launch_bounds__(kLossBlocks) k_loss_final(const float* __restr
 }
 
 // ---- backward ----
-// Per sample: dz2_i = g w3_i [h2_i > 0]; dz1_j = [h1_j > 0] sum_i dz2_i W2_ij.
-// Writes d = (dz1[H], dz2[H]) per sample, unit-major like the saved (h1, h2):
-// d[u * B + b].
-template <int H>
-__global__ void __launch_bounds__(256) k_bwd_sample(const float* __restrict__ th, int64_t B,
-                                                    const float* __restrict__ saved,
-                                                    const float* __restrict__ gF, float* d) {
-    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    const float* W2 = th + 2 * H;
-    const float* w3 = th + 3 * H + H * H;
-    const float* h = saved + b;
-    float g = gF[b];
-    float dz2[H];
-#pragma unroll
-    for (int i = 0; i < H; ++i) dz2[i] = h[(int64_t)(H + i) * B] > 0.0f ? g * w3[i] : 0.0f;
-    float* o = d + b;
-    // (four interleaved j chains, or W2 rows into H accumulators with i fully
-    // unrolled, measured slower: 50 and 57 us against 45 at a 65,536 batch)
-    for (int j = 0; j < H; ++j) {
-        float acc = 0.0f;
-#pragma unroll
-        for (int i = 0; i < H; ++i) acc = __builtin_fmaf(dz2[i], W2[i * H + j], acc);
-        o[(int64_t)j * B] = h[(int64_t)j * B] > 0.0f ? acc : 0.0f;
-    }
-#pragma unroll
-    for (int i = 0; i < H; ++i) o[(int64_t)(H + i) * B] = dz2[i];
-}
+// Per sample: dz2_i = g w3_i [h2_i > 0]; dz1_j = [h1_j > 0] sum_i dz2_i W2_ij,
+// computed inside the batch reduction below from the saved (h1, h2).
 
 // Batch reductions: block c sums samples [c*chunk, (c+1)*chunk) into its row
 // of `part` (P floats): dW2_ij = sum dz2_i h1_j, dw3_i = sum g h2_i,
-// db2 = sum dz2, dw1_j = sum dz1_j x, db1 = sum dz1, db3 = sum g.  dW2 is a
-// product [H x chunk] x [chunk x H]: each thread keeps a T x T tile of it in
-// registers (T = 4 at H = 64), fed from samples staged in LDS 32 at a time,
-// two 16-byte LDS reads per sample for T^2 FMAs.  Every sum runs over the
-// samples in order, so the result does not depend on scheduling.
+// db2 = sum dz2, dw1_j = sum dz1_j x, db1 = sum dz1, db3 = sum g.  Samples
+// are staged in LDS 32 at a time; their dz2 and dz1 are formed there (W2 in
+// LDS, each dz1_j one FMA chain over i in order), so they never go through
+// memory.  dW2 is a product [H x chunk] x [chunk x H]: each thread keeps a
+// T x T tile of it in registers (T = 4 at H = 64), two 16-byte LDS reads per
+// sample for T^2 FMAs.  Every sum runs over the samples in order, so the
+// result does not depend on scheduling.
 constexpr int kRedChunk = 64;  // 1024 workgroups at a 65,536 batch (256-sample chunks: 1 per CU)
 constexpr int kRedSub = 32;
 template <int H>
-__global__ void __launch_bounds__(256) k_bwd_reduce(const double* __restrict__ x, int64_t B,
-                                                    const float* __restrict__ saved, const float* __restrict__ d,
+__global__ void __launch_bounds__(256) k_bwd_reduce(const float* __restrict__ th, const double* __restrict__ x,
+                                                    int64_t B, const float* __restrict__ saved,
                                                     const float* __restrict__ gF, float* part) {
     constexpr int P = H * H + 4 * H + 1;
     constexpr int T = H >= 64 ? 4 : (H >= 32 ? 2 : 1);  // tile edge
@@ -466,8 +442,15 @@ __global__ void __launch_bounds__(256) k_bwd_reduce(const double* __restrict__ x
     __shared__ __align__(16) float sh1[kRedSub][H];
     __shared__ __align__(16) float sdz2[kRedSub][H];
     __shared__ float sh2[kRedSub][H], sdz1[kRedSub][H];
+    __shared__ float sW2[H][H];  // row i: hidden-2 unit i
+    __shared__ float sw3[H];
     __shared__ float sx[kRedSub], sg[kRedSub];
     const int tid = threadIdx.x;
+    for (int e = tid; e < H * H; e += 256) sW2[e / H][e % H] = th[2 * H + e];
+    for (int e = tid; e < H; e += 256) sw3[e] = th[3 * H + H * H + e];
+    // dz1 outputs per thread: kJ consecutive units of one sample
+    constexpr int kJ = H * kRedSub / 256;
+    static_assert(kJ >= 1 && H % kJ == 0, "dz1 outputs split evenly over the threads");
     const bool tile_on = tid < NBK * NBK;
     const int i0 = (tid / NBK) * T, j0 = (tid % NBK) * T;
     float acc[T][T];
@@ -486,13 +469,32 @@ __global__ void __launch_bounds__(256) k_bwd_reduce(const double* __restrict__ x
             const bool ok = b < B;
             sh1[r][c] = ok ? saved[(int64_t)c * B + b] : 0.0f;
             sh2[r][c] = ok ? saved[(int64_t)(H + c) * B + b] : 0.0f;
-            sdz1[r][c] = ok ? d[(int64_t)c * B + b] : 0.0f;
-            sdz2[r][c] = ok ? d[(int64_t)(H + c) * B + b] : 0.0f;
         }
         if (tid < kRedSub) {
             int64_t b = s0 + tid;
             sx[tid] = b < B ? (float)x[b] : 0.0f;
             sg[tid] = b < B ? gF[b] : 0.0f;
+        }
+        __syncthreads();
+        // dz2_i = g w3_i [h2_i > 0] (samples past B were staged as zeros)
+        for (int e = tid; e < kRedSub * H; e += 256) {
+            const int r = e / H, i = e % H;
+            sdz2[r][i] = sh2[r][i] > 0.0f ? sg[r] * sw3[i] : 0.0f;
+        }
+        __syncthreads();
+        // dz1_j = [h1_j > 0] sum_i dz2_i W2_ij, one FMA chain per output
+        {
+            const int r = tid / (H / kJ), j0 = (tid % (H / kJ)) * kJ;
+            float a1[kJ];
+#pragma unroll
+            for (int q = 0; q < kJ; ++q) a1[q] = 0.0f;
+            for (int i = 0; i < H; ++i) {
+                const float dz = sdz2[r][i];
+#pragma unroll
+                for (int q = 0; q < kJ; ++q) a1[q] = __builtin_fmaf(dz, sW2[i][j0 + q], a1[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < kJ; ++q) sdz1[r][j0 + q] = sh1[r][j0 + q] > 0.0f ? a1[q] : 0.0f;
         }
         __syncthreads();
         if (tile_on) {
@@ -701,18 +703,16 @@ hipError_t launch_mlp_forward(int H, const float* d_theta, const double* d_x, in
 
 size_t mlp_backward_ws_floats(int H, int64_t B) {
     int64_t rows = (B + kRedChunk - 1) / kRedChunk;
-    return (size_t)B * 2 * H + (size_t)rows * (H * H + 4 * H + 1);
+    return (size_t)rows * (H * H + 4 * H + 1);
 }
 
 template <int H>
 static hipError_t bwd_h(const float* th, const double* x, int64_t B, const float* saved, const float* gF,
                         float* gtheta, float* ws, hipStream_t st) {
     constexpr int P = H * H + 4 * H + 1;
-    float* d = ws;
-    float* part = ws + (size_t)B * 2 * H;
+    float* part = ws;
     int rows = (int)((B + kRedChunk - 1) / kRedChunk);
-    hipLaunchKernelGGL(k_bwd_sample<H>, dim3(nblk(B, 256)), dim3(256), 0, st, th, B, saved, gF, d);
-    hipLaunchKernelGGL(k_bwd_reduce<H>, dim3(rows), dim3(256), 0, st, x, B, saved, d, gF, part);
+    hipLaunchKernelGGL(k_bwd_reduce<H>, dim3(rows), dim3(256), 0, st, th, x, B, saved, gF, part);
     hipLaunchKernelGGL(k_sum_rows, dim3((P + 31) / 32), dim3(256), 0, st, part, rows, P, gtheta);
     return hipGetLastError();
 }
