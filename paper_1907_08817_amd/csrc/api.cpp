@@ -79,6 +79,12 @@ hipError_t launch_loss_grad(const float* d_F, const float* d_y, int64_t B, int l
                             float* d_loss, float* d_partial, hipStream_t st);
 hipError_t launch_keep_best(const float* d_theta, float* d_best, int P, const float* d_loss, float* d_best_loss,
                             hipStream_t st);
+hipError_t launch_loss_grad_keep(const float* d_F, const float* d_y, int64_t B, int loss, float delta, float* d_gF,
+                                 float* d_loss, float* d_partial, const float* d_theta, float* d_best, int P,
+                                 float* d_best_loss, hipStream_t st);
+hipError_t launch_mlp_backward_adam(int H, float* d_theta, const double* d_x, int64_t B, const float* d_saved,
+                                    const float* d_gF, float* d_ws, float* d_m1, float* d_m2, int64_t t, float lr,
+                                    float b1, float b2, float eps, hipStream_t st);
 size_t disorder_ws_doubles();
 hipError_t launch_disorder(const float* d_F, int64_t k, double* d_ws, hipStream_t st);
 }  // namespace nns
@@ -471,7 +477,7 @@ struct FitPlan {
     int64_t k, B;
     int H;
     size_t off_init, off_Fs, off_dis, off_best, off_knots, off_knotws, off_sample, off_count, off_x, off_y, off_bx, off_by, off_F, off_gF, off_saved, off_bws, off_theta,
-        off_grad, off_m1, off_m2, off_loss, off_lpart, off_radix, total;
+        off_m1, off_m2, off_loss, off_lpart, off_radix, total;
 };
 
 int64_t sample_count(int64_t n, double frac) {
@@ -502,7 +508,6 @@ FitPlan plan_fit(int64_t n, const nnsort_fit_params* fp) {
     p.off_saved = take((size_t)p.B * 2 * p.H * 4);
     p.off_bws = take(mlp_backward_ws_floats(p.H, p.B) * 4);
     p.off_theta = take((size_t)P * 4);
-    p.off_grad = take((size_t)P * 4);
     p.off_m1 = take((size_t)P * 4);
     p.off_m2 = take((size_t)P * 4);
     p.off_loss = take(64);
@@ -549,7 +554,6 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
     float* saved = (float*)(ws + P.off_saved);
     float* bws = (float*)(ws + P.off_bws);
     float* theta = (float*)(ws + P.off_theta);
-    float* grad = (float*)(ws + P.off_grad);
     float* m1 = (float*)(ws + P.off_m1);
     float* m2 = (float*)(ws + P.off_m2);
     float* dloss = (float*)(ws + P.off_loss);
@@ -600,12 +604,14 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
     for (int t = 1; t <= fp->steps; ++t) {
         NNS_HIP(launch_batch(x, y, (int64_t)k2, fp->seed, t, P.B, bx, by, st));
         NNS_HIP(launch_mlp_forward(H, theta, bx, P.B, F, saved, st));
-        NNS_HIP(launch_loss_grad(F, by, P.B, fp->loss, fp->huber_delta, gF, dloss, lpart, st));
-        NNS_HIP(launch_keep_best(theta, best, Pn, dloss, best_loss, st));
+        // loss and dL/dF, keeping the parameters if this batch's loss is the
+        // lowest so far; then the gradients applied by one Adam step
+        NNS_HIP(launch_loss_grad_keep(F, by, P.B, fp->loss, fp->huber_delta, gF, dloss, lpart, theta, best, Pn,
+                                      best_loss, st));
         if (loss_history && t - 1 < history_len)
             NNS_HIP(hipMemcpyAsync(loss_history + (t - 1), dloss, 4, hipMemcpyDeviceToHost, st));
-        NNS_HIP(launch_mlp_backward(H, theta, bx, P.B, saved, gF, grad, bws, st));
-        NNS_HIP(launch_adam(theta, grad, m1, m2, Pn, t, fp->lr, 0.9f, 0.999f, 1e-8f, st));
+        NNS_HIP(launch_mlp_backward_adam(H, theta, bx, P.B, saved, gF, bws, m1, m2, t, fp->lr, 0.9f, 0.999f, 1e-8f,
+                                         st));
     }
     // Returned: the parameters with the lowest batch loss seen, unless they
     // move F backwards along the sorted sample more than the initial ones do

@@ -416,6 +416,32 @@ __global__ void __launch_bounds__(kLossBlocks) k_loss_final(const float* __restr
     }
 }
 
+// The fit's loss total with the keep-best step: the same sum as
+// k_loss_final, then the parameters are kept when this batch's loss is the
+// lowest so far (as k_keep_best).
+__global__ void __launch_bounds__(kLossBlocks) k_loss_final_keep(const float* __restrict__ partial, int nb,
+                                                               int64_t B, float* loss_out,
+                                                               const float* __restrict__ th, float* best, int P,
+                                                               float* best_loss) {
+    __shared__ float s_p[kLossBlocks];
+    __shared__ float s_l;
+    __shared__ int better;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) s_p[i] = partial[i];  // nb <= kLossBlocks
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float s = 0.0f;
+        for (int i = 0; i < nb; ++i) s += s_p[i];
+        const float l = s / (float)B;
+        loss_out[0] = l;
+        s_l = l;
+        better = l < best_loss[0] ? 1 : 0;
+    }
+    __syncthreads();
+    if (!better) return;
+    for (int p = threadIdx.x; p < P; p += blockDim.x) best[p] = th[p];
+    if (threadIdx.x == 0) best_loss[0] = s_l;
+}
+
 // ---- backward ----
 // Per sample: dz2_i = g w3_i [h2_i > 0]; dz1_j = [h1_j > 0] sum_i dz2_i W2_ij,
 // computed inside the batch reduction below from the saved (h1, h2).
@@ -549,12 +575,22 @@ __global__ void __launch_bounds__(256) k_bwd_reduce(const float* __restrict__ th
     if (tid == 0) row[4 * H + H * H] = accb3;
 }
 
+// One Adam step of parameter p with gradient gv (bias corrections c1, c2).
+__device__ __forceinline__ void adam_update(int64_t p, float gv, float* th, float* m1, float* m2, float b1, float b2,
+                                            float c1, float c2, float lr, float eps) {
+    float m = b1 * m1[p] + (1.0f - b1) * gv;
+    float v = b2 * m2[p] + (1.0f - b2) * gv * gv;
+    m1[p] = m;
+    m2[p] = v;
+    float mh = m / c1, vh = v / c2;
+    th[p] = th[p] - lr * mh / (sqrtf(vh) + eps);
+}
+
 // Column sums of `part` (rows x P), in a fixed order: 32 columns per block,
 // eight groups of rows summed side by side, then the eight group sums in order.
-__global__ void __launch_bounds__(256) k_sum_rows(const float* __restrict__ part, int rows, int P, float* out) {
-    __shared__ float s[8][32];
-    const int c = threadIdx.x & 31, grp = threadIdx.x >> 5;
-    const int p = blockIdx.x * 32 + c;
+// The result is valid in the threads of group 0 (column p).
+__device__ __forceinline__ float column_sum(const float* __restrict__ part, int rows, int P, int p, int c, int grp,
+                                            float (*s)[32]) {
     float acc = 0.0f;
     if (p < P) {
 #pragma unroll 8
@@ -562,12 +598,32 @@ __global__ void __launch_bounds__(256) k_sum_rows(const float* __restrict__ part
     }
     s[grp][c] = acc;
     __syncthreads();
-    if (grp == 0 && p < P) {
-        float t = 0.0f;
+    float t = 0.0f;
+    if (grp == 0) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) t += s[q][c];
-        out[p] = t;
     }
+    return t;
+}
+
+__global__ void __launch_bounds__(256) k_sum_rows(const float* __restrict__ part, int rows, int P, float* out) {
+    __shared__ float s[8][32];
+    const int c = threadIdx.x & 31, grp = threadIdx.x >> 5;
+    const int p = blockIdx.x * 32 + c;
+    const float t = column_sum(part, rows, P, p, c, grp, s);
+    if (grp == 0 && p < P) out[p] = t;
+}
+
+// The fit's update: the same column sums, each fed straight into its
+// parameter's Adam step (the gradient never goes through memory).
+__global__ void __launch_bounds__(256) k_sum_rows_adam(const float* __restrict__ part, int rows, int P, float* th,
+                                                       float* m1, float* m2, float b1, float b2, float c1, float c2,
+                                                       float lr, float eps) {
+    __shared__ float s[8][32];
+    const int c = threadIdx.x & 31, grp = threadIdx.x >> 5;
+    const int p = blockIdx.x * 32 + c;
+    const float t = column_sum(part, rows, P, p, c, grp, s);
+    if (grp == 0 && p < P) adam_update(p, t, th, m1, m2, b1, b2, c1, c2, lr, eps);
 }
 
 // Keep the parameters with the lowest batch loss seen so far (the loss of a
@@ -633,13 +689,7 @@ __global__ void __launch_bounds__(256) k_adam(float* th, const float* __restrict
                                               float eps) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= count) return;
-    float gv = g[p];
-    float m = b1 * m1[p] + (1.0f - b1) * gv;
-    float v = b2 * m2[p] + (1.0f - b2) * gv * gv;
-    m1[p] = m;
-    m2[p] = v;
-    float mh = m / c1, vh = v / c2;
-    th[p] = th[p] - lr * mh / (sqrtf(vh) + eps);
+    adam_update(p, g[p], th, m1, m2, b1, b2, c1, c2, lr, eps);
 }
 
 // ---- launchers ----
@@ -706,24 +756,52 @@ size_t mlp_backward_ws_floats(int H, int64_t B) {
     return (size_t)rows * (H * H + 4 * H + 1);
 }
 
+// Backward pass: per-chunk partial gradients into ws, then either their sums
+// (gtheta) or, when `adam` is given, their sums applied as one Adam step.
+struct AdamStep {
+    float* m1;
+    float* m2;
+    float b1, b2, c1, c2, lr, eps;
+};
+
 template <int H>
 static hipError_t bwd_h(const float* th, const double* x, int64_t B, const float* saved, const float* gF,
-                        float* gtheta, float* ws, hipStream_t st) {
+                        float* gtheta, float* ws, const AdamStep* adam, float* th_update, hipStream_t st) {
     constexpr int P = H * H + 4 * H + 1;
     float* part = ws;
     int rows = (int)((B + kRedChunk - 1) / kRedChunk);
     hipLaunchKernelGGL(k_bwd_reduce<H>, dim3(rows), dim3(256), 0, st, th, x, B, saved, gF, part);
-    hipLaunchKernelGGL(k_sum_rows, dim3((P + 31) / 32), dim3(256), 0, st, part, rows, P, gtheta);
+    if (adam)
+        hipLaunchKernelGGL(k_sum_rows_adam, dim3((P + 31) / 32), dim3(256), 0, st, part, rows, P, th_update,
+                           adam->m1, adam->m2, adam->b1, adam->b2, adam->c1, adam->c2, adam->lr, adam->eps);
+    else
+        hipLaunchKernelGGL(k_sum_rows, dim3((P + 31) / 32), dim3(256), 0, st, part, rows, P, gtheta);
     return hipGetLastError();
 }
 
 hipError_t launch_mlp_backward(int H, const float* d_theta, const double* d_x, int64_t B, const float* d_saved,
                                const float* d_gF, float* d_gtheta, float* d_ws, hipStream_t st) {
     switch (H) {
-    case 8: return bwd_h<8>(d_theta, d_x, B, d_saved, d_gF, d_gtheta, d_ws, st);
-    case 16: return bwd_h<16>(d_theta, d_x, B, d_saved, d_gF, d_gtheta, d_ws, st);
-    case 32: return bwd_h<32>(d_theta, d_x, B, d_saved, d_gF, d_gtheta, d_ws, st);
-    case 64: return bwd_h<64>(d_theta, d_x, B, d_saved, d_gF, d_gtheta, d_ws, st);
+    case 8: return bwd_h<8>(d_theta, d_x, B, d_saved, d_gF, d_gtheta, d_ws, nullptr, nullptr, st);
+    case 16: return bwd_h<16>(d_theta, d_x, B, d_saved, d_gF, d_gtheta, d_ws, nullptr, nullptr, st);
+    case 32: return bwd_h<32>(d_theta, d_x, B, d_saved, d_gF, d_gtheta, d_ws, nullptr, nullptr, st);
+    case 64: return bwd_h<64>(d_theta, d_x, B, d_saved, d_gF, d_gtheta, d_ws, nullptr, nullptr, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// The fit's backward and update: gradients of d_theta applied to it by one
+// Adam step t (the same arithmetic as launch_mlp_backward then launch_adam).
+hipError_t launch_mlp_backward_adam(int H, float* d_theta, const double* d_x, int64_t B, const float* d_saved,
+                                    const float* d_gF, float* d_ws, float* d_m1, float* d_m2, int64_t t, float lr,
+                                    float b1, float b2, float eps, hipStream_t st) {
+    const AdamStep a{d_m1, d_m2, b1, b2, (float)(1.0 - pow((double)b1, (double)t)),
+                     (float)(1.0 - pow((double)b2, (double)t)), lr, eps};
+    switch (H) {
+    case 8: return bwd_h<8>(d_theta, d_x, B, d_saved, d_gF, nullptr, d_ws, &a, d_theta, st);
+    case 16: return bwd_h<16>(d_theta, d_x, B, d_saved, d_gF, nullptr, d_ws, &a, d_theta, st);
+    case 32: return bwd_h<32>(d_theta, d_x, B, d_saved, d_gF, nullptr, d_ws, &a, d_theta, st);
+    case 64: return bwd_h<64>(d_theta, d_x, B, d_saved, d_gF, nullptr, d_ws, &a, d_theta, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -734,6 +812,17 @@ hipError_t launch_loss_grad(const float* d_F, const float* d_y, int64_t B, int l
                             float* d_loss, float* d_partial, hipStream_t st) {
     hipLaunchKernelGGL(k_loss, dim3(kLossBlocks), dim3(256), 0, st, d_F, d_y, B, loss, delta, d_gF, d_partial);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kLossBlocks), 0, st, d_partial, kLossBlocks, B, d_loss);
+    return hipGetLastError();
+}
+
+// The fit's loss: as launch_loss_grad, with the keep-best step folded into
+// the final sum.
+hipError_t launch_loss_grad_keep(const float* d_F, const float* d_y, int64_t B, int loss, float delta, float* d_gF,
+                                 float* d_loss, float* d_partial, const float* d_theta, float* d_best, int P,
+                                 float* d_best_loss, hipStream_t st) {
+    hipLaunchKernelGGL(k_loss, dim3(kLossBlocks), dim3(256), 0, st, d_F, d_y, B, loss, delta, d_gF, d_partial);
+    hipLaunchKernelGGL(k_loss_final_keep, dim3(1), dim3(kLossBlocks), 0, st, d_partial, kLossBlocks, B, d_loss,
+                       d_theta, d_best, P, d_best_loss);
     return hipGetLastError();
 }
 
