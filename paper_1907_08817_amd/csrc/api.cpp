@@ -85,6 +85,8 @@ hipError_t launch_loss_grad_keep(const float* d_F, const float* d_y, int64_t B, 
 hipError_t launch_mlp_backward_adam(int H, float* d_theta, const double* d_x, int64_t B, const float* d_saved,
                                     const float* d_gF, float* d_ws, float* d_m1, float* d_m2, int64_t t, float lr,
                                     float b1, float b2, float eps, hipStream_t st);
+hipError_t launch_mlp_forward_fit(int H, const float* d_theta, const double* d_x, int64_t B, float* d_F,
+                                  float* d_saved, hipStream_t st);
 size_t disorder_ws_doubles();
 hipError_t launch_disorder(const float* d_F, int64_t k, double* d_ws, hipStream_t st);
 }  // namespace nns
@@ -603,7 +605,7 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
     NNS_HIP(fill_u32((uint32_t*)best_loss, 1, 0x7F800000u, st));  // +inf
     for (int t = 1; t <= fp->steps; ++t) {
         NNS_HIP(launch_batch(x, y, (int64_t)k2, fp->seed, t, P.B, bx, by, st));
-        NNS_HIP(launch_mlp_forward(H, theta, bx, P.B, F, saved, st));
+        NNS_HIP(launch_mlp_forward_fit(H, theta, bx, P.B, F, saved, st));
         // loss and dL/dF, keeping the parameters if this batch's loss is the
         // lowest so far; then the gradients applied by one Adam step
         NNS_HIP(launch_loss_grad_keep(F, by, P.B, fp->loss, fp->huber_delta, gF, dloss, lpart, theta, best, Pn,
@@ -619,9 +621,9 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
     const float* chosen = best;
     if (fp->steps > 0) {
         const size_t dw = disorder_ws_doubles();
-        NNS_HIP(launch_mlp_forward(H, init_theta, x, (int64_t)k2, Fs, nullptr, st));
+        NNS_HIP(launch_mlp_forward_fit(H, init_theta, x, (int64_t)k2, Fs, nullptr, st));
         NNS_HIP(launch_disorder(Fs, (int64_t)k2, dis, st));
-        NNS_HIP(launch_mlp_forward(H, best, x, (int64_t)k2, Fs, nullptr, st));
+        NNS_HIP(launch_mlp_forward_fit(H, best, x, (int64_t)k2, Fs, nullptr, st));
         NNS_HIP(launch_disorder(Fs, (int64_t)k2, dis + dw, st));
         double d[2];
         NNS_HIP(hipMemcpyAsync(&d[0], dis + dw - 1, 8, hipMemcpyDeviceToHost, st));

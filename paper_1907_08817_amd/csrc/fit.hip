@@ -370,6 +370,72 @@ __global__ void __launch_bounds__(256) k_fwd(const float* __restrict__ th, const
     F[b] = p + s;
 }
 
+// The same forward pass for the fit, spread over four waves per 64 samples:
+// wave q computes hidden-2 units [q H/4, (q+1) H/4) of its samples (lane =
+// sample), each z2_i the same FMA chain over j in order as above; the
+// activations meet in LDS and the compensated layer-3 sum runs over i in
+// order as above.  h1, h2 and F are therefore the same bit for bit, with four
+// times as many waves to cover latency.
+template <int H>
+__global__ void __launch_bounds__(256) k_fwd_fit(const float* __restrict__ th, const double* __restrict__ x,
+                                                 int64_t B, float* F, float* saved) {
+    constexpr int Q = H / 4;  // hidden-2 units per wave
+    __shared__ float s_h2[64][H + 1];
+    // the wave index, known wave-uniform so that W2 is read by scalar loads
+    const int lane = threadIdx.x & 63, q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t b = (int64_t)blockIdx.x * 64 + lane;
+    const bool ok = b < B;
+    const float* w1 = th;
+    const float* b1 = th + H;
+    const float* W2 = th + 2 * H;
+    const float* b2 = th + 2 * H + H * H;
+    const float* w3 = th + 3 * H + H * H;
+    const double xv = ok ? x[b] : 0.0;
+    const float xh = (float)xv;
+    const float xl = (float)(xv - (double)xh);
+    float h1[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        float z = __builtin_fmaf(w1[j], xh, b1[j]);
+        z = __builtin_fmaf(w1[j], xl, z);
+        h1[j] = z > 0.0f ? z : 0.0f;
+    }
+    static_assert(Q % 4 == 0 || Q < 4, "outputs in groups of four");
+    constexpr int G = Q < 4 ? Q : 4;
+    for (int i0 = q * Q; i0 < (q + 1) * Q; i0 += G) {
+        float z[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) z[k] = b2[i0 + k];
+#pragma unroll
+        for (int j = 0; j < H; ++j)
+#pragma unroll
+            for (int k = 0; k < G; ++k) z[k] = __builtin_fmaf(W2[(i0 + k) * H + j], h1[j], z[k]);
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const float h2 = z[k] > 0.0f ? z[k] : 0.0f;
+            s_h2[lane][i0 + k] = h2;
+            if (saved && ok) saved[(int64_t)(H + i0 + k) * B + b] = h2;
+        }
+    }
+    if (saved && ok) {  // h1: a quarter of the units per wave
+#pragma unroll
+        for (int j = 0; j < H; ++j)
+            if (j / Q == q) saved[(int64_t)j * B + b] = h1[j];
+    }
+    __syncthreads();
+    if (q != 0 || !ok) return;
+    float p = th[4 * H + H * H], s = 0.0f;
+    for (int i = 0; i < H; ++i) {
+        const float h2 = s_h2[lane][i];
+        float pr = w3[i] * h2;
+        float r = __builtin_fmaf(w3[i], h2, -pr);
+        float e;
+        p = two_sum_f(p, pr, e);
+        s = s + (e + r);
+    }
+    F[b] = p + s;
+}
+
 // ---- loss and dL/dF ----
 constexpr int kLossBlocks = 256;
 __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ F, const float* __restrict__ y, int64_t B,
@@ -738,6 +804,24 @@ template <int H>
 static hipError_t fwd_h(const float* th, const double* x, int64_t B, float* F, float* saved, hipStream_t st) {
     hipLaunchKernelGGL(k_fwd<H>, dim3(nblk(B, 256)), dim3(256), 0, st, th, x, B, F, saved);
     return hipGetLastError();
+}
+
+// The fit's forward: k_fwd_fit, the same results as launch_mlp_forward.
+template <int H>
+static hipError_t fwd_fit_h(const float* th, const double* x, int64_t B, float* F, float* saved, hipStream_t st) {
+    hipLaunchKernelGGL(k_fwd_fit<H>, dim3(nblk(B, 64)), dim3(256), 0, st, th, x, B, F, saved);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward_fit(int H, const float* d_theta, const double* d_x, int64_t B, float* d_F,
+                                  float* d_saved, hipStream_t st) {
+    switch (H) {
+    case 8: return fwd_fit_h<8>(d_theta, d_x, B, d_F, d_saved, st);
+    case 16: return fwd_fit_h<16>(d_theta, d_x, B, d_F, d_saved, st);
+    case 32: return fwd_fit_h<32>(d_theta, d_x, B, d_F, d_saved, st);
+    case 64: return fwd_fit_h<64>(d_theta, d_x, B, d_F, d_saved, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_mlp_forward(int H, const float* d_theta, const double* d_x, int64_t B, float* d_F,
