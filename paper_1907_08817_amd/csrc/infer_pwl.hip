@@ -7,16 +7,16 @@
 // output F = b3 + sum_i w3_i relu(z2_i) is affine.  The function is the same
 // as the direct evaluation of the same weights; only the rounding differs.
 //
-// Compiled on the device from the FP32 weights in FP64, in three launches:
+// Compiled on the device from the FP32 weights in FP64, in two launches:
 //  1. k_pwl_intervals, one workgroup per interval: the sorted layer-1 knots
 //     (every workgroup ranks them the same way), A and B of the interval, and
 //     its layer-2 roots sorted;
 //  2. k_pwl_pieces, one workgroup per interval: the interval's first piece
 //     index (from the root counts), then per piece its left edge xq, slope
-//     alpha and value Fq at xq;
+//     alpha and value Fq at xq.
 // The map kernel's workgroups each index the pieces by 1024 cells of [0, 1],
-// then find each key's piece (two index entries bracket it,
-// a binary search between them settles it) and evaluates one FP64 fma.
+// then find each key's piece (two index entries bracket it, a binary search
+// between them settles it) and evaluate one FP64 fma.
 #include "infer_common.h"
 
 namespace nns {
