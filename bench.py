@@ -86,6 +86,33 @@ def valu_issue(counters: dict, launch_ms: float):
     return {"valu_insts": insts, "issue_ms": round(ms, 4), "frac": round(ms / launch_ms, 4)}
 
 
+def host_parallel_sort(xs: np.ndarray, threads: int) -> np.ndarray:
+    """A conventional multi-threaded host sort, for context: each of `threads`
+    chunks is sorted by one worker and cut at splitters drawn from a sorted
+    sample; each bucket then merges its sorted pieces (numpy's stable sort
+    finds the runs).  numpy releases the GIL inside sort and searchsorted."""
+    from concurrent.futures import ThreadPoolExecutor
+    if threads < 2 or xs.size < 1 << 16:
+        return np.sort(xs)
+    rng = np.random.default_rng(0)
+    sample = np.sort(xs[rng.integers(0, xs.size, 64 * threads)])
+    split = sample[64::64]
+    chunks = np.array_split(xs, threads)
+    with ThreadPoolExecutor(threads) as pool:
+        srt = list(pool.map(np.sort, chunks))
+        cuts = [np.concatenate(([0], np.searchsorted(c, split), [c.size])) for c in srt]
+        sizes = [sum(int(cuts[c][b + 1] - cuts[c][b]) for c in range(threads)) for b in range(threads)]
+        offs = np.concatenate(([0], np.cumsum(sizes)))
+        out = np.empty_like(xs)
+
+        def bucket(b):
+            piece = np.concatenate([srt[c][cuts[c][b]:cuts[c][b + 1]] for c in range(threads)])
+            out[offs[b]:offs[b + 1]] = np.sort(piece, kind="stable")
+
+        list(pool.map(bucket, range(threads)))
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -258,9 +285,15 @@ def main():
         # a conventional host sort of the same sample (numpy's introsort, one
         # thread), with the host's CPU model
         t0 = time.perf_counter()
-        np.sort(xs, kind="quicksort")
+        ref = np.sort(xs, kind="quicksort")
         context["host_sort_gkeys"] = round(m / (time.perf_counter() - t0) / 1e9, 5)
         context["host_sort"] = "numpy quicksort (introsort), 1 thread, same sample"
+        t0 = time.perf_counter()
+        par = host_parallel_sort(xs, cores)
+        context["host_par_sort_gkeys"] = round(m / (time.perf_counter() - t0) / 1e9, 5)
+        context["host_par_sort"] = (f"sample sort over {cores} threads (numpy sort per chunk and bucket), "
+                                    f"same sample, output equal to the 1-thread sort: "
+                                    f"{bool(np.array_equal(par, ref, equal_nan=True))}")
         try:
             context["host_cpu"] = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo")
                                        if l.startswith("model name"))

@@ -71,17 +71,15 @@ hipError_t launch_make_xy(const uint64_t* d_sorted, int64_t k, bool is_f64, doub
 hipError_t launch_init(float* d_theta, int H, int init, uint64_t seed, const double* d_x, int64_t k,
                        int64_t* d_knots, void* d_knotws, hipStream_t st);
 size_t knot_ws_bytes();
-hipError_t launch_batch(const double* d_x, const float* d_y, int64_t k, uint64_t seed, int64_t step, int64_t B,
-                        double* d_bx, float* d_by, hipStream_t st);
 size_t mlp_backward_ws_floats(int H, int64_t B);
 size_t loss_ws_floats();
 hipError_t launch_loss_grad(const float* d_F, const float* d_y, int64_t B, int loss, float delta, float* d_gF,
                             float* d_loss, float* d_partial, hipStream_t st);
-hipError_t launch_keep_best(const float* d_theta, float* d_best, int P, const float* d_loss, float* d_best_loss,
-                            hipStream_t st);
-hipError_t launch_loss_grad_keep(const float* d_F, const float* d_y, int64_t B, int loss, float delta, float* d_gF,
-                                 float* d_loss, float* d_partial, const float* d_theta, float* d_best, int P,
-                                 float* d_best_loss, hipStream_t st);
+size_t fit_loss_ws_floats(int64_t B);
+hipError_t launch_fit_step_forward(int H, const float* d_theta, const double* d_x, const float* d_y, int64_t k,
+                                   uint64_t seed, int64_t step, int64_t B, double* d_bx, float* d_saved, int loss,
+                                   float delta, float* d_gF, float* d_loss, float* d_partial, float* d_best, int P,
+                                   float* d_best_loss, hipStream_t st);
 hipError_t launch_mlp_backward_adam(int H, float* d_theta, const double* d_x, int64_t B, const float* d_saved,
                                     const float* d_gF, float* d_ws, float* d_m1, float* d_m2, int64_t t, float lr,
                                     float b1, float b2, float eps, hipStream_t st);
@@ -478,7 +476,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
 struct FitPlan {
     int64_t k, B;
     int H;
-    size_t off_init, off_Fs, off_dis, off_best, off_knots, off_knotws, off_sample, off_count, off_x, off_y, off_bx, off_by, off_F, off_gF, off_saved, off_bws, off_theta,
+    size_t off_init, off_Fs, off_dis, off_best, off_knots, off_knotws, off_sample, off_count, off_x, off_y, off_bx, off_gF, off_saved, off_bws, off_theta,
         off_m1, off_m2, off_loss, off_lpart, off_radix, total;
 };
 
@@ -504,8 +502,6 @@ FitPlan plan_fit(int64_t n, const nnsort_fit_params* fp) {
     p.off_x = take((size_t)p.k * 8);
     p.off_y = take((size_t)p.k * 4);
     p.off_bx = take((size_t)p.B * 8);
-    p.off_by = take((size_t)p.B * 4);
-    p.off_F = take((size_t)p.B * 4);
     p.off_gF = take((size_t)p.B * 4);
     p.off_saved = take((size_t)p.B * 2 * p.H * 4);
     p.off_bws = take(mlp_backward_ws_floats(p.H, p.B) * 4);
@@ -513,7 +509,7 @@ FitPlan plan_fit(int64_t n, const nnsort_fit_params* fp) {
     p.off_m1 = take((size_t)P * 4);
     p.off_m2 = take((size_t)P * 4);
     p.off_loss = take(64);
-    p.off_lpart = take(loss_ws_floats() * 4);
+    p.off_lpart = take(fit_loss_ws_floats(p.B) * 4);
     p.off_knots = take((NNSORT_MAX_HIDDEN + 1) * 8);
     p.off_knotws = take(knot_ws_bytes());
     p.off_best = take((size_t)(P + 64) * 4);
@@ -550,8 +546,6 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
     double* x = (double*)(ws + P.off_x);
     float* y = (float*)(ws + P.off_y);
     double* bx = (double*)(ws + P.off_bx);
-    float* by = (float*)(ws + P.off_by);
-    float* F = (float*)(ws + P.off_F);
     float* gF = (float*)(ws + P.off_gF);
     float* saved = (float*)(ws + P.off_saved);
     float* bws = (float*)(ws + P.off_bws);
@@ -604,12 +598,11 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
     NNS_HIP(hipMemcpyAsync(init_theta, theta, (size_t)Pn * 4, hipMemcpyDeviceToDevice, st));
     NNS_HIP(fill_u32((uint32_t*)best_loss, 1, 0x7F800000u, st));  // +inf
     for (int t = 1; t <= fp->steps; ++t) {
-        NNS_HIP(launch_batch(x, y, (int64_t)k2, fp->seed, t, P.B, bx, by, st));
-        NNS_HIP(launch_mlp_forward_fit(H, theta, bx, P.B, F, saved, st));
-        // loss and dL/dF, keeping the parameters if this batch's loss is the
-        // lowest so far; then the gradients applied by one Adam step
-        NNS_HIP(launch_loss_grad_keep(F, by, P.B, fp->loss, fp->huber_delta, gF, dloss, lpart, theta, best, Pn,
-                                      best_loss, st));
+        // the batch, its forward, loss and dL/dF, keeping the parameters if
+        // this batch's loss is the lowest so far; then the gradients applied
+        // by one Adam step
+        NNS_HIP(launch_fit_step_forward(H, theta, x, y, (int64_t)k2, fp->seed, t, P.B, bx, saved, fp->loss,
+                                        fp->huber_delta, gF, dloss, lpart, best, Pn, best_loss, st));
         if (loss_history && t - 1 < history_len)
             NNS_HIP(hipMemcpyAsync(loss_history + (t - 1), dloss, 4, hipMemcpyDeviceToHost, st));
         NNS_HIP(launch_mlp_backward_adam(H, theta, bx, P.B, saved, gF, bws, m1, m2, t, fp->lr, 0.9f, 0.999f, 1e-8f,

@@ -297,17 +297,6 @@ __global__ void k_init(float* theta, int H, int init, uint64_t seed, const doubl
     }
 }
 
-// Gather a batch: bx[b] = x[idx], by[b] = y[idx], idx = Philox(step, b) mod k.
-__global__ void __launch_bounds__(256) k_batch(const double* __restrict__ x, const float* __restrict__ y,
-                                               int64_t k, uint64_t seed, int64_t step, int64_t B,
-                                               double* bx, float* by) {
-    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    uint64_t j = rand64(seed, kStreamBatch, (uint64_t)b, (uint32_t)step) % (uint64_t)k;
-    bx[b] = x[j];
-    by[b] = y[j];
-}
-
 // ---- forward (FP32 form order), saving h1 and h2 ----
 __device__ __forceinline__ float two_sum_f(float a, float b, float& err) {
     float s = a + b;
@@ -376,9 +365,42 @@ __global__ void __launch_bounds__(256) k_fwd(const float* __restrict__ th, const
 // activations meet in LDS and the compensated layer-3 sum runs over i in
 // order as above.  h1, h2 and F are therefore the same bit for bit, with four
 // times as many waves to cover latency.
-template <int H>
+// One training step's batch, drawn and scored inside the fit's forward.
+struct FitBatch {
+    const float* y;   // labels of the sample
+    int64_t k;        // sample size
+    uint64_t seed;
+    int64_t step;
+    double* bx;       // out: the batch's inputs, for the backward
+    int loss;         // 0 MSE, 1 Huber
+    float delta;
+    float* gF;        // out: dL/dF per batch entry
+    float* partial;   // out: the loss summed over each workgroup's 64 entries
+};
+
+// Loss of one entry and its dL/dF before the 1/B scale (MSE, or Huber with
+// threshold delta).
+__device__ __forceinline__ float loss_term(float e, int loss, float delta, float& g) {
+    if (loss == 1) {
+        if (fabsf(e) <= delta) {
+            g = e;
+            return 0.5f * e * e;
+        }
+        g = e > 0.0f ? delta : -delta;
+        return delta * fabsf(e) - 0.5f * delta * delta;
+    }
+    g = 2.0f * e;
+    return e * e;
+}
+
+// STEP = false: F of x[0..B).  STEP = true: x is the fit sample and entry b of
+// the batch is x[idx], idx = Philox(step, b) mod k (stream kStreamBatch); the
+// kernel then also writes bx, and in place of F the loss terms: dL/dF and one
+// partial loss sum per 64 entries (a butterfly over the wave, so the order is
+// fixed).
+template <int H, bool STEP>
 __global__ void __launch_bounds__(256) k_fwd_fit(const float* __restrict__ th, const double* __restrict__ x,
-                                                 int64_t B, float* F, float* saved) {
+                                                 int64_t B, float* F, float* saved, FitBatch fb) {
     constexpr int Q = H / 4;  // hidden-2 units per wave
     __shared__ float s_h2[64][H + 1];
     // the wave index, known wave-uniform so that W2 is read by scalar loads
@@ -390,7 +412,26 @@ __global__ void __launch_bounds__(256) k_fwd_fit(const float* __restrict__ th, c
     const float* W2 = th + 2 * H;
     const float* b2 = th + 2 * H + H * H;
     const float* w3 = th + 3 * H + H * H;
-    const double xv = ok ? x[b] : 0.0;
+    double xv;
+    float yv = 0.0f;
+    if constexpr (STEP) {
+        // wave 0 draws the entries and hands the inputs to the other waves
+        __shared__ double s_x[64];
+        if (q == 0) {
+            double v = 0.0;
+            if (ok) {
+                const uint64_t j = rand64(fb.seed, kStreamBatch, (uint64_t)b, (uint32_t)fb.step) % (uint64_t)fb.k;
+                v = x[j];
+                yv = fb.y[j];
+                fb.bx[b] = v;
+            }
+            s_x[lane] = v;
+        }
+        __syncthreads();
+        xv = s_x[lane];
+    } else {
+        xv = ok ? x[b] : 0.0;
+    }
     const float xh = (float)xv;
     const float xl = (float)(xv - (double)xh);
     float h1[H];
@@ -423,7 +464,7 @@ __global__ void __launch_bounds__(256) k_fwd_fit(const float* __restrict__ th, c
             if (j / Q == q) saved[(int64_t)j * B + b] = h1[j];
     }
     __syncthreads();
-    if (q != 0 || !ok) return;
+    if (q != 0) return;
     float p = th[4 * H + H * H], s = 0.0f;
     for (int i = 0; i < H; ++i) {
         const float h2 = s_h2[lane][i];
@@ -433,7 +474,20 @@ __global__ void __launch_bounds__(256) k_fwd_fit(const float* __restrict__ th, c
         p = two_sum_f(p, pr, e);
         s = s + (e + r);
     }
-    F[b] = p + s;
+    const float Fb = p + s;
+    if constexpr (STEP) {
+        float l = 0.0f;
+        if (ok) {
+            float g;
+            l = loss_term(Fb - yv, fb.loss, fb.delta, g);
+            fb.gF[b] = g * (1.0f / (float)B);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
+        if (lane == 0) fb.partial[blockIdx.x] = l;
+    } else if (ok) {
+        F[b] = Fb;
+    }
 }
 
 // ---- loss and dL/dF ----
@@ -444,20 +498,8 @@ __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ F, const
     float acc = 0.0f;
     float invB = 1.0f / (float)B;
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < B; b += (int64_t)gridDim.x * blockDim.x) {
-        float e = F[b] - y[b];
-        float g, l;
-        if (loss == 1) {
-            if (fabsf(e) <= delta) {
-                l = 0.5f * e * e;
-                g = e;
-            } else {
-                l = delta * fabsf(e) - 0.5f * delta * delta;
-                g = e > 0.0f ? delta : -delta;
-            }
-        } else {
-            l = e * e;
-            g = 2.0f * e;
-        }
+        float g;
+        const float l = loss_term(F[b] - y[b], loss, delta, g);
         gF[b] = g * invB;
         acc += l;
     }
@@ -482,21 +524,36 @@ __global__ void __launch_bounds__(kLossBlocks) k_loss_final(const float* __restr
     }
 }
 
-// The fit's loss total with the keep-best step: the same sum as
-// k_loss_final, then the parameters are kept when this batch's loss is the
-// lowest so far (as k_keep_best).
+// The fit's loss total with the keep-best step: the nb partial sums of the
+// step's forward are added in 256 groups of ceil(nb / 256) consecutive ones,
+// those sums in 16 groups of 16, and those 16 in order (a fixed order); then
+// the parameters are kept when this batch's loss is the lowest so far (a
+// step's loss is measured before its update).
 __global__ void __launch_bounds__(kLossBlocks) k_loss_final_keep(const float* __restrict__ partial, int nb,
                                                                int64_t B, float* loss_out,
                                                                const float* __restrict__ th, float* best, int P,
                                                                float* best_loss) {
-    __shared__ float s_p[kLossBlocks];
+    static_assert(kLossBlocks == 256, "16 groups of 16");
+    __shared__ float s_p[kLossBlocks], s_q[16];
     __shared__ float s_l;
     __shared__ int better;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) s_p[i] = partial[i];  // nb <= kLossBlocks
+    {
+        const int c = (nb + kLossBlocks - 1) / kLossBlocks;
+        const int i0 = threadIdx.x * c, i1 = i0 + c < nb ? i0 + c : nb;
+        float g = 0.0f;
+        for (int i = i0; i < i1; ++i) g += partial[i];
+        s_p[threadIdx.x] = g;
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        float g = 0.0f;
+        for (int i = 0; i < 16; ++i) g += s_p[16 * threadIdx.x + i];
+        s_q[threadIdx.x] = g;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         float s = 0.0f;
-        for (int i = 0; i < nb; ++i) s += s_p[i];
+        for (int i = 0; i < 16; ++i) s += s_q[i];
         const float l = s / (float)B;
         loss_out[0] = l;
         s_l = l;
@@ -515,19 +572,23 @@ __global__ void __launch_bounds__(kLossBlocks) k_loss_final_keep(const float* __
 // Batch reductions: block c sums samples [c*chunk, (c+1)*chunk) into its row
 // of `part` (P floats): dW2_ij = sum dz2_i h1_j, dw3_i = sum g h2_i,
 // db2 = sum dz2, dw1_j = sum dz1_j x, db1 = sum dz1, db3 = sum g.  Samples
-// are staged in LDS 32 at a time; their dz2 and dz1 are formed there (W2 in
+// are staged in LDS 16 or 32 at a time; their dz2 and dz1 are formed there (W2 in
 // LDS, each dz1_j one FMA chain over i in order), so they never go through
 // memory.  dW2 is a product [H x chunk] x [chunk x H]: each thread keeps a
 // T x T tile of it in registers (T = 4 at H = 64), two 16-byte LDS reads per
 // sample for T^2 FMAs.  Every sum runs over the samples in order, so the
 // result does not depend on scheduling.
-constexpr int kRedChunk = 64;  // 1024 workgroups at a 65,536 batch (256-sample chunks: 1 per CU)
-constexpr int kRedSub = 32;
+constexpr int kRedChunk = 64;  // 1024 workgroups at a 65,536 batch
 template <int H>
 __global__ void __launch_bounds__(256) k_bwd_reduce(const float* __restrict__ th, const double* __restrict__ x,
                                                     int64_t B, const float* __restrict__ saved,
                                                     const float* __restrict__ gF, float* part) {
     constexpr int P = H * H + 4 * H + 1;
+    // samples staged at a time: 16 keeps the workgroup at 32 KB of LDS at
+    // H = 64, so that all 1024 workgroups of a 65,536 batch are resident at
+    // once (five per CU; 32 samples need 48 KB, three per CU, and a second
+    // round of workgroups)
+    constexpr int kRedSub = H >= 32 ? 16 : 32;
     constexpr int T = H >= 64 ? 4 : (H >= 32 ? 2 : 1);  // tile edge
     constexpr int NBK = H / T;                          // tiles per dimension (<= 16)
     static_assert(NBK * NBK <= 256, "one tile per thread");
@@ -652,14 +713,16 @@ __device__ __forceinline__ void adam_update(int64_t p, float gv, float* th, floa
     th[p] = th[p] - lr * mh / (sqrtf(vh) + eps);
 }
 
-// Column sums of `part` (rows x P), in a fixed order: 32 columns per block,
-// eight groups of rows summed side by side, then the eight group sums in order.
-// The result is valid in the threads of group 0 (column p).
+// Column sums of `part` (rows x P), in a fixed order: kSumCols columns per
+// block, eight groups of rows summed side by side, then the eight group sums
+// in order.  The result is valid in the threads of group 0 (column p).
+constexpr int kSumCols = 32;
+constexpr int kSumUnroll = 8;
 __device__ __forceinline__ float column_sum(const float* __restrict__ part, int rows, int P, int p, int c, int grp,
-                                            float (*s)[32]) {
+                                            float (*s)[kSumCols]) {
     float acc = 0.0f;
     if (p < P) {
-#pragma unroll 8
+#pragma unroll kSumUnroll
         for (int r = grp; r < rows; r += 8) acc += part[(int64_t)r * P + p];
     }
     s[grp][c] = acc;
@@ -672,41 +735,27 @@ __device__ __forceinline__ float column_sum(const float* __restrict__ part, int 
     return t;
 }
 
-__global__ void __launch_bounds__(256) k_sum_rows(const float* __restrict__ part, int rows, int P, float* out) {
-    __shared__ float s[8][32];
-    const int c = threadIdx.x & 31, grp = threadIdx.x >> 5;
-    const int p = blockIdx.x * 32 + c;
+__global__ void __launch_bounds__(8 * kSumCols) k_sum_rows(const float* __restrict__ part, int rows, int P,
+                                                           float* out) {
+    __shared__ float s[8][kSumCols];
+    const int c = threadIdx.x % kSumCols, grp = threadIdx.x / kSumCols;
+    const int p = blockIdx.x * kSumCols + c;
     const float t = column_sum(part, rows, P, p, c, grp, s);
     if (grp == 0 && p < P) out[p] = t;
 }
 
 // The fit's update: the same column sums, each fed straight into its
 // parameter's Adam step (the gradient never goes through memory).
-__global__ void __launch_bounds__(256) k_sum_rows_adam(const float* __restrict__ part, int rows, int P, float* th,
-                                                       float* m1, float* m2, float b1, float b2, float c1, float c2,
-                                                       float lr, float eps) {
-    __shared__ float s[8][32];
-    const int c = threadIdx.x & 31, grp = threadIdx.x >> 5;
-    const int p = blockIdx.x * 32 + c;
+__global__ void __launch_bounds__(8 * kSumCols) k_sum_rows_adam(const float* __restrict__ part, int rows, int P,
+                                                                float* th, float* m1, float* m2, float b1, float b2,
+                                                                float c1, float c2, float lr, float eps) {
+    __shared__ float s[8][kSumCols];
+    const int c = threadIdx.x % kSumCols, grp = threadIdx.x / kSumCols;
+    const int p = blockIdx.x * kSumCols + c;
     const float t = column_sum(part, rows, P, p, c, grp, s);
     if (grp == 0 && p < P) adam_update(p, t, th, m1, m2, b1, b2, c1, c2, lr, eps);
 }
 
-// Keep the parameters with the lowest batch loss seen so far (the loss of a
-// step is measured before that step's update).
-__global__ void __launch_bounds__(256) k_keep_best(const float* __restrict__ th, float* best, int P,
-                                                   const float* __restrict__ loss, float* best_loss) {
-    __shared__ int better;
-    if (threadIdx.x == 0) {
-        float l = loss[0];
-        better = l < best_loss[0] ? 1 : 0;
-    }
-    __syncthreads();
-    if (!better) return;
-    for (int p = threadIdx.x; p < P; p += blockDim.x) best[p] = th[p];
-    __syncthreads();
-    if (threadIdx.x == 0) best_loss[0] = loss[0];
-}
 
 // Disorder of a model over the sorted sample: sum_j max(0, F_j - F_{j+1}),
 // how far F moves backwards along keys that are in order (0 for a monotone
@@ -741,12 +790,6 @@ size_t disorder_ws_doubles() { return kDisorderBlocks + 1; }
 hipError_t launch_disorder(const float* d_F, int64_t k, double* d_ws, hipStream_t st) {
     hipLaunchKernelGGL(k_disorder_partial, dim3(kDisorderBlocks), dim3(256), 0, st, d_F, k, d_ws);
     hipLaunchKernelGGL(k_disorder_final, dim3(1), dim3(64), 0, st, d_ws, kDisorderBlocks, d_ws + kDisorderBlocks);
-    return hipGetLastError();
-}
-
-hipError_t launch_keep_best(const float* d_theta, float* d_best, int P, const float* d_loss, float* d_best_loss,
-                            hipStream_t st) {
-    hipLaunchKernelGGL(k_keep_best, dim3(1), dim3(256), 0, st, d_theta, d_best, P, d_loss, d_best_loss);
     return hipGetLastError();
 }
 
@@ -794,12 +837,6 @@ hipError_t launch_init(float* d_theta, int H, int init, uint64_t seed, const dou
     return hipGetLastError();
 }
 
-hipError_t launch_batch(const double* d_x, const float* d_y, int64_t k, uint64_t seed, int64_t step, int64_t B,
-                        double* d_bx, float* d_by, hipStream_t st) {
-    hipLaunchKernelGGL(k_batch, dim3(nblk(B, 256)), dim3(256), 0, st, d_x, d_y, k, seed, step, B, d_bx, d_by);
-    return hipGetLastError();
-}
-
 template <int H>
 static hipError_t fwd_h(const float* th, const double* x, int64_t B, float* F, float* saved, hipStream_t st) {
     hipLaunchKernelGGL(k_fwd<H>, dim3(nblk(B, 256)), dim3(256), 0, st, th, x, B, F, saved);
@@ -809,7 +846,44 @@ static hipError_t fwd_h(const float* th, const double* x, int64_t B, float* F, f
 // The fit's forward: k_fwd_fit, the same results as launch_mlp_forward.
 template <int H>
 static hipError_t fwd_fit_h(const float* th, const double* x, int64_t B, float* F, float* saved, hipStream_t st) {
-    hipLaunchKernelGGL(k_fwd_fit<H>, dim3(nblk(B, 64)), dim3(256), 0, st, th, x, B, F, saved);
+    hipLaunchKernelGGL((k_fwd_fit<H, false>), dim3(nblk(B, 64)), dim3(256), 0, st, th, x, B, F, saved,
+                       FitBatch{});
+    return hipGetLastError();
+}
+
+template <int H>
+static hipError_t fwd_step_h(const float* th, const double* x, int64_t B, float* saved, const FitBatch& fb,
+                             hipStream_t st) {
+    hipLaunchKernelGGL((k_fwd_fit<H, true>), dim3(nblk(B, 64)), dim3(256), 0, st, th, x, B, nullptr, saved, fb);
+    return hipGetLastError();
+}
+
+size_t fit_loss_ws_floats(int64_t B) {
+    const int64_t nb = (B + 63) / 64;
+    return (size_t)(nb > kLossBlocks ? nb : kLossBlocks);
+}
+
+// One training step's batch, forward and loss: the batch drawn from the
+// sample (x, y of k entries) with replacement, h1 and h2 saved for
+// the backward, dL/dF into gF, the batch loss into loss_out; the parameters
+// are copied to `best` when that loss is the lowest so far.  partial holds
+// fit_loss_ws_floats(B) floats.
+hipError_t launch_fit_step_forward(int H, const float* d_theta, const double* d_x, const float* d_y, int64_t k,
+                                   uint64_t seed, int64_t step, int64_t B, double* d_bx, float* d_saved, int loss,
+                                   float delta, float* d_gF, float* d_loss, float* d_partial, float* d_best, int P,
+                                   float* d_best_loss, hipStream_t st) {
+    const FitBatch fb{d_y, k, seed, step, d_bx, loss, delta, d_gF, d_partial};
+    hipError_t e;
+    switch (H) {
+    case 8: e = fwd_step_h<8>(d_theta, d_x, B, d_saved, fb, st); break;
+    case 16: e = fwd_step_h<16>(d_theta, d_x, B, d_saved, fb, st); break;
+    case 32: e = fwd_step_h<32>(d_theta, d_x, B, d_saved, fb, st); break;
+    case 64: e = fwd_step_h<64>(d_theta, d_x, B, d_saved, fb, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_loss_final_keep, dim3(1), dim3(kLossBlocks), 0, st, d_partial, (int)nblk(B, 64), B, d_loss,
+                       d_theta, d_best, P, d_best_loss);
     return hipGetLastError();
 }
 
@@ -856,10 +930,12 @@ static hipError_t bwd_h(const float* th, const double* x, int64_t B, const float
     int rows = (int)((B + kRedChunk - 1) / kRedChunk);
     hipLaunchKernelGGL(k_bwd_reduce<H>, dim3(rows), dim3(256), 0, st, th, x, B, saved, gF, part);
     if (adam)
-        hipLaunchKernelGGL(k_sum_rows_adam, dim3((P + 31) / 32), dim3(256), 0, st, part, rows, P, th_update,
+        hipLaunchKernelGGL(k_sum_rows_adam, dim3((P + kSumCols - 1) / kSumCols), dim3(8 * kSumCols), 0, st, part,
+                           rows, P, th_update,
                            adam->m1, adam->m2, adam->b1, adam->b2, adam->c1, adam->c2, adam->lr, adam->eps);
     else
-        hipLaunchKernelGGL(k_sum_rows, dim3((P + 31) / 32), dim3(256), 0, st, part, rows, P, gtheta);
+        hipLaunchKernelGGL(k_sum_rows, dim3((P + kSumCols - 1) / kSumCols), dim3(8 * kSumCols), 0, st, part, rows,
+                           P, gtheta);
     return hipGetLastError();
 }
 
@@ -896,17 +972,6 @@ hipError_t launch_loss_grad(const float* d_F, const float* d_y, int64_t B, int l
                             float* d_loss, float* d_partial, hipStream_t st) {
     hipLaunchKernelGGL(k_loss, dim3(kLossBlocks), dim3(256), 0, st, d_F, d_y, B, loss, delta, d_gF, d_partial);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kLossBlocks), 0, st, d_partial, kLossBlocks, B, d_loss);
-    return hipGetLastError();
-}
-
-// The fit's loss: as launch_loss_grad, with the keep-best step folded into
-// the final sum.
-hipError_t launch_loss_grad_keep(const float* d_F, const float* d_y, int64_t B, int loss, float delta, float* d_gF,
-                                 float* d_loss, float* d_partial, const float* d_theta, float* d_best, int P,
-                                 float* d_best_loss, hipStream_t st) {
-    hipLaunchKernelGGL(k_loss, dim3(kLossBlocks), dim3(256), 0, st, d_F, d_y, B, loss, delta, d_gF, d_partial);
-    hipLaunchKernelGGL(k_loss_final_keep, dim3(1), dim3(kLossBlocks), 0, st, d_partial, kLossBlocks, B, d_loss,
-                       d_theta, d_best, P, d_best_loss);
     return hipGetLastError();
 }
 
