@@ -278,6 +278,8 @@ def main():
         xs = x[:m]
         mdict = nn.model_to_dict(model)
         formc = {"bf16": oracle.FORM_BF16W, "fp32": oracle.FORM_FP32C, "pwl": oracle.FORM_FP64}[form]
+        evaluator = {"bf16": "FP64 evaluator with W2 rounded to bf16", "fp32": "canonical FP32 evaluator",
+                     "pwl": "FP64 evaluator"}[form]
         t0 = time.perf_counter()
         oracle.nnsort(xs, mdict, form=formc)
         cpu_s = time.perf_counter() - t0
@@ -300,8 +302,7 @@ def main():
         except (OSError, StopIteration):
             context["host_cpu"] = None
         cpu = {"value": round(m / cpu_s / 1e9, 6), "unit": "Gkeys/s", "cores": cores, "kind": "oracle",
-               "sample": f"first {m} keys of the same workload, same model, FP64 bf16-W2 evaluator; "
-                         f"{cpu_s:.1f} s"}
+               "sample": f"first {m} keys of the same workload, same model, {evaluator}; {cpu_s:.1f} s"}
 
     res = {
         "metric": "sorted Gkeys/s at 1e8 f64 keys, BF16-MFMA vs FP32 NN-sort; % HBM roofline",
