@@ -3,14 +3,16 @@
 Workload (default): 1e8 float64 keys from a skewed mixture of 8 Gaussians
 (weights Dirichlet(0.3), means U[-1e6, 1e6], sigma log-uniform in [1, 1e4])
 with 1% duplicated keys; model 1 -> 64 -> 64 -> 1 fitted on the device from a
-1% sample (200 Adam steps, done once before timing, as the paper excludes
-training from the sort time); inference in the BF16 form (hidden layer on
-bf16 matrix cores, FP32 accumulation).  A step is one full sort of the
-resident keys: map, rounds, polish, residue sort and merge.
+1% sample (200 Adam steps) before timing, as the paper excludes training from
+the sort time (the first fit call and a second, steady-state one are timed
+and reported); inference in the BF16 form (hidden layer on bf16 matrix cores,
+FP32 accumulation).  A step is one full sort of the resident keys: map,
+rounds, polish, residue sort and merge.
 
-Beside the headline it reports the FP32 form on the same weights, a full-n
-GPU radix sort, the fit time, and the CPU oracle on a bounded sample of the
-same workload.  Prints one JSON line.
+Beside the headline it reports the FP32 and piecewise-linear forms on the same
+weights, a full-n GPU radix sort, the fit time, the CPU oracle on a bounded
+sample of the same workload, and 1-thread and multi-threaded host sorts of
+that sample.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -141,12 +143,17 @@ def main():
     fp = nn.fit_params(hidden=H, sample_frac=frac)
     ws = nn.alloc_workspace(nn.workspace_size(n, dt, sp, fp), dev)
 
-    # device fit (once; excluded from the sort time, reported separately)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    model = nn.nnsort_fit(keys, fp, ws=ws)
-    torch.cuda.synchronize()
-    fit_ms = (time.perf_counter() - t0) * 1e3
+    # device fit, excluded from the sort time and reported separately: the
+    # first call in the process (which also loads the fit's kernels) and a
+    # second one, the steady-state time that value_with_fit uses
+    fit_calls_ms = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        model = nn.nnsort_fit(keys, fp, ws=ws)
+        torch.cuda.synchronize()
+        fit_calls_ms.append((time.perf_counter() - t0) * 1e3)
+    fit_first_ms, fit_ms = fit_calls_ms
 
     def run_sort(params):
         return nn.nnsort_sort_with_model(model, keys, out=out, sp=params, ws=ws)
@@ -326,6 +333,7 @@ def main():
         "cpu_baseline": cpu,
         "sorted_ok": sorted_ok,
         "fit_ms": round(fit_ms, 2),
+        "fit_first_call_ms": round(fit_first_ms, 2),
         "value_with_fit": round(n / ((ms_per_step + fit_ms) * 1e-3) / 1e9, 4),
         "e2e_hbm": e2e,
         "rounds": stats["rounds"],

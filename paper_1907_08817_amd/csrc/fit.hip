@@ -171,20 +171,28 @@ __global__ void __launch_bounds__(kKnotThreads) k_knot_scan(const double* __rest
 }
 
 // Apply the scan's result (the first piece, or the split of the chosen one)
-// and choose the next piece to split.
+// and choose the next piece to split: the valid piece (a split point, a
+// positive deviation) of largest deviation, ties to the leftmost start.  Piece
+// starts are distinct, so that order is strict and a butterfly over one wave
+// finds the same piece as a scan in index order.
 __global__ void __launch_bounds__(kKnotBlocks) k_knot_update(int64_t k, int H, KnotWork* w) {
     static_assert(kKnotBlocks == kKnotThreads, "one thread per scan block");
+    static_assert(NNSORT_MAX_HIDDEN <= 64, "one lane per piece");
     __shared__ double s_d[kKnotThreads];
     __shared__ int64_t s_j[kKnotThreads];
     __shared__ double r_d[2];
     __shared__ int64_t r_j[2];
+    __shared__ int64_t c_a[NNSORT_MAX_HIDDEN], c_j[NNSORT_MAX_HIDDEN];
+    __shared__ double c_d[NNSORT_MAX_HIDDEN];
+    __shared__ int s_np;
     if (w->done) return;
+    const int t = threadIdx.x;
     for (int r = 0; r < 2; ++r) {
-        s_d[threadIdx.x] = w->part_d[r][threadIdx.x];
-        s_j[threadIdx.x] = w->part_j[r][threadIdx.x];
+        s_d[t] = w->part_d[r][t];
+        s_j[t] = w->part_j[r][t];
         __syncthreads();
         arg_max_reduce(s_d, s_j);
-        if (threadIdx.x == 0) {
+        if (t == 0) {
             double d = s_d[0];
             int64_t j = s_j[0];
             if (!(d > 1.0 / (double)k)) {  // within one rank step of linear: final
@@ -196,41 +204,67 @@ __global__ void __launch_bounds__(kKnotBlocks) k_knot_update(int64_t k, int H, K
         }
         __syncthreads();
     }
-    if (threadIdx.x != 0) return;
-    int np = w->np;
-    if (np == 0) {
-        w->pa[0] = 0;
-        w->pb[0] = k - 1;
-        w->pd[0] = r_d[0];
-        w->pj[0] = r_j[0];
-        np = 1;
-    } else {
-        const int bst = w->best;
-        const int64_t b = w->pb[bst], sj = w->pj[bst];
-        w->pb[bst] = sj;
-        w->pd[bst] = r_d[0];
-        w->pj[bst] = r_j[0];
-        w->pa[np] = sj;
-        w->pb[np] = b;
-        w->pd[np] = r_d[1];
-        w->pj[np] = r_j[1];
-        ++np;
+    const int np0 = w->np;
+    if (t < np0) {
+        c_a[t] = w->pa[t];
+        c_j[t] = w->pj[t];
+        c_d[t] = w->pd[t];
     }
-    w->np = np;
-    int best = -1;
-    if (np < H) {
-        for (int i = 0; i < np; ++i) {
-            if (w->pj[i] < 0 || !(w->pd[i] > 0.0)) continue;
-            if (best < 0 || w->pd[i] > w->pd[best] || (w->pd[i] == w->pd[best] && w->pa[i] < w->pa[best])) best = i;
+    __syncthreads();
+    if (t == 0) {
+        int np = np0;
+        if (np == 0) {
+            w->pa[0] = 0;
+            w->pb[0] = k - 1;
+            c_a[0] = 0;
+            np = 1;
+        } else {
+            const int bst = w->best;
+            const int64_t b = w->pb[bst], sj = c_j[bst];
+            w->pb[bst] = sj;
+            w->pa[np] = sj;
+            w->pb[np] = b;
+            c_a[np] = sj;
+            c_d[bst] = r_d[0];
+            c_j[bst] = r_j[0];
+            w->pd[bst] = r_d[0];
+            w->pj[bst] = r_j[0];
+            ++np;
+        }
+        const int nw = np - 1;  // the new piece (or the first one)
+        c_d[nw] = r_d[np0 == 0 ? 0 : 1];
+        c_j[nw] = r_j[np0 == 0 ? 0 : 1];
+        w->pd[nw] = c_d[nw];
+        w->pj[nw] = c_j[nw];
+        w->np = np;
+        s_np = np;
+    }
+    __syncthreads();
+    if (t >= 64) return;
+    const int np = s_np;
+    bool ok = np < H && t < np && c_j[t] >= 0 && c_d[t] > 0.0;
+    double d = ok ? c_d[t] : 0.0;
+    int64_t a = ok ? c_a[t] : 0;
+    int best = ok ? t : -1;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double d2 = __shfl_xor(d, off);
+        const int64_t a2 = __shfl_xor(a, off);
+        const int b2 = __shfl_xor(best, off);
+        if (b2 >= 0 && (best < 0 || d2 > d || (d2 == d && a2 < a))) {
+            d = d2;
+            a = a2;
+            best = b2;
         }
     }
+    if (t != 0) return;
     w->best = best;
     if (best < 0) {
         w->done = 1;
     } else {
-        w->ra[0] = w->pa[best];
-        w->rb[0] = w->pj[best];
-        w->ra[1] = w->pj[best];
+        w->ra[0] = c_a[best];
+        w->rb[0] = c_j[best];
+        w->ra[1] = c_j[best];
         w->rb[1] = w->pb[best];
     }
 }
