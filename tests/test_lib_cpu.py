@@ -137,3 +137,21 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=60)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+@pytest.mark.parametrize("dtype", ["f64", "u64"])
+def test_bench_host_parallel_sort_matches_numpy(dtype):
+    """The benchmark's multi-threaded host sort (a context figure) returns
+    numpy's sorted order, duplicates and ragged bucket sizes included."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    rng = np.random.default_rng(7)
+    if dtype == "f64":
+        x = np.concatenate([rng.lognormal(0.0, 2.0, 200_003), np.full(5000, 3.25), rng.random(1001)])
+    else:
+        x = np.concatenate([rng.zipf(1.3, 200_003).astype(np.uint64), np.arange(999, dtype=np.uint64)])
+    rng.shuffle(x)
+    for threads in (1, 3, 8):
+        assert np.array_equal(bench.host_parallel_sort(x, threads), np.sort(x))
