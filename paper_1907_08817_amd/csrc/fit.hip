@@ -393,12 +393,6 @@ __global__ void __launch_bounds__(256) k_fwd(const float* __restrict__ th, const
     F[b] = p + s;
 }
 
-// The same forward pass for the fit, spread over four waves per 64 samples:
-// wave q computes hidden-2 units [q H/4, (q+1) H/4) of its samples (lane =
-// sample), each z2_i the same FMA chain over j in order as above; the
-// activations meet in LDS and the compensated layer-3 sum runs over i in
-// order as above.  h1, h2 and F are therefore the same bit for bit, with four
-// times as many waves to cover latency.
 // One training step's batch, drawn and scored inside the fit's forward.
 struct FitBatch {
     const float* y;   // labels of the sample
@@ -427,6 +421,13 @@ __device__ __forceinline__ float loss_term(float e, int loss, float delta, float
     return e * e;
 }
 
+// The same forward pass for the fit, spread over four waves per 64 samples:
+// wave q computes hidden-2 units [q H/4, (q+1) H/4) of its samples (lane =
+// sample), each z2_i the same FMA chain over j in order as above; the
+// activations meet in LDS and the compensated layer-3 sum runs over i in
+// order as above.  h1, h2 and F are therefore the same bit for bit, with four
+// times as many waves to cover latency.
+//
 // STEP = false: F of x[0..B).  STEP = true: x is the fit sample and entry b of
 // the batch is x[idx], idx = Philox(step, b) mod k (stream kStreamBatch); the
 // kernel then also writes bx, and in place of F the loss terms: dL/dF and one
