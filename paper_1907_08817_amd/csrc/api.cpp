@@ -83,10 +83,8 @@ hipError_t launch_fit_step_forward(int H, const float* d_theta, const double* d_
 hipError_t launch_mlp_backward_adam(int H, float* d_theta, const double* d_x, int64_t B, const float* d_saved,
                                     const float* d_gF, float* d_ws, float* d_m1, float* d_m2, int64_t t, float lr,
                                     float b1, float b2, float eps, hipStream_t st);
-hipError_t launch_mlp_forward_fit(int H, const float* d_theta, const double* d_x, int64_t B, float* d_F,
-                                  float* d_saved, hipStream_t st);
 size_t disorder_ws_doubles();
-hipError_t launch_disorder(const float* d_F, int64_t k, double* d_ws, hipStream_t st);
+hipError_t launch_disorder(const double* d_F, int64_t k, double* d_ws, hipStream_t st);
 }  // namespace nns
 
 using namespace nns;
@@ -477,7 +475,7 @@ struct FitPlan {
     int64_t k, B;
     int H;
     size_t off_init, off_Fs, off_dis, off_best, off_knots, off_knotws, off_sample, off_count, off_x, off_y, off_bx, off_gF, off_saved, off_bws, off_theta,
-        off_m1, off_m2, off_loss, off_lpart, off_radix, total;
+        off_m1, off_m2, off_loss, off_lpart, off_radix, off_model, total;
 };
 
 int64_t sample_count(int64_t n, double frac) {
@@ -514,7 +512,8 @@ FitPlan plan_fit(int64_t n, const nnsort_fit_params* fp) {
     p.off_knotws = take(knot_ws_bytes());
     p.off_best = take((size_t)(P + 64) * 4);
     p.off_init = take((size_t)P * 4);
-    p.off_Fs = take((size_t)p.k * 4);
+    p.off_Fs = take((size_t)p.k * 8);
+    p.off_model = take(model_region_bytes());
     p.off_dis = take(disorder_ws_doubles() * 2 * 8);
     p.off_radix = take(radix_ws_bytes(p.k));
     p.total = o;
@@ -538,7 +537,7 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
     if (dtype != NNSORT_F64 && dtype != NNSORT_U64) return NNSORT_EINVAL;
     if (n >= (int64_t)0xFFFFFFFF) return NNSORT_EINVAL;
     FitPlan P = plan_fit(n, fp);
-    if (!d_ws || ws_bytes < P.total) return NNSORT_EWORKSPACE;
+    if (!d_ws || ws_bytes < P.total || ((uintptr_t)d_ws & 255u)) return NNSORT_EWORKSPACE;
     const bool is_f64 = dtype == NNSORT_F64;
     char* ws = (char*)d_ws;
     uint64_t* sample = (uint64_t*)(ws + P.off_sample);
@@ -561,7 +560,8 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
     float* best = (float*)(ws + P.off_best);
     float* best_loss = best + Pn;
     float* init_theta = (float*)(ws + P.off_init);
-    float* Fs = (float*)(ws + P.off_Fs);
+    double* Fs = (double*)(ws + P.off_Fs);
+    DevModel* dmodel = (DevModel*)(ws + P.off_model);
     double* dis = (double*)(ws + P.off_dis);
 
     NNS_HIP(fill_u64(count, 1, 0, st));
@@ -610,34 +610,54 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
     }
     // Returned: the parameters with the lowest batch loss seen, unless they
     // move F backwards along the sorted sample more than the initial ones do
-    // (a model that is less monotone only adds work to the polish).
-    const float* chosen = best;
-    if (fp->steps > 0) {
+    // (a model that is less monotone only adds work to the polish).  F is the
+    // FP64 model's, through its piecewise-linear form, on the sample's
+    // translated keys (already in [0, 1], so lo = 0 and inv_range = 1).
+    std::vector<float> cand((size_t)2 * Pn);
+    NNS_HIP(hipMemcpyAsync(cand.data(), best, (size_t)Pn * 4, hipMemcpyDeviceToHost, st));
+    NNS_HIP(hipMemcpyAsync(cand.data() + Pn, init_theta, (size_t)Pn * 4, hipMemcpyDeviceToHost, st));
+    NNS_HIP(hipStreamSynchronize(st));
+    auto model_of = [&](const float* th, double lo_, double inv_) {
+        nnsort_model m = M;
+        m.lo = lo_;
+        m.inv_range = inv_;
+        for (int j = 0; j < H; ++j) {
+            m.w1[j] = th[j];
+            m.b1[j] = th[H + j];
+            m.b2[j] = th[2 * H + H * H + j];
+            m.w3[j] = th[3 * H + H * H + j];
+        }
+        for (int e = 0; e < H * H; ++e) m.w2[e] = th[2 * H + e];
+        m.b3 = th[4 * H + H * H];
+        return m;
+    };
+    int pick = 0;  // the best-loss parameters
+    if (fp->steps > 0 && k2 > 1) {
         const size_t dw = disorder_ws_doubles();
-        NNS_HIP(launch_mlp_forward_fit(H, init_theta, x, (int64_t)k2, Fs, nullptr, st));
-        NNS_HIP(launch_disorder(Fs, (int64_t)k2, dis, st));
-        NNS_HIP(launch_mlp_forward_fit(H, best, x, (int64_t)k2, Fs, nullptr, st));
-        NNS_HIP(launch_disorder(Fs, (int64_t)k2, dis + dw, st));
+        DevModel hm[2];  // host sources stay alive until the stream is synchronised
+        for (int c = 0; c < 2; ++c) {
+            const nnsort_model mc = model_of(cand.data() + (size_t)c * Pn, 0.0, 1.0);
+            to_dev_model(&mc, &hm[c]);
+            NNS_HIP(hipMemcpyAsync(dmodel, &hm[c], sizeof(DevModel), hipMemcpyHostToDevice, st));
+            InferArgs ia{};
+            ia.model = dmodel;
+            ia.pwl = pwl_table_of(dmodel);
+            ia.in = (const uint64_t*)x;
+            ia.n = (int64_t)k2;
+            ia.is_f64 = 1;
+            ia.M = 1.0;
+            ia.S = 2;
+            ia.F_out = Fs;
+            NNS_HIP(launch_infer(ia, hm[c].H, NNSORT_FORM_PWL, 3, st));
+            NNS_HIP(launch_disorder(Fs, (int64_t)k2, dis + c * dw, st));
+        }
         double d[2];
         NNS_HIP(hipMemcpyAsync(&d[0], dis + dw - 1, 8, hipMemcpyDeviceToHost, st));
         NNS_HIP(hipMemcpyAsync(&d[1], dis + 2 * dw - 1, 8, hipMemcpyDeviceToHost, st));
         NNS_HIP(hipStreamSynchronize(st));
-        if (d[1] > d[0]) chosen = init_theta;
+        if (d[0] > d[1]) pick = 1;
     }
-    std::vector<float> th((size_t)Pn);
-    NNS_HIP(hipMemcpyAsync(th.data(), chosen, (size_t)Pn * 4, hipMemcpyDeviceToHost, st));
-    NNS_HIP(hipStreamSynchronize(st));
-    M.lo = lo;
-    M.inv_range = inv;
-    for (int j = 0; j < H; ++j) {
-        M.w1[j] = th[j];
-        M.b1[j] = th[H + j];
-        M.b2[j] = th[2 * H + H * H + j];
-        M.w3[j] = th[3 * H + H * H + j];
-    }
-    for (int e = 0; e < H * H; ++e) M.w2[e] = th[2 * H + e];
-    M.b3 = th[4 * H + H * H];
-    *out = M;
+    *out = model_of(cand.data() + (size_t)pick * Pn, lo, inv);
     return NNSORT_OK;
 }
 

@@ -428,14 +428,13 @@ __device__ __forceinline__ float loss_term(float e, int loss, float delta, float
 // order as above.  h1, h2 and F are therefore the same bit for bit, with four
 // times as many waves to cover latency.
 //
-// STEP = false: F of x[0..B).  STEP = true: x is the fit sample and entry b of
-// the batch is x[idx], idx = Philox(step, b) mod k (stream kStreamBatch); the
-// kernel then also writes bx, and in place of F the loss terms: dL/dF and one
-// partial loss sum per 64 entries (a butterfly over the wave, so the order is
-// fixed).
-template <int H, bool STEP>
+// x is the fit sample and entry b of the batch is x[idx], idx = Philox(step,
+// b) mod k (stream kStreamBatch); the kernel also writes bx, and in place of F
+// the loss terms: dL/dF and one partial loss sum per 64 entries (a butterfly
+// over the wave, so the order is fixed).
+template <int H>
 __global__ void __launch_bounds__(256) k_fwd_fit(const float* __restrict__ th, const double* __restrict__ x,
-                                                 int64_t B, float* F, float* saved, FitBatch fb) {
+                                                 int64_t B, float* saved, FitBatch fb) {
     constexpr int Q = H / 4;  // hidden-2 units per wave
     __shared__ float s_h2[64][H + 1];
     // the wave index, known wave-uniform so that W2 is read by scalar loads
@@ -447,26 +446,21 @@ __global__ void __launch_bounds__(256) k_fwd_fit(const float* __restrict__ th, c
     const float* W2 = th + 2 * H;
     const float* b2 = th + 2 * H + H * H;
     const float* w3 = th + 3 * H + H * H;
-    double xv;
+    // wave 0 draws the entries and hands the inputs to the other waves
+    __shared__ double s_x[64];
     float yv = 0.0f;
-    if constexpr (STEP) {
-        // wave 0 draws the entries and hands the inputs to the other waves
-        __shared__ double s_x[64];
-        if (q == 0) {
-            double v = 0.0;
-            if (ok) {
-                const uint64_t j = rand64(fb.seed, kStreamBatch, (uint64_t)b, (uint32_t)fb.step) % (uint64_t)fb.k;
-                v = x[j];
-                yv = fb.y[j];
-                fb.bx[b] = v;
-            }
-            s_x[lane] = v;
+    if (q == 0) {
+        double v = 0.0;
+        if (ok) {
+            const uint64_t j = rand64(fb.seed, kStreamBatch, (uint64_t)b, (uint32_t)fb.step) % (uint64_t)fb.k;
+            v = x[j];
+            yv = fb.y[j];
+            fb.bx[b] = v;
         }
-        __syncthreads();
-        xv = s_x[lane];
-    } else {
-        xv = ok ? x[b] : 0.0;
+        s_x[lane] = v;
     }
+    __syncthreads();
+    const double xv = s_x[lane];
     const float xh = (float)xv;
     const float xl = (float)(xv - (double)xh);
     float h1[H];
@@ -510,19 +504,15 @@ __global__ void __launch_bounds__(256) k_fwd_fit(const float* __restrict__ th, c
         s = s + (e + r);
     }
     const float Fb = p + s;
-    if constexpr (STEP) {
-        float l = 0.0f;
-        if (ok) {
-            float g;
-            l = loss_term(Fb - yv, fb.loss, fb.delta, g);
-            fb.gF[b] = g * (1.0f / (float)B);
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
-        if (lane == 0) fb.partial[blockIdx.x] = l;
-    } else if (ok) {
-        F[b] = Fb;
+    float l = 0.0f;
+    if (ok) {
+        float g;
+        l = loss_term(Fb - yv, fb.loss, fb.delta, g);
+        fb.gF[b] = g * (1.0f / (float)B);
     }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
+    if (lane == 0) fb.partial[blockIdx.x] = l;
 }
 
 // ---- loss and dL/dF ----
@@ -795,12 +785,12 @@ __global__ void __launch_bounds__(8 * kSumCols) k_sum_rows_adam(const float* __r
 // Disorder of a model over the sorted sample: sum_j max(0, F_j - F_{j+1}),
 // how far F moves backwards along keys that are in order (0 for a monotone
 // model).  Partial sums per block (fixed order), then one block adds them.
-__global__ void __launch_bounds__(256) k_disorder_partial(const float* __restrict__ F, int64_t k, double* part) {
+__global__ void __launch_bounds__(256) k_disorder_partial(const double* __restrict__ F, int64_t k, double* part) {
     __shared__ double s[256];
     double acc = 0.0;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j + 1 < k; j += (int64_t)gridDim.x * blockDim.x) {
-        float d = F[j] - F[j + 1];
-        acc += d > 0.0f ? (double)d : 0.0;
+        const double d = F[j] - F[j + 1];
+        acc += d > 0.0 ? d : 0.0;
     }
     s[threadIdx.x] = acc;
     __syncthreads();
@@ -822,7 +812,7 @@ __global__ void k_disorder_final(const double* __restrict__ part, int nb, double
 constexpr int kDisorderBlocks = 512;
 size_t disorder_ws_doubles() { return kDisorderBlocks + 1; }
 
-hipError_t launch_disorder(const float* d_F, int64_t k, double* d_ws, hipStream_t st) {
+hipError_t launch_disorder(const double* d_F, int64_t k, double* d_ws, hipStream_t st) {
     hipLaunchKernelGGL(k_disorder_partial, dim3(kDisorderBlocks), dim3(256), 0, st, d_F, k, d_ws);
     hipLaunchKernelGGL(k_disorder_final, dim3(1), dim3(64), 0, st, d_ws, kDisorderBlocks, d_ws + kDisorderBlocks);
     return hipGetLastError();
@@ -878,18 +868,10 @@ static hipError_t fwd_h(const float* th, const double* x, int64_t B, float* F, f
     return hipGetLastError();
 }
 
-// The fit's forward: k_fwd_fit, the same results as launch_mlp_forward.
-template <int H>
-static hipError_t fwd_fit_h(const float* th, const double* x, int64_t B, float* F, float* saved, hipStream_t st) {
-    hipLaunchKernelGGL((k_fwd_fit<H, false>), dim3(nblk(B, 64)), dim3(256), 0, st, th, x, B, F, saved,
-                       FitBatch{});
-    return hipGetLastError();
-}
-
 template <int H>
 static hipError_t fwd_step_h(const float* th, const double* x, int64_t B, float* saved, const FitBatch& fb,
                              hipStream_t st) {
-    hipLaunchKernelGGL((k_fwd_fit<H, true>), dim3(nblk(B, 64)), dim3(256), 0, st, th, x, B, nullptr, saved, fb);
+    hipLaunchKernelGGL(k_fwd_fit<H>, dim3(nblk(B, 64)), dim3(256), 0, st, th, x, B, saved, fb);
     return hipGetLastError();
 }
 
@@ -920,17 +902,6 @@ hipError_t launch_fit_step_forward(int H, const float* d_theta, const double* d_
     hipLaunchKernelGGL(k_loss_final_keep, dim3(1), dim3(kLossBlocks), 0, st, d_partial, (int)nblk(B, 64), B, d_loss,
                        d_theta, d_best, P, d_best_loss);
     return hipGetLastError();
-}
-
-hipError_t launch_mlp_forward_fit(int H, const float* d_theta, const double* d_x, int64_t B, float* d_F,
-                                  float* d_saved, hipStream_t st) {
-    switch (H) {
-    case 8: return fwd_fit_h<8>(d_theta, d_x, B, d_F, d_saved, st);
-    case 16: return fwd_fit_h<16>(d_theta, d_x, B, d_F, d_saved, st);
-    case 32: return fwd_fit_h<32>(d_theta, d_x, B, d_F, d_saved, st);
-    case 64: return fwd_fit_h<64>(d_theta, d_x, B, d_F, d_saved, st);
-    default: return hipErrorInvalidValue;
-    }
 }
 
 hipError_t launch_mlp_forward(int H, const float* d_theta, const double* d_x, int64_t B, float* d_F,

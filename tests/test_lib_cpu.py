@@ -92,9 +92,15 @@ def test_argument_checks_before_device_work():
     assert L.nnsort_predict(ctypes.byref(m64), p, 10, 0, ctypes.byref(sp), None, None, ctypes.c_void_p(0x900008),
                             L.nnsort_model_device_bytes(), None) == -2
     assert "aligned" in L.nnsort_strerror(-2).decode()
-    # fit: bad hidden width
+    # fit: bad hidden width; workspace too small or not 256-byte aligned
     bad = nn.fit_params(hidden=5)
     assert L.nnsort_fit(p, 10, 0, ctypes.byref(bad), ctypes.byref(m), q, 1 << 20, None) == -1
+    good = nn.fit_params(hidden=16)
+    need = ctypes.c_size_t()
+    assert L.nnsort_workspace_size(5000, 0, ctypes.byref(sp), ctypes.byref(good), ctypes.byref(need)) == 0
+    assert L.nnsort_fit(p, 5000, 0, ctypes.byref(good), ctypes.byref(m), q, 64, None) == -2
+    assert L.nnsort_fit(p, 5000, 0, ctypes.byref(good), ctypes.byref(m), ctypes.c_void_p(0x900008), need.value,
+                        None) == -2
     assert L.nnsort_radix_sort(p, q, -1, 0, None, 0, None) == -1
     assert L.nnsort_mlp_forward(24, p, p, 4, p, None, None) == -1
     assert L.nnsort_adam_step(p, p, p, p, 4, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -1
