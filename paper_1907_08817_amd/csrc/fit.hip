@@ -40,28 +40,48 @@ __device__ __forceinline__ uint64_t rand64(uint64_t seed, uint32_t stream, uint6
 constexpr uint32_t kStreamSample = 1, kStreamInit = 2, kStreamBatch = 3;
 
 // Sample k keys with replacement; keep the finite ones (order keys) in G.
+// Each workgroup draws kSampleItems x 256 keys and reserves their place in G
+// with one atomic; the order of G is arbitrary (it is sorted next).
+constexpr int kSampleItems = 8;
 __global__ void __launch_bounds__(256) k_sample(const uint64_t* __restrict__ in, int64_t n, int is_f64,
                                                 uint64_t seed, int64_t k, uint64_t* out,
                                                 unsigned long long* count) {
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < k; base += stride) {
-        int64_t j = base + threadIdx.x;
-        bool ok = false;
-        uint64_t okey = 0;
-        if (j < k) {
-            uint64_t r = rand64(seed, kStreamSample, (uint64_t)j, 0);
-            uint64_t bits = in[r % (uint64_t)n];
-            ok = !is_f64 || (bits & 0x7FF0000000000000ull) != 0x7FF0000000000000ull;
-            okey = order_key(bits, is_f64);
+    __shared__ uint32_t s_w[4];
+    __shared__ unsigned long long s_base;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t per_block = 256 * kSampleItems;
+    for (int64_t base = (int64_t)blockIdx.x * per_block; base < k; base += (int64_t)gridDim.x * per_block) {
+        uint64_t okey[kSampleItems];
+        uint32_t okm = 0;
+#pragma unroll
+        for (int q = 0; q < kSampleItems; ++q) {
+            const int64_t j = base + q * 256 + tid;
+            okey[q] = 0;
+            if (j < k) {
+                const uint64_t r = rand64(seed, kStreamSample, (uint64_t)j, 0);
+                const uint64_t bits = in[r % (uint64_t)n];
+                const bool ok = !is_f64 || (bits & 0x7FF0000000000000ull) != 0x7FF0000000000000ull;
+                okey[q] = order_key(bits, is_f64);
+                okm |= ok ? 1u << q : 0u;
+            }
         }
-        unsigned long long mask = __ballot(ok);
-        if (mask) {
-            int leader = __ffsll((long long)mask) - 1;
-            unsigned long long b0 = 0;
-            if ((int)__lane_id() == leader) b0 = atomicAdd(count, (unsigned long long)__popcll(mask));
-            b0 = __shfl(b0, leader);
-            if (ok) out[b0 + __popcll(mask & ((1ull << __lane_id()) - 1ull))] = okey;
+        const uint32_t c = (uint32_t)__popc(okm);
+        uint32_t inc = c;  // inclusive prefix over the wave
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o);
+            if (lane >= o) inc += y;
         }
+        if (lane == 63) s_w[wv] = inc;
+        __syncthreads();
+        if (tid == 0) s_base = atomicAdd(count, (unsigned long long)(s_w[0] + s_w[1] + s_w[2] + s_w[3]));
+        __syncthreads();
+        unsigned long long pos = s_base + (inc - c);
+        for (int w = 0; w < wv; ++w) pos += s_w[w];
+#pragma unroll
+        for (int q = 0; q < kSampleItems; ++q)
+            if ((okm >> q) & 1u) out[pos++] = okey[q];
+        __syncthreads();  // s_w and s_base are rewritten by the next round
     }
 }
 
@@ -831,7 +851,7 @@ static unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 hipError_t launch_sample(const void* d_in, int64_t n, bool is_f64, uint64_t seed, int64_t k, uint64_t* d_out,
                          uint64_t* d_count, hipStream_t st) {
-    unsigned g = nblk(k, 256);
+    unsigned g = nblk(k, 256 * kSampleItems);
     if (g > 65536) g = 65536;
     hipLaunchKernelGGL(k_sample, dim3(g), dim3(256), 0, st, (const uint64_t*)d_in, n, is_f64 ? 1 : 0, seed, k,
                        d_out, (unsigned long long*)d_count);
