@@ -637,9 +637,13 @@ __global__ void __launch_bounds__(256) k_bwd_reduce(const float* __restrict__ th
     constexpr int T = H >= 64 ? 4 : (H >= 32 ? 2 : 1);  // tile edge
     constexpr int NBK = H / T;                          // tiles per dimension (<= 16)
     static_assert(NBK * NBK <= 256, "one tile per thread");
-    __shared__ __align__(16) float sh1[kRedSub][H];
-    __shared__ __align__(16) float sdz2[kRedSub][H];
-    __shared__ float sh2[kRedSub][H], sdz1[kRedSub][H];
+    // Rows padded against LDS bank conflicts: the staging writes put
+    // consecutive samples in consecutive lanes, and the dz1 loop reads four
+    // samples' dz2 at one unit.  sh1 and sdz2 rows stay 16-byte aligned for
+    // the tile loop's vector reads.
+    __shared__ __align__(16) float sh1[kRedSub][H + 4];
+    __shared__ __align__(16) float sdz2[kRedSub][H + 4];
+    __shared__ float sh2[kRedSub][H + 4], sdz1[kRedSub][H + 1];
     __shared__ float sW2[H][H];  // row i: hidden-2 unit i
     __shared__ float sw3[H];
     __shared__ float sx[kRedSub], sg[kRedSub];
