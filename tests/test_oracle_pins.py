@@ -541,3 +541,155 @@ def test_rounds_follow_processing_order():
     assert st["collided"] == [3, 1]
     assert st["extracted"] == [0, 1]
     assert out.tolist() == [0.0, 0.0, 1.0, 5.0, 10.0]
+
+
+# ---------------------------------------------------------------------------
+# closed forms for the MSE loss, Adam after two steps and the uniform start;
+# each check takes the oracle's C library as an argument so that the mutation
+# test below can run it against deliberately broken builds of the same source
+# ---------------------------------------------------------------------------
+def _lib_loss_grad(lib, th, H, x, y, loss=0, delta=1.0):
+    import ctypes
+    th = np.ascontiguousarray(th, np.float64)
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    g = np.empty(O.num_params(H), np.float64)
+    f = lib.orc_loss_grad_f64
+    f.restype = ctypes.c_double
+    f.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_int, ctypes.c_double,
+                                                           ctypes.c_void_p]
+    L = f(H, th.ctypes.data, x.ctypes.data, y.ctypes.data, x.size, loss, delta, g.ctypes.data)
+    return float(L), g
+
+
+def _lib_adam(lib, th, g, m1, m2, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    import ctypes
+    f = lib.orc_adam_step
+    f.restype = None
+    f.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int, ctypes.c_int64] + [ctypes.c_double] * 4
+    f(th.ctypes.data, g.ctypes.data, m1.ctypes.data, m2.ctypes.data, th.size, t, lr, b1, b2, eps)
+
+
+def _lib_init_uniform(lib, seed, p, bound):
+    import ctypes
+    f = lib.orc_init_uniform
+    f.restype = ctypes.c_double
+    f.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_double]
+    return float(f(seed, p, bound))
+
+
+def check_mse_closed_form(lib):
+    """A network with one active path, w1[0] = a, W2[0][0] = w, w3[0] = c,
+    b3 = d and every other parameter 0, is F(x) = c w a x + d for x > 0 (with
+    a > 0 and w > 0).  Its mean squared error over B points is mean(e^2) with
+    e = F - y, and the gradient, by the chain rule, is 2 mean(e) for b3,
+    2 mean(e w a x) for w3[0], 2 mean(e c a x) for W2[0][0], 2 mean(e c w x) for
+    w1[0], 2 mean(e c w) for b1[0], 2 mean(e c) for b2[0], 0 elsewhere."""
+    H = 4
+    a, w, c, d = 0.75, 1.5, -0.5, 0.25
+    th = np.zeros(O.num_params(H))
+    iw1, ib1, iW2, ib2, iw3, ib3 = 0, H, 2 * H, 2 * H + H * H, 3 * H + H * H, 4 * H + H * H
+    th[iw1], th[iW2], th[iw3], th[ib3] = a, w, c, d
+    x = np.array([0.1, 0.4, 0.7, 1.0, 0.55, 0.25])
+    y = np.array([0.3, 0.0, 0.9, 0.2, 0.5, 0.05])
+    e = c * w * a * x + d - y
+    L, g = _lib_loss_grad(lib, th, H, x, y, 0)
+    assert abs(L - np.mean(e * e)) <= 1e-15, (L, np.mean(e * e))
+    expect = np.zeros_like(g)
+    expect[ib3] = 2 * np.mean(e)
+    expect[iw3] = 2 * np.mean(e * w * a * x)
+    expect[iW2] = 2 * np.mean(e * c * a * x)
+    expect[iw1] = 2 * np.mean(e * c * w * x)
+    expect[ib1] = 2 * np.mean(e * c * w)
+    expect[ib2] = 2 * np.mean(e * c)
+    assert np.allclose(g, expect, rtol=0, atol=1e-15), np.nonzero(np.abs(g - expect) > 1e-15)
+
+
+def check_adam_second_step(lib):
+    """Two Adam steps from zero moments with gradients g1 then g2: the
+    bias-corrected moments after step 2 are m = (b1 g1 + g2) / (1 + b1) and
+    v = (b2 g1^2 + g2^2) / (1 + b2) (since (1 - b) / (1 - b^2) = 1 / (1 + b)),
+    and the update is -lr m / (sqrt(v) + eps)."""
+    b1, b2, eps, lr = 0.9, 0.999, 1e-8, 1e-3
+    th = np.array([1.0, -2.0, 3.0, 0.5, -0.25])
+    g1 = np.array([0.5, -1e-3, 0.0, 4.0, 2.0])
+    g2 = np.array([-0.25, 2e-3, 1.0, 4.0, -3.0])
+    m1, m2 = np.zeros(5), np.zeros(5)
+    expect = th - lr * g1 / (np.abs(g1) + eps)
+    _lib_adam(lib, th, g1.copy(), m1, m2, 1, lr, b1, b2, eps)
+    assert np.allclose(th, expect, rtol=0, atol=1e-15)
+    mh = (b1 * g1 + g2) / (1 + b1)
+    vh = (b2 * g1 * g1 + g2 * g2) / (1 + b2)
+    expect = expect - lr * mh / (np.sqrt(vh) + eps)
+    _lib_adam(lib, th, g2.copy(), m1, m2, 2, lr, b1, b2, eps)
+    assert np.allclose(th, expect, rtol=0, atol=1e-14), (th, expect)
+
+
+def check_init_uniform(lib):
+    """init 0 draws each parameter from U[-bound, bound): every draw in range
+    and on the 24-bit grid bound * 2^-23 (k - 2^23), mean 0 and variance
+    bound^2 / 3 within five standard errors, and the empirical CDF within the
+    Kolmogorov-Smirnov 0.1% critical value of the uniform's."""
+    n, bound = 20_000, 0.125
+    v = np.array([_lib_init_uniform(lib, 7, p, bound) for p in range(n)])
+    assert v.min() >= -bound and v.max() < bound
+    k = v / bound * 2.0 ** 23
+    assert np.array_equal(k, np.round(k))
+    assert abs(v.mean()) < 5 * bound / math.sqrt(3 * n)
+    var_se = bound ** 2 * math.sqrt(4.0 / (45 * n))   # sd of the sample variance of U[-b, b]
+    assert abs(v.var() - bound ** 2 / 3) < 5 * var_se
+    u = np.sort((v + bound) / (2 * bound))
+    ks = np.max(np.maximum(np.arange(1, n + 1) / n - u, u - np.arange(n) / n))
+    assert ks < 1.95 / math.sqrt(n)
+
+
+def test_mse_loss_and_gradient_closed_form():
+    check_mse_closed_form(O._L())
+
+
+def test_adam_second_step_closed_form():
+    check_adam_second_step(O._L())
+
+
+def test_init_uniform_range_grid_and_moments():
+    check_init_uniform(O._L())
+
+
+def test_init0_layout_uses_fan_in_bounds():
+    """init 0: layer-1 parameters (fan-in 1) from U[-1, 1), every later layer
+    (fan-in H) from U[-1/sqrt(H), 1/sqrt(H)); each slice spans most of its
+    range."""
+    H = 32
+    th = O.init_theta(H, 0, 11, np.zeros(0))
+    first, rest = th[:2 * H], th[2 * H:]
+    assert np.abs(first).max() <= 1.0 and np.abs(first).max() > 0.8
+    b = 1.0 / math.sqrt(H)
+    assert np.abs(rest).max() <= b and np.abs(rest).max() > 0.95 * b
+    assert abs(rest.mean()) < 5 * b / math.sqrt(3 * rest.size)
+
+
+_MUTANTS = {
+    "sum_for_mean": ("double invB = 1.0 / (double)B;", "double invB = 1.0;", check_mse_closed_form),
+    "no_factor_two": ("g = 2.0 * e;", "g = e;", check_mse_closed_form),
+    "bias_correction_1_minus_beta": ("pow(beta1, (double)t)", "beta1", check_adam_second_step),
+    "init_half_range": ("bound * (2.0 * u - 1.0)", "bound * u", check_init_uniform),
+}
+
+
+@pytest.mark.parametrize("name", sorted(_MUTANTS))
+def test_pins_reject_mutated_oracle(name, tmp_path):
+    """The closed-form checks are not vacuous: a copy of the oracle with one
+    plausible slip planted (built here, on the CPU) fails its check."""
+    import ctypes
+    import subprocess
+    old, new, check = _MUTANTS[name]
+    src = open(os.path.join(os.path.dirname(O.__file__), "nnsort_oracle.c")).read()
+    assert src.count(old) == 1, old
+    mut = tmp_path / "mutant.c"
+    mut.write_text(src.replace(old, new))
+    so = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+                           "-o", str(so), str(mut), "-lm"])
+    check(O._L())                      # the real oracle passes
+    with pytest.raises(AssertionError):
+        check(ctypes.CDLL(str(so)))
