@@ -232,11 +232,27 @@ int64_t orc_num_slots(int64_t n, double m)
     return (int64_t)t + 1;
 }
 
+/* A model with a non-finite parameter (weights, lo or inv_range) maps no
+ * key: the paper does not consider such models; the reading taken is that
+ * every key then stays in the conflict arrays and the residue sort orders
+ * them all. */
+int orc_model_finite(int H, const float* th, double lo, double inv_range)
+{
+    if (!isfinite(lo) || !isfinite(inv_range)) return 0;
+    for (int p = 0; p < H * H + 4 * H + 1; ++p)
+        if (!isfinite(th[p])) return 0;
+    return 1;
+}
+
 /* Slots of every key (the map w.map(f) followed by the rounding). */
 void orc_predict_slots(const uint64_t* bits, int64_t n, int is_f64, int H, const float* th,
                        double lo, double inv_range, double m, int form, uint32_t* slots)
 {
     double M = m * (double)n;
+    if (!orc_model_finite(H, th, lo, inv_range)) {
+        for (int64_t i = 0; i < n; ++i) slots[i] = ORC_UNMAPPED;
+        return;
+    }
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double x;

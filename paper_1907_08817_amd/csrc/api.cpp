@@ -137,6 +137,21 @@ int check_model(const nnsort_model* m) {
     return NNSORT_OK;
 }
 
+// A model with a non-finite parameter maps no key: every key then stays in
+// the conflict arrays and is sorted conventionally, whatever the form.
+bool model_is_finite(const nnsort_model* m) {
+    const int H = m->hidden;
+    if (!std::isfinite(m->lo) || !std::isfinite(m->inv_range) || !std::isfinite(m->b3)) return false;
+    for (int j = 0; j < H; ++j) {
+        if (!std::isfinite(m->w1[j]) || !std::isfinite(m->b1[j]) || !std::isfinite(m->b2[j]) ||
+            !std::isfinite(m->w3[j]))
+            return false;
+        for (int k = 0; k < H; ++k)
+            if (!std::isfinite(m->w2[j * H + k])) return false;
+    }
+    return true;
+}
+
 // Device layout of the model, zero-padded to a width of 32 or 64.
 void to_dev_model(const nnsort_model* m, DevModel* d) {
     std::memset(d, 0, sizeof(*d));
@@ -326,6 +341,8 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     if (given_slots) {
         NNS_HIP(launch_check_slots(given_slots, n, P.S, counters + kCntBadSlot, st));
         slots_src = given_slots;
+    } else if (!model_is_finite(model)) {
+        NNS_HIP(fill_u32(slots0, n, kUnmapped, st));
     } else {
         NNS_HIP(launch_infer(ia, HP, prm->form, prm->bf16_terms, st));
     }
@@ -440,7 +457,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     S.boundary_keys = (int64_t)c[kCntBoundary];
     S.fallback = c[kCntFallback] ? 1 : c[kCntJunction] ? 2 : 0;
     S.range_resorts = (int32_t)c[kCntResorted];
-    if (stats && prm->stats_level >= 2 && model) {
+    if (stats && prm->stats_level >= 2 && model && model_is_finite(model)) {
         double* Fbuf = (double*)K1;  // partition storage is free now
         InferArgs pa = ia;
         pa.in = (const uint64_t*)d_out;
@@ -520,6 +537,11 @@ FitPlan plan_fit(int64_t n, const nnsort_fit_params* fp) {
     return p;
 }
 
+// The sample is sorted with 32-bit offsets: its size must stay below 2^32 - 1.
+bool valid_sample_count(int64_t n, const nnsort_fit_params* f) {
+    return (double)f->sample_frac * (double)n < 4294967294.0;
+}
+
 bool valid_fit_params(const nnsort_fit_params* f) {
     if (!f) return false;
     if (f->hidden != 8 && f->hidden != 16 && f->hidden != 32 && f->hidden != 64) return false;
@@ -535,7 +557,7 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
              void* d_ws, size_t ws_bytes, hipStream_t st, float* loss_history, int history_len) {
     if (n < 1 || !d_keys || !out || !valid_fit_params(fp)) return NNSORT_EINVAL;
     if (dtype != NNSORT_F64 && dtype != NNSORT_U64) return NNSORT_EINVAL;
-    if (n >= (int64_t)0xFFFFFFFF) return NNSORT_EINVAL;
+    if (n >= (int64_t)0xFFFFFFFF || !valid_sample_count(n, fp)) return NNSORT_EINVAL;
     FitPlan P = plan_fit(n, fp);
     if (!d_ws || ws_bytes < P.total || ((uintptr_t)d_ws & 255u)) return NNSORT_EWORKSPACE;
     const bool is_f64 = dtype == NNSORT_F64;
@@ -701,7 +723,7 @@ int nnsort_workspace_size(int64_t n, nnsort_dtype dtype, const nnsort_sort_param
     }
     need = need > model_region_bytes() ? need : model_region_bytes();
     if (fp) {
-        if (!valid_fit_params(fp)) return NNSORT_EINVAL;
+        if (!valid_fit_params(fp) || !valid_sample_count(n > 0 ? n : 1, fp)) return NNSORT_EINVAL;
         FitPlan F = plan_fit(n > 0 ? n : 1, fp);
         need = F.total > need ? F.total : need;
     }
@@ -786,7 +808,12 @@ int nnsort_predict(const nnsort_model* model, const void* d_in, int64_t n, nnsor
     ia.S = num_slots(n, params->m);
     ia.slots_out = d_slots;
     ia.F_out = d_F;
-    NNS_HIP(launch_infer(ia, hm.H, params->form, params->bf16_terms, st));
+    if (model_is_finite(model)) {
+        NNS_HIP(launch_infer(ia, hm.H, params->form, params->bf16_terms, st));
+    } else {
+        if (d_slots) NNS_HIP(fill_u32(d_slots, n, kUnmapped, st));
+        if (d_F) NNS_HIP(fill_u64((uint64_t*)d_F, n, 0x7FF8000000000000ull, st));
+    }
     NNS_HIP(hipStreamSynchronize(st));
     return NNSORT_OK;
 }

@@ -215,8 +215,8 @@ def test_bf16_F_within_bound(H):
 def test_bf16_slots_track_fp32_on_ramp_model(name, H):
     """On a ramp model (W2 = -I is exact in bf16, output weights all different)
     the three-term BF16 form must give the FP32 form's slots up to rounding:
-    nearly all equal, none more than a few slots away, and the same round
-    counts to within 0.1% of n."""
+    nearly all equal, none more than one slot away, and the same round counts
+    to within 0.1% of n."""
     n = 1_000_000
     x = W.make(name, n)
     model = O.fit(x, H=H, sample_frac=0.01, steps=0)
@@ -227,7 +227,10 @@ def test_bf16_slots_track_fp32_on_ramp_model(name, H):
     a = s32.cpu().numpy().astype(np.int64)
     b = s16.cpu().numpy().astype(np.int64)
     assert np.mean(a == b) > 0.999
-    assert np.max(np.abs(a - b)) <= 4
+    # W2 = -I is exact in bf16 and the split activations are exact, so the two
+    # forms differ only in how the output sum is rounded (Dot2 in FP32 against
+    # FP64 accumulation): a slot can move only across a rounding boundary
+    assert np.max(np.abs(a - b)) <= 1
     _, st32 = nn.nnsort_sort_with_model(m, xd, sp=nn.sort_params(form=nn.FORM_FP32))
     _, st16 = nn.nnsort_sort_with_model(m, xd, sp=nn.sort_params(form=nn.FORM_BF16))
     for c32, c16 in zip(st32["collided"], st16["collided"]):
@@ -433,3 +436,40 @@ def test_huber_fit_tracks_oracle(batch, delta):
     assert abs(hist[0] - rhist[0]) <= 1e-5 * max(1.0, rhist[0])
     assert hist[-1] < 0.7 * hist[0] and rhist[-1] < 0.7 * rhist[0]
     assert abs(hist[-1] - rhist[-1]) <= 0.1 * rhist[-1] + 1e-7
+
+
+# ---------------------------------------------------------------------------
+# a model with a non-finite parameter maps no key
+# ---------------------------------------------------------------------------
+def _nonfinite_models(H=32):
+    base = random_model(H, 31)
+    out = []
+    for where, val in (("w1", np.nan), ("W2", np.nan), ("w3", np.inf), ("b3", -np.inf)):
+        th = base["theta"].copy()
+        idx = {"w1": 3, "W2": 2 * H + 5 * H + 7, "w3": 3 * H + H * H + 2, "b3": -1}[where]
+        th[idx] = val
+        out.append((where, dict(base, theta=th)))
+    out.append(("lo", dict(base, lo=np.nan)))
+    return out
+
+
+@pytest.mark.parametrize("form", [nn.FORM_FP32, nn.FORM_BF16, nn.FORM_PWL])
+def test_nonfinite_model_sends_every_key_to_the_residue(form):
+    """Every key of a sort with a non-finite model takes the conventional
+    path: no key is placed, every round's conflict array holds all n keys, the
+    output is still the exact sorted array, and the slot map reports no slot
+    and F = NaN for every key (the oracle's rule for such models)."""
+    x = W.gauss_mix(70_001, seed=9)
+    xd = to_dev(x)
+    for where, model in _nonfinite_models():
+        m = nn.model_from_dict(model)
+        sp = nn.sort_params(form=form, stats_level=2)
+        out, st = nn.nnsort_sort_with_model(m, xd, sp=sp)
+        assert_same_bits(to_host(out, x.dtype), O.sort_reference(x))
+        ref, ost = O.nnsort(x, model)
+        assert st["unmapped"] == x.size, where
+        assert st["collided"] == ost["collided"] == [x.size] * 3, where
+        assert st["placed"] == [0, 0, 0], where
+        slots, F = nn.nnsort_predict(m, xd, sp)
+        assert np.all(slots.cpu().numpy() == 0xFFFFFFFF), where
+        assert np.all(np.isnan(F.cpu().numpy())), where

@@ -63,6 +63,21 @@ def test_workspace_size_grows_and_validates():
         nn.workspace_size(10, nn.F64, sp, nn.fit_params(hidden=12))
 
 
+def test_fit_sample_beyond_32_bit_offsets_rejected():
+    # the sample is sorted with 32-bit offsets: 50 x 1e8 draws must be refused
+    # (EINVAL) rather than planned; just below the limit is accepted
+    sp, _ = nn.default_params()
+    with pytest.raises(nn.NNSortError) as e:
+        nn.workspace_size(10 ** 8, nn.F64, sp, nn.fit_params(sample_frac=50.0))
+    assert e.value.status == -1
+    assert nn.workspace_size(10 ** 8, nn.F64, sp, nn.fit_params(sample_frac=42.0)) > 0
+    L = nn._lib()
+    fp = nn.fit_params(sample_frac=50.0)
+    m = nn.Model()
+    p = ctypes.c_void_p(0x100000)
+    assert L.nnsort_fit(p, 10 ** 8, 0, ctypes.byref(fp), ctypes.byref(m), p, 1 << 40, None) == -1
+
+
 def test_argument_checks_before_device_work():
     L = nn._lib()
     sp, fp = nn.default_params()

@@ -693,3 +693,24 @@ def test_pins_reject_mutated_oracle(name, tmp_path):
     check(O._L())                      # the real oracle passes
     with pytest.raises(AssertionError):
         check(ctypes.CDLL(str(so)))
+
+
+@pytest.mark.parametrize("where", ["w1", "W2", "b3", "lo"])
+def test_nonfinite_model_maps_no_key(where):
+    """A model with a NaN or infinite parameter maps no key (the reading taken
+    for such models): every key stays in every conflict array, |c_r| = n for
+    each of the eps rounds, nothing is placed, and the residue sort alone
+    yields the output, which is still the brute-force order."""
+    H = 8
+    model = random_model(H, 5)
+    th = model["theta"].copy()
+    if where == "lo":
+        model = dict(model, lo=float("nan"))
+    else:
+        th[{"w1": 0, "W2": 2 * H + 9, "b3": -1}[where]] = np.inf if where == "b3" else np.nan
+        model = dict(model, theta=th)
+    x = np.random.default_rng(2).random(3000)
+    assert np.all(O.predict_slots(x, model) == O.UNMAPPED)
+    out, st = O.nnsort(x, model, tau=16)
+    assert st["collided"] == [x.size] * 3 and st["placed"] == [0, 0, 0]
+    assert np.array_equal(out, np.sort(x))
