@@ -152,6 +152,76 @@ bool model_is_finite(const nnsort_model* m) {
     return true;
 }
 
+float bf16_rne(float v) {
+    uint32_t u;
+    std::memcpy(&u, &v, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    u &= 0xFFFF0000u;
+    float r;
+    std::memcpy(&r, &u, 4);
+    return r;
+}
+
+// Smallest k with 2^k >= U, for U > 0.
+int ceil_log2(double U) {
+    int e;
+    double f = std::frexp(U, &e);  // U = f 2^e, f in [0.5, 1)
+    return f == 0.5 ? e - 1 : e;
+}
+
+bool scaled_exact(float v, int k, float* out) {
+    float s = std::ldexp(v, k);
+    *out = s;
+    return std::isfinite(s) && std::ldexp(s, -k) == v;
+}
+
+// The BF16 form's scaled operands (see DevModel).  Bounds: for x in [0, 1] a
+// hidden-1 pre-activation, rounded in FP32, stays below (|w1| + |b1|)(1 + 2^-22);
+// a hidden-2 pre-activation below (|b2| + sum_j |bf16(W2)| U1_j) plus the FP32
+// accumulation error of 3H + 1 terms (< 2^-16 relative).  A margin of 1/64
+// covers both; a looser bound only makes a scaled value smaller.
+void bf16_operands(DevModel* d) {
+    const int H = d->H;
+    const double margin = 1.0 + 1.0 / 64.0;
+    double U1[64];
+    int k1[64], k2[64];
+    for (int j = 0; j < H; ++j) {
+        U1[j] = ((double)std::fabs(d->w1[j]) + (double)std::fabs(d->b1[j])) * margin;
+        k1[j] = U1[j] > 0.0 ? ceil_log2(U1[j]) : 0;
+    }
+    for (int i = 0; i < H; ++i) {
+        double U = std::fabs((double)d->b2[i]);
+        for (int j = 0; j < H; ++j) U += std::fabs((double)bf16_rne(d->w2[i * H + j])) * U1[j];
+        U *= margin;
+        k2[i] = U > 0.0 ? ceil_log2(U) : 0;
+    }
+    bool ok = true;
+    for (int j = 0; j < H && ok; ++j)
+        ok = k1[j] > -100 && k1[j] < 100 && scaled_exact(d->w1[j], -k1[j], &d->w1s[j]) &&
+             scaled_exact(d->b1[j], -k1[j], &d->b1s[j]);
+    for (int i = 0; i < H && ok; ++i) {
+        ok = k2[i] > -100 && k2[i] < 100 && scaled_exact(d->b2[i], -k2[i], &d->b2s[i]);
+        d->w3s[i] = std::ldexp((double)d->w3[i], k2[i]);
+        for (int j = 0; j < H && ok; ++j) {
+            float a = bf16_rne(d->w2[i * H + j]), as;
+            uint32_t bitsv;
+            ok = scaled_exact(a, k1[j] - k2[i], &as);
+            std::memcpy(&bitsv, &as, 4);
+            ok = ok && (bitsv & 0xFFFFu) == 0 && std::fpclassify(as) != FP_SUBNORMAL;
+            d->w2s[i * H + j] = as;
+        }
+    }
+    d->bf16_scaled = ok ? 1 : 0;
+    if (ok) return;
+    for (int j = 0; j < H; ++j) {
+        d->w1s[j] = d->w1[j];
+        d->b1s[j] = d->b1[j];
+        d->b2s[j] = d->b2[j];
+        d->w3s[j] = (double)d->w3[j];
+        for (int k = 0; k < H; ++k) d->w2s[j * H + k] = bf16_rne(d->w2[j * H + k]);
+    }
+}
+
 // Device layout of the model, zero-padded to a width of 32 or 64.
 void to_dev_model(const nnsort_model* m, DevModel* d) {
     std::memset(d, 0, sizeof(*d));
@@ -168,6 +238,7 @@ void to_dev_model(const nnsort_model* m, DevModel* d) {
         for (int k = 0; k < H; ++k) d->w2[j * HP + k] = m->w2[j * H + k];
     }
     d->b3 = m->b3;
+    bf16_operands(d);
 }
 
 }  // namespace
@@ -336,6 +407,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     ia.M = prm->m * (double)n;
     ia.S = P.S;
     ia.slots_out = slots0;
+    ia.bf16_scaled = model ? hm.bf16_scaled : 0;
     ev.mark(7);
     const uint32_t* slots_src = slots0;
     if (given_slots) {
@@ -808,6 +880,7 @@ int nnsort_predict(const nnsort_model* model, const void* d_in, int64_t n, nnsor
     ia.S = num_slots(n, params->m);
     ia.slots_out = d_slots;
     ia.F_out = d_F;
+    ia.bf16_scaled = hm.bf16_scaled;
     if (model_is_finite(model)) {
         NNS_HIP(launch_infer(ia, hm.H, params->form, params->bf16_terms, st));
     } else {

@@ -103,7 +103,7 @@ hipError_t launch_pos_err_sum(const double* d_F, int64_t n, double* d_sum, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_bf16_infer(const InferArgs& a, int H, int bf16_terms, hipStream_t st);
+hipError_t launch_bf16_infer(const InferArgs& a, int H, int bf16_terms, bool scaled, hipStream_t st);
 hipError_t launch_pwl_infer(const InferArgs& a, int H, hipStream_t st);
 
 static int grid_for(int64_t n, int threads, int max_blocks) {
@@ -115,7 +115,7 @@ static int grid_for(int64_t n, int threads, int max_blocks) {
 
 hipError_t launch_infer(const InferArgs& a, int H, int form, int bf16_terms, hipStream_t st) {
     if (a.n <= 0) return hipSuccess;
-    if (form == NNSORT_FORM_BF16) return launch_bf16_infer(a, H, bf16_terms, st);
+    if (form == NNSORT_FORM_BF16) return launch_bf16_infer(a, H, bf16_terms, a.bf16_scaled != 0, st);
     if (form == NNSORT_FORM_PWL) return launch_pwl_infer(a, H, st);
     int grid = grid_for(a.n, 256, 256 * 64);
     if (H == 32)

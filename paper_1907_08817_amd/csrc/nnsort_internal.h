@@ -80,8 +80,27 @@ struct DevModel {
     float b2[64];
     float w3[64];
     float b3;
+    // Operands of the BF16 form, prepared on the host (bf16_operands()):
+    // with power-of-two scales 2^k1[j] per hidden-1 unit and 2^k2[i] per
+    // hidden-2 unit chosen so that every pre-activation of the scaled network
+    // lies in (-inf, 1] for inputs in [0, 1], relu becomes a clamp to [0, 1],
+    // which the FMA producing layer 1 and the conversion feeding layer 3
+    // apply for free.  Scaling by powers of two commutes with rounding, so the
+    // scaled network computes the same F bit for bit (barring subnormals):
+    //   w1s = w1 2^-k1, b1s = b1 2^-k1, w2s[i][j] = bf16(W2[i][j]) 2^(k1[j] - k2[i]),
+    //   b2s = b2 2^-k2, w3s = w3 2^k2 (FP64).
+    // bf16_scaled = 0 when some scaled operand would not be exact (subnormal
+    // or out of range): the fields then hold the unscaled values and the
+    // kernel applies relu explicitly.
+    int bf16_scaled;
+    float w1s[64];
+    float b1s[64];
+    float b2s[64];
+    alignas(8) double w3s[64];
+    alignas(16) float w2s[64 * 64];  // bf16 values held as FP32
 };
 static_assert(offsetof(DevModel, w2) % 16 == 0, "W2 rows are read as 16-byte vectors");
+static_assert(offsetof(DevModel, w2s) % 16 == 0, "W2 rows are read as 16-byte vectors");
 
 // Workspace carve-up for a sort of n keys.
 struct SortPlan {
@@ -133,6 +152,7 @@ struct InferArgs {
     int64_t S;
     uint32_t* slots_out;  // optional per-key slot
     double* F_out;        // optional per-key F
+    int bf16_scaled;      // the host copy's DevModel::bf16_scaled (BF16 form)
 };
 
 // H is the padded model width (32 or 64).

@@ -211,6 +211,31 @@ def test_bf16_F_within_bound(H):
     assert np.all(d[ok] <= bound[ok] + 1e-300), float(np.max(d[ok] / bound[ok]))
 
 
+def test_bf16_scaled_operands_change_no_bit():
+    """The BF16 form runs on power-of-two-scaled operands (relu as a clamp to
+    [0, 1]) when every scaled operand is exact, and on the unscaled ones with
+    an explicit relu otherwise.  Scaling commutes with rounding, so both give
+    the same F bit for bit.  Model 2 differs from model 1 only in a hidden-2
+    row whose output weight is 0 (it adds an exact 0 to F) and whose tiny
+    W2 entry cannot be scaled exactly, which forces the unscaled kernel."""
+    x = W.gauss_mix(200_000, seed=8)
+    H = 64
+    m1 = O.fit(x, H=H, sample_frac=0.01, steps=0)
+    th = m1["theta"].copy()
+    iW2, iw3 = 2 * H, 3 * H + H * H
+    th[iw3 + H - 1] = 0.0
+    m1 = dict(m1, theta=th)
+    th2 = th.copy()
+    th2[iW2 + (H - 1) * H + 0] = 1e-37
+    th2[iW2 + (H - 1) * H + 1] = 1.0
+    m2 = dict(m1, theta=th2)
+    sp = nn.sort_params(form=nn.FORM_BF16, bf16_terms=3)
+    xd = to_dev(x)
+    _, F1 = nn.nnsort_predict(nn.model_from_dict(m1), xd, sp)
+    _, F2 = nn.nnsort_predict(nn.model_from_dict(m2), xd, sp)
+    assert_same_bits(F1.cpu().numpy(), F2.cpu().numpy())
+
+
 @pytest.mark.parametrize("name,H", [("gauss_mix", 64), ("lognormal", 32)])
 def test_bf16_slots_track_fp32_on_ramp_model(name, H):
     """On a ramp model (W2 = -I is exact in bf16, output weights all different)
