@@ -52,7 +52,8 @@ typedef enum {
     NNSORT_EHIP = -3,        /* a HIP runtime call failed */
     NNSORT_EMODEL = -4,      /* malformed model (hidden width, version) */
     NNSORT_EIO = -5,         /* model file could not be read or written */
-    NNSORT_EINTERNAL = -6    /* a device-side consistency check failed */
+    NNSORT_EINTERNAL = -6,   /* a device-side consistency check failed */
+    NNSORT_ETOOBIG = -7      /* input beyond the static scratch of nnsort_sort_with_model_noalloc */
 } nnsort_status;
 
 typedef enum { NNSORT_FORM_FP32 = 0, NNSORT_FORM_BF16 = 1, NNSORT_FORM_PWL = 2 } nnsort_form;
@@ -198,6 +199,22 @@ int nnsort_fit_history(const void* d_keys, int64_t n, nnsort_dtype dtype,
 int nnsort_sort_with_model(const nnsort_model* model, const void* d_in, void* d_out, int64_t n,
                            nnsort_dtype dtype, const nnsort_sort_params* params, void* d_ws,
                            size_t ws_bytes, nnsort_stats* stats, void* stream);
+
+/* nnsort_sort_with_model without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The sort runs in a static 64 MiB device
+ * array of the library (one per GPU, held until the process ends): n may be
+ * at most the largest count whose nnsort_workspace_size(n, dtype, params,
+ * NULL) is at most 64 MiB (about 1.5 million keys at m = 1.25); larger inputs
+ * return NNSORT_ETOOBIG before any device work.  The call allocates nothing:
+ * no device memory, no events (stats carries counts but no phase times).
+ * Every call on one GPU shares that GPU's array, which keeps the previous
+ * call's contents (each call initialises what it reads): calls that overlap
+ * on one GPU, from several streams or threads, race and must not be issued.
+ * Otherwise as nnsort_sort_with_model (same checks, synchronises the stream). */
+int nnsort_sort_with_model_noalloc(const nnsort_model* model, const void* d_in, void* d_out, int64_t n,
+                                   nnsort_dtype dtype, const nnsort_sort_params* params, nnsort_stats* stats,
+                                   void* stream);
 
 /* Fit on d_in, then sort it: nnsort_fit followed by nnsort_sort_with_model.
  * The fitted model is copied to *model_out when it is not NULL; stats->

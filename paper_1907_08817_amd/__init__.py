@@ -24,7 +24,8 @@ MAX_HIDDEN = 64
 MAX_EPS = 8
 F64, U64 = 0, 1
 FORM_FP32, FORM_BF16, FORM_PWL = 0, 1, 2
-STATUS = {0: "OK", -1: "EINVAL", -2: "EWORKSPACE", -3: "EHIP", -4: "EMODEL", -5: "EIO", -6: "EINTERNAL"}
+STATUS = {0: "OK", -1: "EINVAL", -2: "EWORKSPACE", -3: "EHIP", -4: "EMODEL", -5: "EIO", -6: "EINTERNAL",
+          -7: "ETOOBIG"}
 
 
 class NNSortError(RuntimeError):
@@ -85,6 +86,7 @@ def _lib():
             "nnsort_fit": (i32, [P, i64, i32, pF, pM, P, sz, P]),
             "nnsort_fit_history": (i32, [P, i64, i32, pF, pM, P, sz, ctypes.POINTER(f32), i32, P]),
             "nnsort_sort_with_model": (i32, [pM, P, P, i64, i32, pS, P, sz, pT, P]),
+            "nnsort_sort_with_model_noalloc": (i32, [pM, P, P, i64, i32, pS, pT, P]),
             "nnsort_sort": (i32, [P, P, i64, i32, pF, pS, P, sz, pM, pT, P]),
             "nnsort_model_device_bytes": (sz, []),
             "nnsort_predict": (i32, [pM, P, i64, i32, pS, P, P, P, sz, P]),
@@ -112,7 +114,7 @@ def _lib():
 
 def exported_symbols() -> list:
     return [n for n in ("nnsort_default_params", "nnsort_workspace_size", "nnsort_fit", "nnsort_fit_history",
-                        "nnsort_sort_with_model", "nnsort_sort", "nnsort_model_device_bytes", "nnsort_predict",
+                        "nnsort_sort_with_model", "nnsort_sort_with_model_noalloc", "nnsort_sort", "nnsort_model_device_bytes", "nnsort_predict",
                         "nnsort_sort_with_slots", "nnsort_radix_workspace_size", "nnsort_radix_sort",
                         "nnsort_mlp_saved_floats", "nnsort_mlp_backward_ws_floats", "nnsort_mlp_forward",
                         "nnsort_mlp_backward", "nnsort_loss_ws_floats", "nnsort_loss_grad", "nnsort_adam_step",
@@ -285,6 +287,22 @@ def nnsort_sort_with_model(model: Model, keys, out=None, sp: SortParams | None =
     rc = _lib().nnsort_sort_with_model(ctypes.byref(model), _ptr(keys), _ptr(out), keys.numel(), dt,
                                        ctypes.byref(sp), _ptr(ws), ws.numel(), ctypes.byref(st), _stream(stream))
     _check(rc, "nnsort_sort_with_model")
+    return out, stats_to_dict(st)
+
+
+def nnsort_sort_with_model_noalloc(model: Model, keys, out=None, sp: SortParams | None = None, stream=None):
+    """Sort keys with a given model in the library's static device scratch (no
+    workspace; inputs up to about 1.5M keys); returns (sorted tensor, stats)."""
+    torch = _torch()
+    keys = _keys(keys)
+    sp = sp or default_params()[0]
+    if out is None:
+        out = torch.empty_like(keys)
+    st = Stats()
+    rc = _lib().nnsort_sort_with_model_noalloc(ctypes.byref(model), _ptr(keys), _ptr(out), keys.numel(),
+                                               _dtype_code(keys), ctypes.byref(sp), ctypes.byref(st),
+                                               _stream(stream))
+    _check(rc, "nnsort_sort_with_model_noalloc")
     return out, stats_to_dict(st)
 
 

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "nnsort_internal.h"
@@ -327,7 +328,7 @@ int plain_sort(const void* d_in, void* d_out, int64_t n, bool is_f64, void* d_ws
 
 int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void* d_in, void* d_out, int64_t n,
               nnsort_dtype dtype, const nnsort_sort_params* prm, void* d_ws, size_t ws_bytes, nnsort_stats* stats,
-              hipStream_t st) {
+              hipStream_t st, bool timers = true) {
     if (n < 0 || (n > 0 && (!d_in || !d_out))) return NNSORT_EINVAL;
     if (dtype != NNSORT_F64 && dtype != NNSORT_U64) return NNSORT_EINVAL;
     if (!valid_sort_params(prm, n)) return NNSORT_EINVAL;
@@ -345,7 +346,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     nnsort_stats S{};
     S.n = n;
     S.form = prm->form;
-    Events ev(stats && prm->stats_level >= 1, st);
+    Events ev(timers && stats && prm->stats_level >= 1, st);
     ev.mark(0);
     if (n == 0) {
         if (stats) *stats = S;
@@ -757,7 +758,58 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
 
 }  // namespace
 
+// ---- the allocation-free sort: a static device scratch array ----
+// nnsort_sort_with_model_noalloc sorts in this array instead of a caller
+// workspace.  Each GPU the library runs on holds its own copy for the life of
+// the process.  Host code never passes the array's name to a kernel (on the
+// host it is only a stand-in); it uses the device address that
+// hipGetSymbolAddress returns, taken once per device with that device current.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_current_device(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return NNSORT_EINTERNAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(scratch)");
+        if (!p || ((uintptr_t)p & 255u)) return NNSORT_EINTERNAL;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return NNSORT_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+int nnsort_sort_with_model_noalloc(const nnsort_model* model, const void* d_in, void* d_out, int64_t n,
+                                   nnsort_dtype dtype, const nnsort_sort_params* params, nnsort_stats* stats,
+                                   void* stream) {
+    if (!model || !params) return NNSORT_EINVAL;
+    size_t need = 0;
+    int rc = nnsort_workspace_size(n, dtype, params, nullptr, &need);
+    if (rc) return rc;
+    if (need > kScratchBytes) return NNSORT_ETOOBIG;
+    if (n == 0) return sort_impl(model, nullptr, d_in, d_out, n, dtype, params, nullptr, 0, stats,
+                                 (hipStream_t)stream, false);
+    void* ws = nullptr;
+    rc = scratch_of_current_device(&ws);
+    if (rc) return rc;
+    return sort_impl(model, nullptr, d_in, d_out, n, dtype, params, ws, kScratchBytes, stats, (hipStream_t)stream,
+                     false);
+}
 
 void nnsort_default_params(nnsort_sort_params* sp, nnsort_fit_params* fp) {
     if (sp) {
@@ -998,6 +1050,7 @@ const char* nnsort_strerror(int status) {
     case NNSORT_EMODEL: return "malformed model";
     case NNSORT_EIO: return "model file I/O error";
     case NNSORT_EINTERNAL: return "internal consistency check failed";
+    case NNSORT_ETOOBIG: return "input needs more than the 64 MiB static scratch of nnsort_sort_with_model_noalloc";
     default: return "unknown status";
     }
 }

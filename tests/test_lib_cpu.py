@@ -176,3 +176,16 @@ def test_bench_host_parallel_sort_matches_numpy(dtype):
     rng.shuffle(x)
     for threads in (1, 3, 8):
         assert np.array_equal(bench.host_parallel_sort(x, threads), np.sort(x))
+
+
+def test_noalloc_size_check_precedes_device_work():
+    # beyond the 64 MiB static scratch: ETOOBIG from the host-side check,
+    # before anything touches a device (this container has none)
+    L = nn._lib()
+    sp, _ = nn.default_params()
+    m = nn.Model()
+    m.version, m.hidden = 1, 32
+    p, q = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x90000000)
+    assert L.nnsort_sort_with_model_noalloc(ctypes.byref(m), p, q, 10 ** 7, 0, ctypes.byref(sp), None, None) == -7
+    assert L.nnsort_sort_with_model_noalloc(None, p, q, 10, 0, ctypes.byref(sp), None, None) == -1
+    assert nn.workspace_size(1_552_000, nn.F64, sp) <= 64 << 20 < nn.workspace_size(1_552_001, nn.F64, sp)
