@@ -131,7 +131,12 @@ typedef struct {
 /* Statistics of one sort.  collided[r] is |c_{r+1}|, the conflict array after
  * round r+1; residue = |last conflict array|, so residue / n is the paper's
  * traditional sorting rate (Sec. 4.1, Eq. (ratio)).  Times are milliseconds
- * between HIP events on the call's stream. */
+ * between HIP events on the call's stream.
+ * Not reported: the out-of-order count e_r of each o_r (Sec. 3).  Here a
+ * slot range's keys reach its workgroup in the order of the partition's
+ * atomic ranks, not in input order, so which of a slot's keys sits in which
+ * o_r (and so e_r) is not the paper's first-arrival assignment; the round
+ * counts, which depend only on each slot's multiplicity, are. */
 typedef struct {
     int64_t n;
     int32_t rounds;
@@ -160,6 +165,7 @@ typedef struct {
      * residue path and its placement; t_merge = the check and repair of the
      * boundaries between neighbouring ranges; t_total = the whole call. */
     double t_infer_ms, t_place_ms, t_polish_ms, t_residue_ms, t_merge_ms, t_total_ms;
+    double t_fit_ms;         /* nnsort_sort: the fit that preceded the sort (0 otherwise) */
 } nnsort_stats;
 
 /* Default parameters (m 1.25, eps 3, tau 1024, FP32 form, 3 bf16 terms;
@@ -218,13 +224,14 @@ int nnsort_sort_with_model_noalloc(const nnsort_model* model, const void* d_in, 
 
 /* Fit on d_in, then sort it: nnsort_fit followed by nnsort_sort_with_model.
  * The fitted model is copied to *model_out when it is not NULL; stats->
- * t_total_ms then includes the fit. */
+ * t_fit_ms is the fit and stats->t_total_ms the fit plus the sort. */
 int nnsort_sort(const void* d_in, void* d_out, int64_t n, nnsort_dtype dtype,
                 const nnsort_fit_params* fit_params, const nnsort_sort_params* sort_params,
                 void* d_ws, size_t ws_bytes, nnsort_model* model_out, nnsort_stats* stats,
                 void* stream);
 
-/* The input and sorting phases' map only: for each key, F(key) (the model's
+/* The input and sorting phases' map only (the test hook that returns the
+ * predicted slots; it also returns F, so it is named nnsort_predict): for each key, F(key) (the model's
  * normalised position, as a double; NaN for unmappable keys) and its slot
  * round(F m n) clamped to [0, m n] (0xFFFFFFFF for unmappable keys).  Either
  * output may be NULL.  d_ws must hold nnsort_model_device_bytes() bytes (the

@@ -63,7 +63,7 @@ class Stats(ctypes.Structure):
                 ("fallback", ctypes.c_int32), ("range_resorts", ctypes.c_int32), ("pos_err", ctypes.c_double),
                 ("t_infer_ms", ctypes.c_double), ("t_place_ms", ctypes.c_double),
                 ("t_polish_ms", ctypes.c_double), ("t_residue_ms", ctypes.c_double),
-                ("t_merge_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
+                ("t_merge_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double), ("t_fit_ms", ctypes.c_double)]
 
 
 _LIB = None
@@ -191,7 +191,8 @@ def stats_to_dict(s: Stats) -> dict:
             "big_buckets": s.big_buckets, "big_bucket_keys": s.big_bucket_keys,
             "boundary_keys": s.boundary_keys, "fallback": s.fallback, "range_resorts": s.range_resorts, "pos_err": s.pos_err,
             "t_infer_ms": s.t_infer_ms, "t_place_ms": s.t_place_ms, "t_polish_ms": s.t_polish_ms,
-            "t_residue_ms": s.t_residue_ms, "t_merge_ms": s.t_merge_ms, "t_total_ms": s.t_total_ms}
+            "t_residue_ms": s.t_residue_ms, "t_merge_ms": s.t_merge_ms, "t_total_ms": s.t_total_ms,
+            "t_fit_ms": s.t_fit_ms}
 
 
 def model_save(m: Model, path: str):

@@ -902,6 +902,7 @@ int nnsort_sort(const void* d_in, void* d_out, int64_t n, nnsort_dtype dtype, co
     if (model_out) *model_out = m;
     if (stats && ev.on) {
         NNS_HIP(hipEventSynchronize(ev.e[2]));
+        stats->t_fit_ms = ev.ms(0, 1);
         stats->t_total_ms = ev.ms(0, 2);
     }
     return NNSORT_OK;

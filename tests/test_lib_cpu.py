@@ -33,7 +33,7 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(nn.SortParams) == 32
     assert ctypes.sizeof(nn.FitParams) == 48
     assert ctypes.sizeof(nn.Model) == 8 + 16 + 4 * (64 * 4 + 64 * 64 + 1 + 3)
-    assert ctypes.sizeof(nn.Stats) == 8 + 8 + 16 * 8 + 5 * 8 + 8 + 8 + 6 * 8
+    assert ctypes.sizeof(nn.Stats) == 8 + 8 + 16 * 8 + 5 * 8 + 8 + 8 + 7 * 8
 
 
 def test_default_params():
