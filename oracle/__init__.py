@@ -26,7 +26,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nnsort_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# NNSORT_ORACLE_LIB names another build of the same source (the sanitizer
+# test loads an ASan/UBSan build this way); it is then used as it is.
+_LIB_PATH = os.environ.get("NNSORT_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 UNMAPPED = 0xFFFFFFFF
@@ -35,6 +37,8 @@ FORM_FP32C, FORM_FP64, FORM_BF16W = 0, 1, 2
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (the checker, never the product)."""
+    if os.environ.get("NNSORT_ORACLE_LIB"):
+        return _LIB_PATH
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call([
