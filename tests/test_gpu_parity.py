@@ -340,6 +340,32 @@ def test_fit_loss_tracks_oracle():
     assert abs(hist[-1] - rhist[-1]) <= 0.05 * rhist[-1] + 1e-6
 
 
+def test_default_fit_recipe_matches_oracle():
+    """The default fit (H 64, 1% sample, 200 Adam steps on batches of 65,536,
+    ramp start, keep the lowest batch loss unless it is more disordered than
+    the start) on the device and in the oracle: the batch loss of every step
+    within FP32 evaluation error of the oracle's FP64 loss, the same lo and
+    inv_range, and the two chosen models' slots within one slot of each other
+    on a sample of keys."""
+    x = W.gauss_mix(1_000_000, seed=13)
+    _, fp = nn.default_params()
+    fp.hidden = 64
+    m, hist = nn.nnsort_fit(to_dev(x), fp, history=True)
+    ref, rhist = O.fit(x, H=64, sample_frac=fp.sample_frac, batch=fp.batch, steps=fp.steps, lr=fp.lr,
+                       seed=fp.seed, init=fp.init, loss=fp.loss, return_history=True)
+    assert len(hist) == len(rhist) == 200
+    h, r = np.array(hist), np.array(rhist)
+    assert np.all(np.abs(h - r) <= 1e-3 * r + 1e-12), float(np.max(np.abs(h - r) / r))
+    got = nn.model_to_dict(m)
+    assert got["lo"] == ref["lo"] and got["inv_range"] == ref["inv_range"]
+    xs = x[np.random.default_rng(3).choice(x.size, 100_000, replace=False)]
+    M = 1.25 * x.size
+    xh, ok = O.translate(xs, got["lo"], got["inv_range"])
+    a = O.slots_from_F(O.eval_F(xh, got, O.FORM_FP32C), M).astype(np.int64)
+    b = O.slots_from_F(O.eval_F(xh, ref, O.FORM_FP32C), M).astype(np.int64)
+    assert np.max(np.abs(a - b)[ok]) <= 1
+
+
 @pytest.mark.parametrize("H,loss", [(8, 0), (32, 0), (64, 0), (32, 1)])
 def test_gradient_vs_fp64_reference(H, loss):
     rng = np.random.default_rng(H)
