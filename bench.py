@@ -186,9 +186,18 @@ def main():
         _, st2 = run_sort(nn.sort_params(form=form_code, bf16_terms=args.bf16_terms, stats_level=2))
         pos_err["form"] = st2["pos_err"]
 
-    # roofline of the dominant kernel: the model map (inference + hand-off)
+    # conflicts of the fit's starting model (no Adam step), beside those of
+    # the fitted one that the timed sorts used
+    fp0 = nn.fit_params(hidden=H, sample_frac=frac, steps=0)
+    model0 = nn.nnsort_fit(keys, fp0, ws=ws)
+    _, st0 = nn.nnsort_sort_with_model(model0, keys, out=out, sp=sp, ws=ws)
+    init_collided = [round(v / n, 5) for v in st0["collided"]]
+
+    # roofline of the dominant kernel: the model map (inference + hand-off).
+    # BF16 form: the hidden-to-hidden product is the matrix cores' work,
+    # 2 H^2 flop per key (algorithmic); the bf16x3 split issues it three times
     k1_ms = float(np.mean(infer_ms))
-    flop_per_key = 2 * (2 * H + H * H)
+    flop_per_key = 2 * H * H if form == "bf16" else 2 * (2 * H + H * H)
     achieved_tflops = flop_per_key * n / (k1_ms * 1e-3) / 1e12
     if form == "pwl":
         # HBM-bound: 8 bytes read and a 4-byte slot written per key; the map
@@ -216,6 +225,10 @@ def main():
                     "frac": round(achieved_tflops / peak, 5), "traffic": ctr.get("bytes_per_launch"),
                     "flop_per_key": flop_per_key, "keys_per_launch": n, "avg_launch_ms": round(k1_ms, 4),
                     "valu_issue": valu_issue(ctr, k1_ms)}
+        if form == "bf16":
+            issued = args.bf16_terms * flop_per_key
+            roofline["issued_flop_per_key"] = issued
+            roofline["issued_frac"] = round(issued * n / (k1_ms * 1e-3) / 1e12 / peak, 5)
 
     # whole-sort algorithmic HBM bytes: keys read, placed keys written/read,
     # conflict (key, slot) pairs written/read, residue radix passes, output
@@ -338,6 +351,7 @@ def main():
         "e2e_hbm": e2e,
         "rounds": stats["rounds"],
         "collided_frac": [round(v / n, 5) for v in c],
+        "init_collided_frac": init_collided,
         "residue_frac": round(ct / n, 5),
         "pos_err": {k: float(f"{v:.5g}") for k, v in pos_err.items()},
         "boundary_keys": stats["boundary_keys"],
