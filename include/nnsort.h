@@ -287,6 +287,20 @@ int nnsort_loss_grad(const float* d_F, const float* d_y, int64_t batch, int loss
 int nnsort_adam_step(float* d_theta, const float* d_g, float* d_m1, float* d_m2, int64_t count,
                      int64_t t, float lr, float beta1, float beta2, float eps, void* stream);
 
+/* One training step of the fit as nnsort_fit runs it for hidden = 32 or 64
+ * (one fused kernel on the FP32 matrix cores), without the Adam update: the
+ * batch of `batch` entries drawn from the sample d_x[0..k) / d_y[0..k) with
+ * replacement (entry b is index Philox4x32-10(seed, stream 3, counter (b,
+ * step)) mod k), its loss (0 MSE, 1 Huber(delta), mean over the batch) into
+ * d_loss[0] and dL/dtheta into d_gtheta (P floats, overwritten).  A test hook
+ * for the gradient the fit applies.  d_ws holds
+ * nnsort_fit_gradient_ws_floats(hidden, batch) floats.  EINVAL: hidden not 32
+ * or 64, batch, k or step < 1, null pointers; EWORKSPACE: d_ws too small. */
+size_t nnsort_fit_gradient_ws_floats(int hidden, int64_t batch);
+int nnsort_fit_gradient(int hidden, const float* d_theta, const double* d_x, const float* d_y, int64_t k,
+                        int64_t batch, uint64_t seed, int64_t step, int loss, float delta, float* d_gtheta,
+                        float* d_loss, float* d_ws, size_t ws_floats, void* stream);
+
 /* Save or load a model as a small binary file (magic "NNSM", version,
  * hidden, lo, inv_range, then the FP32 weights).  EIO on file errors,
  * EMODEL on a malformed file. */

@@ -98,6 +98,8 @@ def _lib():
             "nnsort_mlp_forward": (i32, [i32, P, P, i64, P, P, P]),
             "nnsort_mlp_backward": (i32, [i32, P, P, i64, P, P, P, P, P]),
             "nnsort_loss_ws_floats": (sz, []),
+            "nnsort_fit_gradient_ws_floats": (sz, [i32, i64]),
+            "nnsort_fit_gradient": (i32, [i32, P, P, P, i64, i64, ctypes.c_uint64, i64, i32, f32, P, P, P, sz, P]),
             "nnsort_loss_grad": (i32, [P, P, i64, i32, f32, P, P, P, P]),
             "nnsort_adam_step": (i32, [P, P, P, P, i64, i64, f32, f32, f32, f32, P]),
             "nnsort_model_save": (i32, [pM, ctypes.c_char_p]),
@@ -118,6 +120,7 @@ def exported_symbols() -> list:
                         "nnsort_sort_with_slots", "nnsort_radix_workspace_size", "nnsort_radix_sort",
                         "nnsort_mlp_saved_floats", "nnsort_mlp_backward_ws_floats", "nnsort_mlp_forward",
                         "nnsort_mlp_backward", "nnsort_loss_ws_floats", "nnsort_loss_grad", "nnsort_adam_step",
+                        "nnsort_fit_gradient_ws_floats", "nnsort_fit_gradient",
                         "nnsort_model_save", "nnsort_model_load", "nnsort_strerror")
             if hasattr(_lib(), n)]
 
@@ -406,6 +409,23 @@ def nnsort_loss_grad(F, y, loss: int = 0, delta: float = 1.0, stream=None):
                                  _stream(stream))
     _check(rc, "nnsort_loss_grad")
     return L, gF
+
+
+def nnsort_fit_gradient(hidden: int, theta, x, y, batch: int, seed: int, step: int, loss: int = 0,
+                        delta: float = 1.0, stream=None):
+    """Gradient and loss of one fit step (the fused kernel nnsort_fit runs for
+    hidden 32 and 64) on a batch drawn from the sample (x float64, y float32);
+    returns (loss tensor [1], gtheta tensor [P])."""
+    torch = _torch()
+    g = torch.empty(theta.numel(), dtype=torch.float32, device=x.device)
+    L = torch.empty(1, dtype=torch.float32, device=x.device)
+    wf = int(_lib().nnsort_fit_gradient_ws_floats(hidden, batch))
+    ws = torch.empty(wf, dtype=torch.float32, device=x.device)
+    rc = _lib().nnsort_fit_gradient(hidden, _ptr(theta), _ptr(x), _ptr(y), x.numel(), int(batch), int(seed),
+                                    int(step), int(loss), float(delta), _ptr(g), _ptr(L), _ptr(ws), wf,
+                                    _stream(stream))
+    _check(rc, "nnsort_fit_gradient")
+    return L, g
 
 
 def nnsort_adam_step(theta, g, m1, m2, t: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnnsort.so")
-SOURCES = ["api.cpp", "infer.hip", "infer_bf16.hip", "infer_pwl.hip", "lsd.hip", "partition.hip", "bucket.hip", "radix.hip", "segsort.hip", "fit.hip"]
+SOURCES = ["api.cpp", "infer.hip", "infer_bf16.hip", "infer_pwl.hip", "lsd.hip", "partition.hip", "bucket.hip", "radix.hip", "segsort.hip", "fit.hip", "fit_mfma.hip"]
 ARCH = os.environ.get("NNSORT_ARCH", "gfx950")
 
 

@@ -86,6 +86,15 @@ hipError_t launch_mlp_backward_adam(int H, float* d_theta, const double* d_x, in
                                     float b1, float b2, float eps, hipStream_t st);
 size_t disorder_ws_doubles();
 hipError_t launch_disorder(const double* d_F, int64_t k, double* d_ws, hipStream_t st);
+bool fit_step_mfma(int H);
+int fit_step_groups(int64_t B);
+hipError_t launch_fit_gradient(int H, const float* d_theta, const double* d_x, const float* d_y, int64_t k,
+                               int64_t B, uint64_t seed, int64_t t, int loss, float delta, float* d_part,
+                               float* d_loss_part, float* d_gtheta, float* d_loss, hipStream_t st);
+hipError_t launch_fit_step_mfma(int H, float* d_theta, const double* d_x, const float* d_y, int64_t k, int64_t B,
+                                uint64_t seed, int64_t t, int loss, float delta, float lr, float b1, float b2,
+                                float eps, float* d_part, float* d_loss_part, float* d_m1, float* d_m2, float* d_best,
+                                float* d_best_loss, float* d_loss, hipStream_t st);
 }  // namespace nns
 
 using namespace nns;
@@ -695,13 +704,20 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
     for (int t = 1; t <= fp->steps; ++t) {
         // the batch, its forward, loss and dL/dF, keeping the parameters if
         // this batch's loss is the lowest so far; then the gradients applied
-        // by one Adam step
-        NNS_HIP(launch_fit_step_forward(H, theta, x, y, (int64_t)k2, fp->seed, t, P.B, bx, saved, fp->loss,
-                                        fp->huber_delta, gF, dloss, lpart, best, Pn, best_loss, st));
+        // by one Adam step.  Widths 32 and 64: one fused kernel on the FP32
+        // matrix cores plus the update; 8 and 16: forward, then backward.
+        if (fit_step_mfma(H)) {
+            NNS_HIP(launch_fit_step_mfma(H, theta, x, y, (int64_t)k2, P.B, fp->seed, t, fp->loss, fp->huber_delta,
+                                         fp->lr, 0.9f, 0.999f, 1e-8f, bws, lpart, m1, m2, best, best_loss, dloss,
+                                         st));
+        } else {
+            NNS_HIP(launch_fit_step_forward(H, theta, x, y, (int64_t)k2, fp->seed, t, P.B, bx, saved, fp->loss,
+                                            fp->huber_delta, gF, dloss, lpart, best, Pn, best_loss, st));
+            NNS_HIP(launch_mlp_backward_adam(H, theta, bx, P.B, saved, gF, bws, m1, m2, t, fp->lr, 0.9f, 0.999f,
+                                             1e-8f, st));
+        }
         if (loss_history && t - 1 < history_len)
             NNS_HIP(hipMemcpyAsync(loss_history + (t - 1), dloss, 4, hipMemcpyDeviceToHost, st));
-        NNS_HIP(launch_mlp_backward_adam(H, theta, bx, P.B, saved, gF, bws, m1, m2, t, fp->lr, 0.9f, 0.999f, 1e-8f,
-                                         st));
     }
     // Returned: the parameters with the lowest batch loss seen, unless they
     // move F backwards along the sorted sample more than the initial ones do
@@ -980,6 +996,25 @@ int nnsort_mlp_backward(int hidden, const float* d_theta, const double* d_x, int
 }
 
 size_t nnsort_loss_ws_floats(void) { return loss_ws_floats(); }
+
+size_t nnsort_fit_gradient_ws_floats(int hidden, int64_t batch) {
+    const int64_t G = fit_step_groups(batch > 0 ? batch : 1);
+    return (size_t)G * (hidden * hidden + 4 * hidden + 1) + 256;
+}
+
+int nnsort_fit_gradient(int hidden, const float* d_theta, const double* d_x, const float* d_y, int64_t k,
+                        int64_t batch, uint64_t seed, int64_t step, int loss, float delta, float* d_gtheta,
+                        float* d_loss, float* d_ws, size_t ws_floats, void* stream) {
+    if (!fit_step_mfma(hidden) || batch < 1 || k < 1 || step < 1 || (loss != 0 && loss != 1)) return NNSORT_EINVAL;
+    if (!d_theta || !d_x || !d_y || !d_gtheta || !d_loss || !d_ws) return NNSORT_EINVAL;
+    if (ws_floats < nnsort_fit_gradient_ws_floats(hidden, batch)) return NNSORT_EWORKSPACE;
+    const int64_t G = fit_step_groups(batch);
+    float* part = d_ws;
+    float* lpart = d_ws + (size_t)G * (hidden * hidden + 4 * hidden + 1);
+    NNS_HIP(launch_fit_gradient(hidden, d_theta, d_x, d_y, k, batch, seed, step, loss, delta, part, lpart, d_gtheta,
+                                d_loss, (hipStream_t)stream));
+    return NNSORT_OK;
+}
 
 int nnsort_loss_grad(const float* d_F, const float* d_y, int64_t batch, int loss, float delta, float* d_gF,
                         float* d_loss, float* d_ws, void* stream) {

@@ -9,35 +9,10 @@
 // deltas, then batch reductions in fixed blocks summed in a fixed order, so a
 // gradient does not depend on scheduling.  This translation unit is compiled
 // with -ffp-contract=off.
-#include "nnsort_internal.h"
+#include "fit_common.h"
 
 namespace nns {
 
-// ---- Philox4x32-10 ----
-__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
-        uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
-        uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-    }
-}
-
-__device__ __forceinline__ uint64_t rand64(uint64_t seed, uint32_t stream, uint64_t a, uint32_t b) {
-    uint32_t c[4] = {(uint32_t)a, (uint32_t)(a >> 32), b, stream};
-    philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-    return (uint64_t)c[0] | ((uint64_t)c[1] << 32);
-}
-
-constexpr uint32_t kStreamSample = 1, kStreamInit = 2, kStreamBatch = 3;
 
 // Sample k keys with replacement; keep the finite ones (order keys) in G.
 // Each workgroup draws kSampleItems x 256 keys and reserves their place in G
@@ -426,20 +401,6 @@ struct FitBatch {
     float* partial;   // out: the loss summed over each workgroup's 64 entries
 };
 
-// Loss of one entry and its dL/dF before the 1/B scale (MSE, or Huber with
-// threshold delta).
-__device__ __forceinline__ float loss_term(float e, int loss, float delta, float& g) {
-    if (loss == 1) {
-        if (fabsf(e) <= delta) {
-            g = e;
-            return 0.5f * e * e;
-        }
-        g = e > 0.0f ? delta : -delta;
-        return delta * fabsf(e) - 0.5f * delta * delta;
-    }
-    g = 2.0f * e;
-    return e * e;
-}
 
 // The same forward pass for the fit, spread over four waves per 64 samples:
 // wave q computes hidden-2 units [q H/4, (q+1) H/4) of its samples (lane =
@@ -751,38 +712,7 @@ __global__ void __launch_bounds__(256) k_bwd_reduce(const float* __restrict__ th
     if (tid == 0) row[4 * H + H * H] = accb3;
 }
 
-// One Adam step of parameter p with gradient gv (bias corrections c1, c2).
-__device__ __forceinline__ void adam_update(int64_t p, float gv, float* th, float* m1, float* m2, float b1, float b2,
-                                            float c1, float c2, float lr, float eps) {
-    float m = b1 * m1[p] + (1.0f - b1) * gv;
-    float v = b2 * m2[p] + (1.0f - b2) * gv * gv;
-    m1[p] = m;
-    m2[p] = v;
-    float mh = m / c1, vh = v / c2;
-    th[p] = th[p] - lr * mh / (sqrtf(vh) + eps);
-}
 
-// Column sums of `part` (rows x P), in a fixed order: kSumCols columns per
-// block, eight groups of rows summed side by side, then the eight group sums
-// in order.  The result is valid in the threads of group 0 (column p).
-constexpr int kSumCols = 32;
-constexpr int kSumUnroll = 8;
-__device__ __forceinline__ float column_sum(const float* __restrict__ part, int rows, int P, int p, int c, int grp,
-                                            float (*s)[kSumCols]) {
-    float acc = 0.0f;
-    if (p < P) {
-#pragma unroll kSumUnroll
-        for (int r = grp; r < rows; r += 8) acc += part[(int64_t)r * P + p];
-    }
-    s[grp][c] = acc;
-    __syncthreads();
-    float t = 0.0f;
-    if (grp == 0) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) t += s[q][c];
-    }
-    return t;
-}
 
 __global__ void __launch_bounds__(8 * kSumCols) k_sum_rows(const float* __restrict__ part, int rows, int P,
                                                            float* out) {

@@ -386,6 +386,43 @@ def test_gradient_vs_fp64_reference(H, loss):
     assert np.linalg.norm(g - gr) <= 1e-4 * np.linalg.norm(gr)
 
 
+@pytest.mark.parametrize("H,loss,B", [(32, 0, 3000), (64, 0, 3000), (64, 1, 4096), (64, 0, 65536)])
+def test_fit_step_gradient_vs_fp64_reference(H, loss, B):
+    """The fit's own step for widths 32 and 64 (one fused kernel on the FP32
+    matrix cores): the batch it draws from the sample (Philox, stream 3) is
+    the oracle's, and its loss and gradient match the oracle's FP64 ones on
+    that batch."""
+    rng = np.random.default_rng(H + B)
+    model = random_model(H, 20 + H)
+    th = torch.from_numpy(model["theta"]).to(DEV)
+    k = 5000
+    x = np.sort(rng.random(k))
+    y = ((np.arange(k) + 0.5) / k).astype(np.float32)
+    seed, step = 17, 5
+    L, g = nn.nnsort_fit_gradient(H, th, torch.from_numpy(x).to(DEV), torch.from_numpy(y).to(DEV), B, seed, step,
+                                  loss=loss, delta=0.05)
+    g = g.cpu().numpy().astype(np.float64)
+    bi = O.batch_indices(seed, step, k, B)
+    Lr, gr = O.loss_grad(model["theta"].astype(np.float64), H, x[bi], y[bi].astype(np.float64), loss, 0.05)
+    assert abs(float(L.item()) - Lr) <= 1e-5 * max(1.0, Lr)
+    assert np.linalg.norm(g - gr) <= 1e-4 * np.linalg.norm(gr), np.linalg.norm(g - gr) / np.linalg.norm(gr)
+
+
+@pytest.mark.parametrize("H", [32, 64])
+def test_fit_mfma_loss_tracks_oracle(H):
+    """A fit that moves (uniform start, lr 1e-2, 30 steps) through the fused
+    step: the first batch loss matches the oracle's to FP32 rounding, the loss
+    halves, and the last loss stays close to the oracle's FP64 fit."""
+    x = W.uniform(100_000, seed=8)
+    fp = nn.fit_params(hidden=H, sample_frac=0.2, batch=2048, steps=30, init=0, lr=1e-2, seed=3)
+    m, hist = nn.nnsort_fit(to_dev(x), fp, history=True)
+    ref, rhist = O.fit(x, H=H, sample_frac=0.2, batch=2048, steps=30, init=0, lr=1e-2, seed=3,
+                       return_history=True)
+    assert abs(hist[0] - rhist[0]) <= 1e-5 * max(1.0, rhist[0])
+    assert hist[-1] < 0.5 * hist[0]
+    assert abs(hist[-1] - rhist[-1]) <= 0.05 * rhist[-1] + 1e-6
+
+
 def test_gradient_vs_finite_differences_through_autograd():
     """torch.autograd through NNSortMLPFn; compared with central differences of
     the FP64 loss of the oracle on parameters away from ReLU kinks."""
