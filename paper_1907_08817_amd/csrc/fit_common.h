@@ -48,14 +48,23 @@ __device__ __forceinline__ float loss_term(float e, int loss, float delta, float
 }
 
 // One Adam step of parameter p with gradient gv (bias corrections c1, c2).
+// The step on one parameter held in registers: (th, m, v) -> updated.
+__device__ __forceinline__ void adam_step(float gv, float& th, float& m1, float& m2, float b1, float b2, float c1,
+                                          float c2, float lr, float eps) {
+    const float m = b1 * m1 + (1.0f - b1) * gv;
+    const float v = b2 * m2 + (1.0f - b2) * gv * gv;
+    m1 = m;
+    m2 = v;
+    const float mh = m / c1, vh = v / c2;
+    th = th - lr * mh / (sqrtf(vh) + eps);
+}
 __device__ __forceinline__ void adam_update(int64_t p, float gv, float* th, float* m1, float* m2, float b1, float b2,
                                             float c1, float c2, float lr, float eps) {
-    float m = b1 * m1[p] + (1.0f - b1) * gv;
-    float v = b2 * m2[p] + (1.0f - b2) * gv * gv;
+    float t = th[p], m = m1[p], v = m2[p];
+    adam_step(gv, t, m, v, b1, b2, c1, c2, lr, eps);
     m1[p] = m;
     m2[p] = v;
-    float mh = m / c1, vh = v / c2;
-    th[p] = th[p] - lr * mh / (sqrtf(vh) + eps);
+    th[p] = t;
 }
 
 // Column sums of `part` (rows x P), in a fixed order: kSumCols columns per
