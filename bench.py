@@ -28,6 +28,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+HEADLINE_METRIC = "sorted Gkeys/s at 1e8 f64 keys, BF16-MFMA vs FP32 NN-sort; % HBM roofline"
+DEFAULT_WORKLOAD = "gauss_mix_1e8_bf16_h64"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 BF16_PEAK_TFLOPS = 2500.0      # dense bf16 MFMA
 FP32_VALU_PEAK_TFLOPS = 157.3  # vector FP32
@@ -38,7 +40,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="gauss_mix_1e8_bf16_h64")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--n", type=int, default=0, help="override the key count (testing only)")
     ap.add_argument("--form", choices=["config", "bf16", "fp32", "pwl"], default="config",
                     help="map form; 'config' takes the workload's (bf16 for the headline workload)")
@@ -58,17 +60,17 @@ def src_sha(paths):
     return h.hexdigest()
 
 
-def load_counters(kernel: str, sha: str) -> dict:
+def load_counters(kernel: str, sha: str, keys: int) -> dict:
     """The committed counter record of `kernel` (HBM bytes and VALU
-    instructions per launch), or {} when absent or taken on a different
-    kernel source."""
+    instructions per launch), or {} when absent, taken on a different kernel
+    source or on a launch of a different size."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
         return {}
     e = d.get(kernel)
-    if not e or e.get("source_sha256") != sha:
+    if not e or e.get("source_sha256") != sha or e.get("keys_per_launch") != keys:
         return {}
     return e
 
@@ -204,7 +206,7 @@ def main():
         # time includes the two launches that compile the pieces
         kname = "k_infer_pwl"
         ctr = load_counters(kname, src_sha(["paper_1907_08817_amd/csrc/infer_pwl.hip",
-                                            "paper_1907_08817_amd/csrc/infer_common.h"]))
+                                            "paper_1907_08817_amd/csrc/infer_common.h"]), n)
         achieved_gbs = 12 * n / (k1_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 5),
@@ -215,7 +217,7 @@ def main():
             f"k_infer_fp32<{64 if H > 32 else 32}>"
         ksha = src_sha(["paper_1907_08817_amd/csrc/infer_bf16.hip" if form == "bf16" else
                         "paper_1907_08817_amd/csrc/infer.hip", "paper_1907_08817_amd/csrc/infer_common.h"])
-        ctr = load_counters(kname, ksha)
+        ctr = load_counters(kname, ksha, n)
         peak = BF16_PEAK_TFLOPS if form == "bf16" else FP32_VALU_PEAK_TFLOPS
         # the matrix-core roofline the metric names, and beside it the vector
         # issue bound that actually limits this kernel (from the committed
@@ -325,7 +327,8 @@ def main():
                "sample": f"first {m} keys of the same workload, same model, {evaluator}; {cpu_s:.1f} s"}
 
     res = {
-        "metric": "sorted Gkeys/s at 1e8 f64 keys, BF16-MFMA vs FP32 NN-sort; % HBM roofline",
+        "metric": HEADLINE_METRIC if (args.workload == DEFAULT_WORKLOAD and n == n_cfg and form == "bf16")
+        else f"sorted Gkeys/s at {n:.0e} {'f64' if dt == nn.F64 else 'u64'} keys, {form} NN-sort ({args.workload})",
         "value": round(value, 4),
         "unit": "Gkeys/s",
         "n_gpus": 1,
