@@ -20,7 +20,10 @@
 //    product is exact there), the two halves' sums added in FP64, so that F
 //    keeps a resolution finer than one slot at n = 1e9.
 // The two lane halves then swap one partial sum, so that lane l ends with F
-// of its own key l; translate, slot and store run once per key.
+// of its own key l; translate, slot and store run once per key.  The two
+// tiles go through each k-step together: one read of the k-step's layer-1
+// weights and W2 operands from LDS serves both (half the LDS traffic of
+// mapping them one after the other, 125 VGPRs at H = 64, 4 waves per SIMD).
 //
 // Scaled operands (the host's bf16_operands()): with every pre-activation of
 // the power-of-two-scaled network at most 1, relu(z) equals clamp(z, 0, 1),
@@ -73,67 +76,96 @@ struct TileOps {
     const double* w3g;  // w3 in accumulator order of this lane half
 };
 
-// This lane's half of the layer-3 sum for key j of a tile whose translated
-// input is (xh, xl): units of lane half g only, b3 included in half 0.
+// The bf16 terms of unit pair q of eight activations (truncation split):
+// term 0 the heads, term 1 the first residuals, term 2 the second.
+template <int T>
+__device__ __forceinline__ void split_terms(const float (&h)[8], u32x4& t0, u32x4& t1, u32x4& t2) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float h0 = h[2 * q], h1 = h[2 * q + 1];
+        t0[q] = pack_hi(h0, h1);
+        if (T >= 2) {
+            const float r0 = h0 - __uint_as_float(__float_as_uint(h0) & 0xFFFF0000u);
+            const float r1 = h1 - __uint_as_float(__float_as_uint(h1) & 0xFFFF0000u);
+            t1[q] = pack_hi(r0, r1);
+            if (T >= 3) {
+                const float q0 = r0 - __uint_as_float(__float_as_uint(r0) & 0xFFFF0000u);
+                const float q1 = r1 - __uint_as_float(__float_as_uint(r1) & 0xFFFF0000u);
+                t2[q] = pack_hi(q0, q1);
+            }
+        }
+    }
+}
+
+// This lane's halves of the layer-3 sums of two tiles, A and B, whose keys'
+// translated inputs are (xa, xla) and (xb, xlb): units of lane half g only,
+// b3 included in half 0.  Each tile's products and sums run in the same order
+// as for a tile alone; the two share every read of the per-unit vectors and
+// of the W2 operands, so a 64-key block costs half the LDS traffic.
 template <int H, int T, bool SCALED>
-__device__ __forceinline__ double tile_half_sum(float xh, float xl, int g, float b3, const TileOps& op,
-                                                const u32x4 (*s_A)[H / 16][64], int lane) {
+__device__ __forceinline__ void pair_half_sums(float xa, float xla, float xb, float xlb, int g, float b3,
+                                               const TileOps& op, const u32x4 (*s_A)[H / 16][64], int lane,
+                                               double& sumA, double& sumB) {
     constexpr int RB = H / 32;  // 32-row blocks of hidden-2 units
     constexpr int KS = H / 16;  // k-steps of 16 hidden-1 units
-    floatx16 acc[RB];
+    // the accumulators start at b2: the first product of each tile takes it
+    // as its C operand
+    floatx16 b2v[RB], accA[RB], accB[RB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) acc[rb][v] = op.b2g[16 * rb + v];
+        for (int v = 0; v < 16; ++v) b2v[rb][v] = op.b2g[16 * rb + v];
 
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-        float h[8];
+        // the k-step's layer-1 weights and W2 operands, read once for both tiles
+        float w[8], c[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            const int u = 16 * s + t;
-            float z = __builtin_fmaf(op.w1g[u], xh, op.b1g[u]);
-            z = __builtin_fmaf(op.w1g[u], xl, z);
-            h[t] = SCALED ? clamp01(z) : (z > 0.0f ? z : 0.0f);
+            w[t] = op.w1g[16 * s + t];
+            c[t] = op.b1g[16 * s + t];
         }
-        u32x4 B0, B1, B2;
-        float r1[8], r2[8];
+        bf16x8 av[RB];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            float hi = __uint_as_float(__float_as_uint(h[t]) & 0xFFFF0000u);
-            r1[t] = h[t] - hi;
-            if (T >= 3) {
-                float mid = __uint_as_float(__float_as_uint(r1[t]) & 0xFFFF0000u);
-                r2[t] = r1[t] - mid;
+        for (int rb = 0; rb < RB; ++rb) av[rb] = as_bf16x8(s_A[rb][s][lane]);
+#pragma unroll
+        for (int tile = 0; tile < 2; ++tile) {
+            const float x0 = tile ? xb : xa, x1 = tile ? xlb : xla;
+            float h[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                float z = __builtin_fmaf(w[t], x0, c[t]);
+                z = __builtin_fmaf(w[t], x1, z);
+                h[t] = SCALED ? clamp01(z) : (z > 0.0f ? z : 0.0f);
             }
-        }
+            u32x4 B0, B1, B2;
+            split_terms<T>(h, B0, B1, B2);
+            floatx16* acc = tile ? accB : accA;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            B0[q] = pack_hi(h[2 * q], h[2 * q + 1]);
-            if (T >= 2) B1[q] = pack_hi(r1[2 * q], r1[2 * q + 1]);
-            if (T >= 3) B2[q] = pack_hi(r2[2 * q], r2[2 * q + 1]);
-        }
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-            const bf16x8 av = as_bf16x8(s_A[rb][s][lane]);
-            acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, as_bf16x8(B0), acc[rb], 0, 0, 0);
-            if (T >= 2) acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, as_bf16x8(B1), acc[rb], 0, 0, 0);
-            if (T >= 3) acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, as_bf16x8(B2), acc[rb], 0, 0, 0);
+            for (int rb = 0; rb < RB; ++rb) {
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rb], as_bf16x8(B0), s == 0 ? b2v[rb] : acc[rb], 0, 0, 0);
+                if (T >= 2) acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rb], as_bf16x8(B1), acc[rb], 0, 0, 0);
+                if (T >= 3) acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rb], as_bf16x8(B2), acc[rb], 0, 0, 0);
+            }
         }
     }
 
     // layer 3: w3 . relu(z2) accumulated in FP64.  A product of two FP32
     // values is exact in FP64, so the sum carries ~2^-53 relative error per
     // step: F keeps a resolution far below one slot at n = 1e9
-    double sum = g == 0 ? (double)b3 : 0.0;
+    double sa = g == 0 ? (double)b3 : 0.0, sb = sa;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            const double h2 = SCALED ? clamp01((double)acc[rb][v]) : (double)relu_bits(acc[rb][v]);
-            sum = __builtin_fma(op.w3g[16 * rb + v], h2, sum);
+            const double w = op.w3g[16 * rb + v];
+            const double ya = SCALED ? clamp01((double)accA[rb][v]) : (double)relu_bits(accA[rb][v]);
+            const double yb = SCALED ? clamp01((double)accB[rb][v]) : (double)relu_bits(accB[rb][v]);
+            sa = __builtin_fma(w, ya, sa);
+            sb = __builtin_fma(w, yb, sb);
         }
-    return sum;
+    sumA = sa;
+    sumB = sb;
 }
 
 template <int H, int T, bool SCALED>
@@ -141,7 +173,7 @@ __global__ void __launch_bounds__(256, 3) k_infer_bf16(InferArgs a) {
     constexpr int RB = H / 32;
     constexpr int KS = H / 16;
     const DevModel* __restrict__ m = a.model;
-    // Per-unit vectors live in LDS and are re-read every tile: held in
+    // Per-unit vectors live in LDS and are re-read every 64 keys: held in
     // registers they would cost 128 VGPRs at H = 64 and cut occupancy to one
     // wave per SIMD, leaving no other wave to cover MFMA and load latency.
     // s_w1 / s_b1 in layer-1 lane order, s_b2 / s_w3 in accumulator order:
@@ -201,10 +233,9 @@ __global__ void __launch_bounds__(256, 3) k_infer_bf16(InferArgs a) {
         // tile A maps keys 0..31 of the block (lane half 0's own keys), tile B
         // keys 32..63: each lane takes the other half's input for one of them
         const float xh_o = other_half(xh), xl_o = other_half(xl);
-        const double sA = tile_half_sum<H, T, SCALED>(g ? xh_o : xh, g ? xl_o : xl, g, b3, op, s_A, lane);
-        // re-read the LDS operands for tile B rather than keep tile A's live
-        __asm__ volatile("" ::: "memory");
-        const double sB = tile_half_sum<H, T, SCALED>(g ? xh : xh_o, g ? xl : xl_o, g, b3, op, s_A, lane);
+        double sA, sB;
+        pair_half_sums<H, T, SCALED>(g ? xh_o : xh, g ? xl_o : xl, g ? xh : xh_o, g ? xl : xl_o, g, b3, op, s_A, lane,
+                                     sA, sB);
         // F of key l: lane half 0 adds half 1's sum of tile A, lane half 1
         // half 0's sum of tile B (the same two terms a sum over both halves
         // of one tile adds)
