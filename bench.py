@@ -241,6 +241,21 @@ def main():
     e2e = {"alg_bytes_per_key": round(alg_bytes / n, 2),
            "achieved_GBs": round(alg_bytes / (ms_per_step * 1e-3) / 1e9, 1),
            "frac_of_8TBs": round(alg_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if not args.copy_calibration:
+        # the same bytes against what a plain device copy of the keys reaches
+        # on this machine (read + write counted), outside the timed region
+        a = torch.empty_like(keys)
+        a.copy_(keys)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            a.copy_(keys)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 2 * 8 * n * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        e2e["copy_GBs"] = round(copy_gbs, 1)
+        e2e["frac_of_copy"] = round(alg_bytes / (ms_per_step * 1e-3) / 1e9 / copy_gbs, 4)
+        del a
 
     context = {}
     if not args.no_context:
