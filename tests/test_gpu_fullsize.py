@@ -210,7 +210,7 @@ def test_fullsize_gauss_mix_1e8_bf16():
     w2_exact = all(O.round_bf16(float(v)) == float(v) for v in md["theta"][2 * H:2 * H + H * H])
     s_dev, _ = nn.nnsort_predict(model, keys, sp, want_F=False)
     got_s = s_dev[torch.from_numpy(idx).to(DEV)].cpu().numpy().astype(np.int64)
-    ref_s = O.predict_slots(xs, md, form=O.FORM_FP32C).astype(np.int64)
+    ref_s = O.slots_from_F(O.eval_F(xh, md, O.FORM_FP32C), 1.25 * x.size).astype(np.int64)
     ds = np.abs(got_s - ref_s)[okm]
     print(f"BF16 vs FP32-form slots on {int(okm.sum())} sampled keys: max |d| {int(ds.max())}, "
           f"equal {np.mean(ds == 0):.6f}; W2 exact in bf16: {w2_exact}")
