@@ -386,12 +386,15 @@ def test_gradient_vs_fp64_reference(H, loss):
     assert np.linalg.norm(g - gr) <= 1e-4 * np.linalg.norm(gr)
 
 
-@pytest.mark.parametrize("H,loss,B", [(32, 0, 3000), (64, 0, 3000), (64, 1, 4096), (64, 0, 65536)])
+@pytest.mark.parametrize("H,loss,B", [(32, 0, 3000), (64, 0, 3000), (64, 1, 4096), (64, 0, 65536),
+                                       (64, 0, 200_003), (32, 1, 100_001)])
 def test_fit_step_gradient_vs_fp64_reference(H, loss, B):
     """The fit's own step for widths 32 and 64 (one fused kernel on the FP32
     matrix cores): the batch it draws from the sample (Philox, stream 3) is
     the oracle's, and its loss and gradient match the oracle's FP64 ones on
-    that batch."""
+    that batch.  Batches past 65,536 entries give each wave several tiles in
+    turn (the next tile's entries are fetched while one is processed), with a
+    ragged last round."""
     rng = np.random.default_rng(H + B)
     model = random_model(H, 20 + H)
     th = torch.from_numpy(model["theta"]).to(DEV)
