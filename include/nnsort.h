@@ -156,8 +156,9 @@ typedef struct {
                                 order, keys without a slot that are not the
                                 extremes).  In both cases the whole output
                                 was then sorted by radix. */
-    int32_t range_resorts;   /* slot ranges whose neighbour-tile merges did not
-                                settle and were re-sorted whole in LDS */
+    int32_t range_resorts;   /* slot ranges sorted whole in LDS: those with a
+                                slot of more than 32 keys, and those whose
+                                neighbour-tile merges did not settle */
     double pos_err;          /* stats_level 2: mean |F(key) n - rank| / n */
     /* stats_level >= 1: t_infer = the map kernel; t_place = the partition of
      * keys by slot range and the gather of dense ranges; t_polish = rounds and

@@ -37,7 +37,7 @@ __device__ __forceinline__ uint32_t range_of(uint32_t slot, uint32_t NB) {
 
 // Counters kept in the workspace (uint64 each).
 enum Counter : int {
-    kCntResorted = 0,     // ranges re-sorted whole after the tile merges
+    kCntResorted = 0,     // ranges sorted whole in LDS (a large slot group, or tile merges that did not settle)
     kCntUnmapped = 1,     // keys with no slot
     kCntCollided = 2,     // [2, 2 + 8): |c_r| for r = 1..8 (all ranges)
     kCntPlaced = 10,      // [10, 18): keys stored in o_r
