@@ -24,11 +24,10 @@ hipError_t launch_big_counts(const uint32_t* d_hist, int64_t big_count, int eps,
                              hipStream_t st);
 size_t polish_part_words(int64_t NB);
 hipError_t launch_polish_small(const int64_t* d_start, int64_t NB, const uint64_t* d_K, const uint32_t* d_S, int eps,
-                               uint64_t* d_out, int64_t base, bool is_f64, uint32_t* d_part, uint64_t* d_counters,
-                               hipStream_t st);
+                               uint64_t* d_out, bool is_f64, uint32_t* d_part, uint64_t* d_counters, hipStream_t st);
 hipError_t launch_polish_half(const int64_t* d_start, const int32_t* d_halflist, int64_t n_half, const uint64_t* d_K,
-                              const uint32_t* d_S, int eps, uint64_t* d_out, int64_t base, bool is_f64,
-                              uint32_t* d_part, uint64_t* d_counters, hipStream_t st);
+                              const uint32_t* d_S, int eps, uint64_t* d_out, bool is_f64, uint32_t* d_part,
+                              uint64_t* d_counters, hipStream_t st);
 hipError_t launch_sum_parts(const uint32_t* d_part, const uint32_t* d_cnt, int64_t NB, int eps, uint64_t* d_counters,
                             hipStream_t st);
 hipError_t launch_boundary_plan(const uint64_t* d_out, bool is_f64, int64_t base, const int64_t* d_start,
@@ -302,7 +301,7 @@ SortPlan plan_sort(int64_t n, double m) {
 namespace {
 
 struct Events {
-    hipEvent_t e[8] = {};
+    hipEvent_t e[10] = {};
     bool on = false;
     hipStream_t st = nullptr;
     explicit Events(bool enable, hipStream_t s) : on(enable), st(s) {
@@ -326,6 +325,34 @@ struct Events {
     }
 };
 
+// Per-thread, per-device pinned host buffer for the mid-sort read of the
+// counters, with an event that marks the copy's arrival: the host then waits
+// for that copy alone while the GPU already polishes the small ranges.  Kept
+// until the process ends.  Null when it cannot be set up; the caller then
+// copies to pageable memory and synchronises the stream.
+constexpr int kMaxDevices = 64;
+struct CounterStage {
+    uint64_t* host = nullptr;
+    hipEvent_t copied = nullptr;
+};
+static thread_local CounterStage t_counter_stage[kMaxDevices];
+
+CounterStage* counter_stage() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    CounterStage& s = t_counter_stage[dev];
+    if (!s.host) {
+        void* p = nullptr;
+        if (hipHostMalloc(&p, kNumCounters * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&s.copied, hipEventDisableTiming) != hipSuccess) {
+            (void)hipHostFree(p);
+            return nullptr;
+        }
+        s.host = (uint64_t*)p;
+    }
+    return &s;
+}
+
 // Conventional sort of everything (no round runs when n <= tau).
 int plain_sort(const void* d_in, void* d_out, int64_t n, bool is_f64, void* d_ws, size_t ws_bytes,
                hipStream_t st) {
@@ -335,9 +362,11 @@ int plain_sort(const void* d_in, void* d_out, int64_t n, bool is_f64, void* d_ws
     return NNSORT_OK;
 }
 
+// allocating = false: the no-allocation entry point (no timing events, and
+// the mid-sort counter read goes to pageable memory).
 int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void* d_in, void* d_out, int64_t n,
               nnsort_dtype dtype, const nnsort_sort_params* prm, void* d_ws, size_t ws_bytes, nnsort_stats* stats,
-              hipStream_t st, bool timers = true) {
+              hipStream_t st, bool allocating = true) {
     if (n < 0 || (n > 0 && (!d_in || !d_out))) return NNSORT_EINVAL;
     if (dtype != NNSORT_F64 && dtype != NNSORT_U64) return NNSORT_EINVAL;
     if (!valid_sort_params(prm, n)) return NNSORT_EINVAL;
@@ -355,7 +384,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     nnsort_stats S{};
     S.n = n;
     S.form = prm->form;
-    Events ev(timers && stats && prm->stats_level >= 1, st);
+    Events ev(allocating && stats && prm->stats_level >= 1, st);
     ev.mark(0);
     if (n == 0) {
         if (stats) *stats = S;
@@ -441,10 +470,36 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     NNS_HIP(launch_classify(start, cnt, P.NB, P.big_max, seglist, bigbucket, halflist, clsum, counters, st));
     NNS_HIP(launch_count_neg(Ks, start, NB, n, counters + kCntUnmappedNeg, st));
     uint64_t c[kNumCounters];
-    NNS_HIP(hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, st));
-    NNS_HIP(hipStreamSynchronize(st));
+    // caller-given slots are checked (counters read back) before any range
+    // is polished: an out-of-range slot leaves the range table inconsistent,
+    // and a polish on it could write outside the output.  The map kernel's
+    // own slots are in range by construction.
+    const bool early_polish = given_slots == nullptr;
+    CounterStage* cs = allocating && early_polish ? counter_stage() : nullptr;
+    if (cs) {
+        NNS_HIP(hipMemcpyAsync(cs->host, counters, sizeof(c), hipMemcpyDeviceToHost, st));
+        NNS_HIP(hipEventRecord(cs->copied, st));
+    } else {
+        NNS_HIP(hipMemcpyAsync(c, counters, sizeof(c), hipMemcpyDeviceToHost, st));
+        NNS_HIP(hipStreamSynchronize(st));
+    }
+    ev.mark(2);
+
+    // ---- rounds + polish of each slot range in LDS, straight to out ----
+    // The ranges of at most half the LDS capacity (nearly all keys) need no
+    // value from the host: they are polished while the host reads the counters
+    // and queues the rest.
+    if (early_polish) NNS_HIP(launch_polish_small(start, P.NB, Ks, Ss, eps, out, is_f64, part, counters, st));
+    ev.mark(8);
+    if (cs) {
+        NNS_HIP(hipEventSynchronize(cs->copied));
+        std::memcpy(c, cs->host, sizeof(c));
+    }
     const int64_t first_unmapped = (int64_t)c[kCntFirstUnmapped];
-    if (c[kCntBadSlot]) return NNSORT_EINVAL;
+    if (c[kCntBadSlot] || (int64_t)c[kCntBigBuckets] > P.big_max) {
+        NNS_HIP(hipStreamSynchronize(st));  // no kernel may still be writing to the caller's buffers
+        return c[kCntBadSlot] ? NNSORT_EINVAL : NNSORT_EINTERNAL;
+    }
     const int64_t big_count = (int64_t)c[kCntBigBuckets];
     const int64_t big_keys = (int64_t)c[kCntBigKeys];
     const int64_t nseg = (int64_t)c[kCntSegments];
@@ -452,7 +507,6 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     const int64_t u_neg = (int64_t)c[kCntUnmappedNeg];
     // G: the keys of ranges too dense for LDS, then the keys without a slot
     const int64_t G_size = big_keys + unm;
-    if (big_count > P.big_max) return NNSORT_EINTERNAL;
 
     // chunks of kBucketCap keys over the dense ranges: at most one partial
     // chunk per range beyond the full ones; the kernels skip chunks past the
@@ -465,12 +519,11 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
         NNS_HIP(launch_big_counts(big_hist, big_count, eps, counters, st));
     }
     if (unm > 0) NNS_HIP(launch_copy_u64(Ks + first_unmapped, G + big_keys, unm, st));
-    ev.mark(2);
-
-    // ---- rounds + polish of each slot range in LDS, straight to out ----
-    NNS_HIP(launch_polish_half(start, halflist, (int64_t)c[kCntHalfFull], Ks, Ss, eps, out, u_neg, is_f64, part,
-                               counters, st));
-    NNS_HIP(launch_polish_small(start, P.NB, Ks, Ss, eps, out, u_neg, is_f64, part, counters, st));
+    ev.mark(9);
+    if (!early_polish) NNS_HIP(launch_polish_small(start, P.NB, Ks, Ss, eps, out, is_f64, part, counters, st));
+    // the ranges above half the LDS capacity, then every range's round counts
+    NNS_HIP(launch_polish_half(start, halflist, (int64_t)c[kCntHalfFull], Ks, Ss, eps, out, is_f64, part, counters,
+                               st));
     NNS_HIP(launch_sum_parts(part, cnt, P.NB, eps, counters, st));
     ev.mark(3);
 
@@ -559,8 +612,11 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     if (ev.on) {
         NNS_HIP(hipEventSynchronize(ev.e[6]));
         S.t_infer_ms = ev.ms(7, 1);  // the map kernel alone
-        S.t_place_ms = ev.ms(1, 2);
-        S.t_polish_ms = ev.ms(2, 3);
+        // the dense-range gather (8 -> 9) runs between the two polish
+        // launches; it counts with the partition, as the hand-off to the
+        // residue path
+        S.t_place_ms = ev.ms(1, 2) + ev.ms(8, 9);
+        S.t_polish_ms = ev.ms(2, 8) + ev.ms(9, 3);
         S.t_residue_ms = ev.ms(3, 4);
         S.t_merge_ms = ev.ms(4, 5);  // the boundary check and repair
         S.t_total_ms = ev.ms(0, 5);
@@ -785,7 +841,6 @@ static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
-constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 void* g_scratch_ptr[kMaxDevices] = {};
 

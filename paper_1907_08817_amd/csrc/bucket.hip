@@ -448,12 +448,15 @@ __device__ bool repair_range(BucketSmem<CAP, NT>& sm, uint32_t cnt, int tid) {
 // two; the LDS a workgroup needs grows with CAP, so ranges of up to half the
 // capacity run in a variant with twice as many workgroups per CU).  K / Sl: the
 // range-partitioned order keys and slots (range b at [start[b], start[b+1]));
-// the range's keys are written as bit patterns to out[base + start[b] ...].
+// the range's keys are written as bit patterns to out[base + start[b] ...],
+// where base, the number of keys without a slot that sort before every mapped
+// key, is read from the counters (so the launch needs no value the host has
+// not yet read back).
 template <int CAP, int LO, int NT>
 __global__ void __launch_bounds__(NT, CAP <= 2048 ? 7 : 4) k_bucket_polish(
     const int64_t* __restrict__ start, const int32_t* __restrict__ list, const uint64_t* __restrict__ K,
-    const uint32_t* __restrict__ Sl, int eps, uint64_t* __restrict__ out, int64_t base, int is_f64,
-    uint32_t* __restrict__ part, unsigned long long* counters) {
+    const uint32_t* __restrict__ Sl, int eps, uint64_t* __restrict__ out, int is_f64, uint32_t* __restrict__ part,
+    unsigned long long* counters) {
     constexpr int kItems = CAP / NT;
     constexpr int kSlotsPer = kBucketSlots / NT;  // slots owned per thread
     __shared__ BucketSmem<CAP, NT> sm;
@@ -466,6 +469,7 @@ __global__ void __launch_bounds__(NT, CAP <= 2048 ? 7 : 4) k_bucket_polish(
     if (cnt <= (uint32_t)LO || cnt > (uint32_t)CAP) return;  // another variant's, or the dense-range path's
     const uint64_t* rk = K + s0;
     const uint32_t* rs = Sl + s0;
+    const int64_t base = (int64_t)counters[kCntUnmappedNeg];
 
     uint64_t key[kItems];
     uint32_t sl[kItems];
@@ -631,12 +635,11 @@ __global__ void __launch_bounds__(NT, CAP <= 2048 ? 7 : 4) k_bucket_polish(
 // Ranges of at most kHalfCap keys: one workgroup per range id (others exit
 // at once).
 hipError_t launch_polish_small(const int64_t* d_start, int64_t NB, const uint64_t* d_K, const uint32_t* d_S, int eps,
-                               uint64_t* d_out, int64_t base, bool is_f64, uint32_t* d_part, uint64_t* d_counters,
-                               hipStream_t st) {
+                               uint64_t* d_out, bool is_f64, uint32_t* d_part, uint64_t* d_counters, hipStream_t st) {
     if (NB <= 0) return hipSuccess;
     static_assert(kBucketCap == 2 * kHalfCap && kHalfCap == 2048, "polish variants");
     hipLaunchKernelGGL((k_bucket_polish<2048, 0, kBucketThreads>), dim3((unsigned)NB), dim3(kBucketThreads), 0, st, d_start,
-                       nullptr, d_K, d_S, eps, d_out, base, is_f64 ? 1 : 0, d_part, (unsigned long long*)d_counters);
+                       nullptr, d_K, d_S, eps, d_out, is_f64 ? 1 : 0, d_part, (unsigned long long*)d_counters);
     return hipGetLastError();
 }
 
@@ -644,12 +647,11 @@ hipError_t launch_polish_small(const int64_t* d_start, int64_t NB, const uint64_
 // twice the threads (its workgroups are few, so each one's latency counts).
 constexpr int kHalfThreads = 512;
 hipError_t launch_polish_half(const int64_t* d_start, const int32_t* d_halflist, int64_t n_half, const uint64_t* d_K,
-                              const uint32_t* d_S, int eps, uint64_t* d_out, int64_t base, bool is_f64,
-                              uint32_t* d_part, uint64_t* d_counters, hipStream_t st) {
+                              const uint32_t* d_S, int eps, uint64_t* d_out, bool is_f64, uint32_t* d_part,
+                              uint64_t* d_counters, hipStream_t st) {
     if (n_half <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_bucket_polish<4096, 2048, kHalfThreads>), dim3((unsigned)n_half), dim3(kHalfThreads), 0, st, d_start,
-                       d_halflist, d_K, d_S, eps, d_out, base, is_f64 ? 1 : 0, d_part,
-                       (unsigned long long*)d_counters);
+                       d_halflist, d_K, d_S, eps, d_out, is_f64 ? 1 : 0, d_part, (unsigned long long*)d_counters);
     return hipGetLastError();
 }
 
