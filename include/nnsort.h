@@ -24,7 +24,10 @@
  *  - The library never allocates device memory: every call that needs scratch
  *    takes a caller-provided workspace d_ws of at least the size that
  *    nnsort_workspace_size() reports, aligned to 256 bytes.  Calls on one
- *    workspace must not overlap.
+ *    workspace must not overlap.  The sorts keep, per host thread and device,
+ *    one 256-byte pinned host buffer (hipHostMalloc) and one event for reading
+ *    back counters mid-sort, until the process ends; the no-allocation entry
+ *    point does not use them.
  *  - Every function returns an nnsort_status; no exception crosses the ABI.
  *    nnsort_strerror() describes a status.  On error the output is
  *    unspecified.
