@@ -182,7 +182,7 @@ int nnsort_workspace_size(int64_t n, nnsort_dtype dtype, const nnsort_sort_param
                           const nnsort_fit_params* fit_params, size_t* bytes);
 
 /* Fit f on the device from a random sample of d_keys[0..n) (Sec. 2,
- * Training): Philox4x32-10 sample with replacement, radix sort of the sample,
+ * Training): Philox4x32-10 sample with replacement, sort of the sample,
  * labels (j + 0.5)/k for the j-th smallest of the k finite sampled keys,
  * lo/inv_range from the sample's extremes, then `steps` Adam steps on
  * batches drawn with replacement.  Writes the model to *out (host): the
@@ -190,7 +190,7 @@ int nnsort_workspace_size(int64_t n, nnsort_dtype dtype, const nnsort_sort_param
  * them moves F backwards along the sorted sample more than with the initial
  * parameters (then those).  Synchronises the stream.  EINVAL: n < 1, null
  * pointers, hidden not 8, 16, 32 or 64, sample_frac <= 0, batch < 1,
- * steps < 0.  EWORKSPACE: d_ws smaller than nnsort_workspace_size() with
+ * steps < 0, sample_frac * n >= 2^32 - 1.  EWORKSPACE: d_ws smaller than nnsort_workspace_size() with
  * these fit parameters, or not 256-byte aligned. */
 int nnsort_fit(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit_params* params,
                nnsort_model* out, void* d_ws, size_t ws_bytes, void* stream);

@@ -66,8 +66,9 @@ hipError_t launch_pos_err_sum(const double* d_F, int64_t n, double* d_sum, hipSt
 // fit
 hipError_t launch_sample(const void* d_in, int64_t n, bool is_f64, uint64_t seed, int64_t k, uint64_t* d_out,
                          uint64_t* d_count, hipStream_t st);
-hipError_t launch_make_xy(const uint64_t* d_sorted, int64_t k, bool is_f64, double lo, double inv, double* d_x,
-                          float* d_y, hipStream_t st);
+hipError_t launch_one_segment(int64_t* d_seg, int64_t nchunks, int64_t k, hipStream_t st);
+hipError_t launch_make_xy(const uint64_t* d_sorted, int64_t k, bool is_f64, double* d_x, float* d_y, double* d_lohi,
+                          hipStream_t st);
 hipError_t launch_init(float* d_theta, int H, int init, uint64_t seed, const double* d_x, int64_t k,
                        int64_t* d_knots, void* d_knotws, hipStream_t st);
 size_t knot_ws_bytes();
@@ -629,7 +630,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
 struct FitPlan {
     int64_t k, B;
     int H;
-    size_t off_init, off_Fs, off_dis, off_best, off_knots, off_knotws, off_sample, off_count, off_x, off_y, off_bx, off_gF, off_saved, off_bws, off_theta,
+    size_t off_init, off_Fs, off_dis, off_best, off_knots, off_knotws, off_sample, off_count, off_seg, off_x, off_y, off_bx, off_gF, off_saved, off_bws, off_theta,
         off_m1, off_m2, off_loss, off_lpart, off_radix, off_model, total;
 };
 
@@ -652,6 +653,7 @@ FitPlan plan_fit(int64_t n, const nnsort_fit_params* fp) {
     };
     p.off_sample = take((size_t)p.k * 8);
     p.off_count = take(64);
+    p.off_seg = take(64);  // the sample as one segment of the chunk sort: chunk and key prefixes
     p.off_x = take((size_t)p.k * 8);
     p.off_y = take((size_t)p.k * 4);
     p.off_bx = take((size_t)p.B * 8);
@@ -675,7 +677,8 @@ FitPlan plan_fit(int64_t n, const nnsort_fit_params* fp) {
     return p;
 }
 
-// The sample is sorted with 32-bit offsets: its size must stay below 2^32 - 1.
+// The fit's sample holds fewer than 2^32 - 1 keys (the bound nnsort_fit
+// documents).
 bool valid_sample_count(int64_t n, const nnsort_fit_params* f) {
     return (double)f->sample_frac * (double)n < 4294967294.0;
 }
@@ -736,21 +739,23 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
         *out = M;
         return NNSORT_OK;
     }
-    NNS_HIP(radix_sort(sample, sample, (int64_t)k2, 0, 0, rws, radix_ws_bytes(P.k), st));
-    uint64_t ends[2];
-    NNS_HIP(hipMemcpyAsync(&ends[0], sample, 8, hipMemcpyDeviceToHost, st));
-    NNS_HIP(hipMemcpyAsync(&ends[1], sample + (k2 - 1), 8, hipMemcpyDeviceToHost, st));
-    NNS_HIP(hipStreamSynchronize(st));
-    auto value_of = [&](uint64_t okey) {
-        if (!is_f64) return (double)okey;
-        uint64_t b = (okey >> 63) ? (okey & 0x7FFFFFFFFFFFFFFFull) : ~okey;
-        double d;
-        std::memcpy(&d, &b, 8);
-        return d;
-    };
-    double lo = value_of(ends[0]), hi = value_of(ends[1]);
-    double inv = hi > lo ? 1.0 / (hi - lo) : 0.0;
-    NNS_HIP(launch_make_xy(sample, (int64_t)k2, is_f64, lo, inv, x, y, st));
+    // the sample sorted as one segment: 4096-key chunks sorted in LDS, then
+    // merge rounds into the radix scratch and back (fewer launches than the
+    // LSD radix sort's 8 passes, and no host read of a digit census)
+    uint64_t* sorted = sample;
+    int64_t* seg = (int64_t*)(ws + P.off_seg);  // chunk prefix {0, nchunks}, key prefix {0, k2}, then (lo, inv)
+    double* lohi = (double*)(seg + 4);
+    {
+        const int64_t nchunks = ((int64_t)k2 + kBigChunk - 1) / kBigChunk;
+        const int rounds = seg_rounds((int64_t)k2, kBigChunk);
+        NNS_HIP(launch_one_segment(seg, nchunks, (int64_t)k2, st));
+        uint64_t* tmp = (uint64_t*)rws;  // radix_ws_bytes(k) >= 8 k
+        NNS_HIP(seg_sort(seg, seg + 2, 1, nchunks, rounds, kBigChunk, sample, tmp, st));
+        if (rounds & 1) sorted = tmp;
+    }
+    // lo and inv_range from the sample's extremes, on the device (read back
+    // with the parameters at the end)
+    NNS_HIP(launch_make_xy(sorted, (int64_t)k2, is_f64, x, y, lohi, st));
     NNS_HIP(launch_init(theta, H, fp->init, fp->seed, x, (int64_t)k2, knots, ws + P.off_knotws, st));
     NNS_HIP(hipMemsetAsync(m1, 0, (size_t)Pn * 4, st));
     NNS_HIP(hipMemsetAsync(m2, 0, (size_t)Pn * 4, st));
@@ -783,7 +788,10 @@ int fit_impl(const void* d_keys, int64_t n, nnsort_dtype dtype, const nnsort_fit
     std::vector<float> cand((size_t)2 * Pn);
     NNS_HIP(hipMemcpyAsync(cand.data(), best, (size_t)Pn * 4, hipMemcpyDeviceToHost, st));
     NNS_HIP(hipMemcpyAsync(cand.data() + Pn, init_theta, (size_t)Pn * 4, hipMemcpyDeviceToHost, st));
+    double lo_inv[2];
+    NNS_HIP(hipMemcpyAsync(lo_inv, lohi, sizeof(lo_inv), hipMemcpyDeviceToHost, st));
     NNS_HIP(hipStreamSynchronize(st));
+    const double lo = lo_inv[0], inv = lo_inv[1];
     auto model_of = [&](const float* th, double lo_, double inv_) {
         nnsort_model m = M;
         m.lo = lo_;

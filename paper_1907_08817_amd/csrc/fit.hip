@@ -60,14 +60,26 @@ __global__ void __launch_bounds__(256) k_sample(const uint64_t* __restrict__ in,
     }
 }
 
-// Training inputs: x_j = clamp((key_j - lo) * inv, 0, 1), y_j = (j + 0.5)/k.
-__global__ void __launch_bounds__(256) k_make_xy(const uint64_t* __restrict__ sorted_okeys, int64_t k,
-                                                 int is_f64, double lo, double inv, double* x, float* y) {
+__device__ __forceinline__ double key_value(uint64_t okey, int is_f64) {
+    const uint64_t bits = order_key_inverse(okey, is_f64);
+    return is_f64 ? __longlong_as_double((long long)bits) : __ull2double_rn(bits);
+}
+
+// Training inputs: x_j = clamp((key_j - lo) * inv, 0, 1), y_j = (j + 0.5)/k,
+// with lo and hi the sample's extremes (its first and last sorted keys) and
+// inv = 1 / (hi - lo) (0 if they are equal); lohi receives (lo, inv) for the
+// model the host returns.
+__global__ void __launch_bounds__(256) k_make_xy(const uint64_t* __restrict__ sorted_okeys, int64_t k, int is_f64,
+                                                 double* x, float* y, double* lohi) {
+    const double lo = key_value(sorted_okeys[0], is_f64), hi = key_value(sorted_okeys[k - 1], is_f64);
+    const double inv = hi > lo ? 1.0 / (hi - lo) : 0.0;
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j == 0) {
+        lohi[0] = lo;
+        lohi[1] = inv;
+    }
     if (j >= k) return;
-    uint64_t bits = order_key_inverse(sorted_okeys[j], is_f64);
-    double v = is_f64 ? __longlong_as_double((long long)bits) : __ull2double_rn(bits);
-    double t = (v - lo) * inv;
+    double t = (key_value(sorted_okeys[j], is_f64) - lo) * inv;
     t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
     x[j] = t;
     y[j] = (float)(((double)j + 0.5) / (double)k);
@@ -792,10 +804,26 @@ hipError_t launch_sample(const void* d_in, int64_t n, bool is_f64, uint64_t seed
     return hipGetLastError();
 }
 
-hipError_t launch_make_xy(const uint64_t* d_sorted, int64_t k, bool is_f64, double lo, double inv, double* d_x,
-                          float* d_y, hipStream_t st) {
-    hipLaunchKernelGGL(k_make_xy, dim3(nblk(k, 256)), dim3(256), 0, st, d_sorted, k, is_f64 ? 1 : 0, lo, inv,
-                       d_x, d_y);
+// The sample as the one segment of the chunk sort: chunk prefix {0, nchunks}
+// and key prefix {0, k}, written by one small launch.
+__global__ void k_one_segment(int64_t* seg, int64_t nchunks, int64_t k) {
+    if (threadIdx.x == 0) {
+        seg[0] = 0;
+        seg[1] = nchunks;
+        seg[2] = 0;
+        seg[3] = k;
+    }
+}
+
+hipError_t launch_one_segment(int64_t* d_seg, int64_t nchunks, int64_t k, hipStream_t st) {
+    hipLaunchKernelGGL(k_one_segment, dim3(1), dim3(64), 0, st, d_seg, nchunks, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_make_xy(const uint64_t* d_sorted, int64_t k, bool is_f64, double* d_x, float* d_y, double* d_lohi,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_make_xy, dim3(nblk(k, 256)), dim3(256), 0, st, d_sorted, k, is_f64 ? 1 : 0, d_x, d_y,
+                       d_lohi);
     return hipGetLastError();
 }
 

@@ -290,6 +290,48 @@ def test_repeat_runs_identical():
         assert sa[k] == sb[k]
 
 
+def test_concurrent_sorts_from_two_threads():
+    """Two host threads sort different inputs at once, each on its own stream
+    and workspace, several times over: every output is exact and the counts
+    are those of a sort run alone (each thread reads its counters back through
+    its own pinned buffer)."""
+    import threading
+    xs = [W.lognormal(700_001, seed=31), W.gauss_mix(500_003, seed=32)]
+    models = [O.fit(x, H=32 if i == 0 else 64, sample_frac=0.01, batch=4096, steps=3) for i, x in enumerate(xs)]
+    alone = [gpu_sort(x, m, form=nn.FORM_BF16) for x, m in zip(xs, models)]
+    sp = nn.sort_params(form=nn.FORM_BF16, stats_level=1)
+    keys = [to_dev(x) for x in xs]
+    outs = [torch.empty_like(k) for k in keys]
+    wss = [nn.alloc_workspace(nn.workspace_size(k.numel(), nn.F64, sp), keys[0].device) for k in keys]
+    ms = [nn.model_from_dict(m) for m in models]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    stats = [[], []]
+    errors = []
+
+    def run(i):
+        try:
+            for _ in range(6):
+                _, st = nn.nnsort_sort_with_model(ms[i], keys[i], out=outs[i], sp=sp, ws=wss[i], stream=streams[i])
+                stats[i].append(st)
+        except Exception as e:  # reported in the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for i, x in enumerate(xs):
+        assert_same_bits(to_host(outs[i], x.dtype), O.sort_reference(x))
+        assert_same_bits(to_host(outs[i], x.dtype), alone[i][0])
+        for st in stats[i]:
+            for k in ("rounds", "collided", "placed", "residue"):
+                assert st[k] == alone[i][1][k], (i, k)
+
+
 @pytest.mark.parametrize("name,n", [("uniform", 1), ("lognormal", 4095), ("gauss_mix", 4097),
                                     ("zipf_u64", 1_000_003), ("uniform", 2_000_000)])
 def test_radix_sort(name, n):
