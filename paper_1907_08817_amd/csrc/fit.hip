@@ -95,21 +95,29 @@ __global__ void __launch_bounds__(256) k_make_xy(const uint64_t* __restrict__ so
 // Each split rescans only the two new pieces.  A scan is spread over
 // kKnotBlocks workgroups per piece, each keeping its first largest deviation
 // (the reduction prefers the larger deviation, then the smaller index, so
-// the result is the first maximum whatever the split into blocks); one small
-// workgroup then applies the split and picks the next piece.  The host
-// launches the scan/update pair H times; once no piece can be split, both
-// return at once.
+// the result is the first maximum whatever the split into blocks).  Split t
+// is one launch: every workgroup first applies the previous scan's result to
+// its own LDS copy of the piece table (all copies come out identical, and
+// workgroup 0 stores its copy for the next launch), then scans its share of
+// the two pieces the table names.  State and partial results alternate
+// between two buffers, so a launch never writes what it reads.  The host
+// launches H steps and a finish that applies the last result; once no piece
+// can be split, the steps only carry the table over.
 constexpr int kKnotBlocks = 256;
 constexpr int kKnotThreads = 256;
 
-struct KnotWork {
+struct KnotState {
     int32_t np, best, done, pad;
     int64_t ra[2], rb[2];  // the two pieces the next scan covers
     int64_t pa[NNSORT_MAX_HIDDEN], pb[NNSORT_MAX_HIDDEN], pj[NNSORT_MAX_HIDDEN];
     double pd[NNSORT_MAX_HIDDEN];
-    double part_d[2][kKnotBlocks];
-    int64_t part_j[2][kKnotBlocks];
 };
+struct KnotWork {
+    KnotState s[2];
+    double part_d[2][2][kKnotBlocks];
+    int64_t part_j[2][2][kKnotBlocks];
+};
+static_assert(sizeof(KnotState) % 8 == 0, "copied as 64-bit words");
 
 size_t knot_ws_bytes() { return sizeof(KnotWork); }
 
@@ -132,24 +140,126 @@ __device__ __forceinline__ void arg_max_reduce(double* s_d, int64_t* s_j) {
     }
 }
 
-__global__ void k_knot_start(int64_t k, KnotWork* w) {
-    if (threadIdx.x != 0) return;
-    w->np = 0;
-    w->best = -1;
-    w->done = 0;
-    w->ra[0] = 0;
-    w->rb[0] = k - 1;
-    w->ra[1] = 0;  // no second piece in the first scan
-    w->rb[1] = 0;
+__device__ __forceinline__ void copy_state(KnotState* dst, const KnotState* src) {
+    const uint64_t* a = (const uint64_t*)src;
+    uint64_t* b = (uint64_t*)dst;
+    for (int i = threadIdx.x; i < (int)(sizeof(KnotState) / 8); i += blockDim.x) b[i] = a[i];
 }
 
-// Block blockIdx.x's share of the points a+1 .. b-1 of piece r = blockIdx.y.
-__global__ void __launch_bounds__(kKnotThreads) k_knot_scan(const double* __restrict__ x, int64_t k, KnotWork* w) {
+__global__ void k_knot_start(int64_t k, KnotWork* w) {
+    if (threadIdx.x != 0) return;
+    KnotState& S = w->s[0];
+    S.np = 0;
+    S.best = -1;
+    S.done = 0;
+    S.ra[0] = 0;
+    S.rb[0] = k - 1;
+    S.ra[1] = 0;  // no second piece in the first scan
+    S.rb[1] = 0;
+}
+
+// Apply a scan's result (per piece r, kKnotBlocks partial (d, j)) to the
+// table S in LDS: the first piece, or the split of the chosen one; then
+// choose the next piece to split: the valid piece (a split point, a positive
+// deviation) of largest deviation, ties to the leftmost start.  Piece starts
+// are distinct, so that order is strict and a butterfly over one wave finds
+// the same piece as a scan in index order.  All kKnotThreads threads call it.
+__device__ void knot_apply(int64_t k, int H, KnotState& S, const double (*part_d)[kKnotBlocks],
+                           const int64_t (*part_j)[kKnotBlocks], double* s_d, int64_t* s_j) {
+    static_assert(kKnotBlocks == kKnotThreads, "one thread per scan block");
+    static_assert(NNSORT_MAX_HIDDEN <= 64, "one lane per piece");
+    __shared__ double r_d[2];
+    __shared__ int64_t r_j[2];
+    if (S.done) return;
+    const int t = threadIdx.x;
+    for (int r = 0; r < 2; ++r) {
+        s_d[t] = part_d[r][t];
+        s_j[t] = part_j[r][t];
+        __syncthreads();
+        arg_max_reduce(s_d, s_j);
+        if (t == 0) {
+            double d = s_d[0];
+            int64_t j = s_j[0];
+            if (!(d > 1.0 / (double)k)) {  // within one rank step of linear: final
+                d = 0.0;
+                j = -1;
+            }
+            r_d[r] = d;
+            r_j[r] = j;
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const int np0 = S.np;
+        int np = np0;
+        if (np == 0) {
+            S.pa[0] = 0;
+            S.pb[0] = k - 1;
+            np = 1;
+        } else {
+            const int bst = S.best;
+            const int64_t b = S.pb[bst], sj = S.pj[bst];
+            S.pb[bst] = sj;
+            S.pa[np] = sj;
+            S.pb[np] = b;
+            S.pd[bst] = r_d[0];
+            S.pj[bst] = r_j[0];
+            ++np;
+        }
+        const int nw = np - 1;  // the new piece (or the first one)
+        S.pd[nw] = r_d[np0 == 0 ? 0 : 1];
+        S.pj[nw] = r_j[np0 == 0 ? 0 : 1];
+        S.np = np;
+    }
+    __syncthreads();
+    if (t < 64) {
+        const int np = S.np;
+        const bool ok = np < H && t < np && S.pj[t] >= 0 && S.pd[t] > 0.0;
+        double d = ok ? S.pd[t] : 0.0;
+        int64_t a = ok ? S.pa[t] : 0;
+        int best = ok ? t : -1;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double d2 = __shfl_xor(d, off);
+            const int64_t a2 = __shfl_xor(a, off);
+            const int b2 = __shfl_xor(best, off);
+            if (b2 >= 0 && (best < 0 || d2 > d || (d2 == d && a2 < a))) {
+                d = d2;
+                a = a2;
+                best = b2;
+            }
+        }
+        if (t == 0) {
+            S.best = best;
+            if (best < 0) {
+                S.done = 1;
+            } else {
+                S.ra[0] = S.pa[best];
+                S.rb[0] = S.pj[best];
+                S.ra[1] = S.pj[best];
+                S.rb[1] = S.pb[best];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Split t: block (blockIdx.x, r = blockIdx.y) applies split t - 1's result
+// (t > 0), then scans its share of the points a+1 .. b-1 of piece r.
+__global__ void __launch_bounds__(kKnotThreads) k_knot_step(const double* __restrict__ x, int64_t k, int H, int t,
+                                                            KnotWork* w) {
+    __shared__ KnotState S;
     __shared__ double s_d[kKnotThreads];
     __shared__ int64_t s_j[kKnotThreads];
-    if (w->done) return;
+    copy_state(&S, &w->s[t == 0 ? 0 : (t - 1) & 1]);
+    __syncthreads();
+    if (t > 0) {
+        knot_apply(k, H, S, w->part_d[(t - 1) & 1], w->part_j[(t - 1) & 1], s_d, s_j);
+        if (blockIdx.x == 0 && blockIdx.y == 0) copy_state(&w->s[t & 1], &S);
+    }
+    if (S.done) return;
     const int r = blockIdx.y;
-    const int64_t a = w->ra[r], b = w->rb[r];
+    const int64_t a = S.ra[r], b = S.rb[r];
     double best = -1.0;
     int64_t bj = -1;
     if (b - a >= 2) {
@@ -172,123 +282,30 @@ __global__ void __launch_bounds__(kKnotThreads) k_knot_scan(const double* __rest
     __syncthreads();
     arg_max_reduce(s_d, s_j);
     if (threadIdx.x == 0) {
-        w->part_d[r][blockIdx.x] = s_d[0];
-        w->part_j[r][blockIdx.x] = s_j[0];
+        w->part_d[t & 1][r][blockIdx.x] = s_d[0];
+        w->part_j[t & 1][r][blockIdx.x] = s_j[0];
     }
 }
 
-// Apply the scan's result (the first piece, or the split of the chosen one)
-// and choose the next piece to split: the valid piece (a split point, a
-// positive deviation) of largest deviation, ties to the leftmost start.  Piece
-// starts are distinct, so that order is strict and a butterfly over one wave
-// finds the same piece as a scan in index order.
-__global__ void __launch_bounds__(kKnotBlocks) k_knot_update(int64_t k, int H, KnotWork* w) {
-    static_assert(kKnotBlocks == kKnotThreads, "one thread per scan block");
-    static_assert(NNSORT_MAX_HIDDEN <= 64, "one lane per piece");
+// The last split's result applied (after steps 0 .. H - 1), then the piece
+// starts in ascending order (distinct: each piece begins where its left
+// neighbour ends) and the last sample index.
+__global__ void __launch_bounds__(kKnotThreads) k_knot_finish(int64_t k, int H, KnotWork* __restrict__ w,
+                                                              int64_t* knots) {
+    __shared__ KnotState S;
     __shared__ double s_d[kKnotThreads];
     __shared__ int64_t s_j[kKnotThreads];
-    __shared__ double r_d[2];
-    __shared__ int64_t r_j[2];
-    __shared__ int64_t c_a[NNSORT_MAX_HIDDEN], c_j[NNSORT_MAX_HIDDEN];
-    __shared__ double c_d[NNSORT_MAX_HIDDEN];
-    __shared__ int s_np;
-    if (w->done) return;
-    const int t = threadIdx.x;
-    for (int r = 0; r < 2; ++r) {
-        s_d[t] = w->part_d[r][t];
-        s_j[t] = w->part_j[r][t];
-        __syncthreads();
-        arg_max_reduce(s_d, s_j);
-        if (t == 0) {
-            double d = s_d[0];
-            int64_t j = s_j[0];
-            if (!(d > 1.0 / (double)k)) {  // within one rank step of linear: final
-                d = 0.0;
-                j = -1;
-            }
-            r_d[r] = d;
-            r_j[r] = j;
-        }
-        __syncthreads();
-    }
-    const int np0 = w->np;
-    if (t < np0) {
-        c_a[t] = w->pa[t];
-        c_j[t] = w->pj[t];
-        c_d[t] = w->pd[t];
-    }
-    __syncthreads();
-    if (t == 0) {
-        int np = np0;
-        if (np == 0) {
-            w->pa[0] = 0;
-            w->pb[0] = k - 1;
-            c_a[0] = 0;
-            np = 1;
-        } else {
-            const int bst = w->best;
-            const int64_t b = w->pb[bst], sj = c_j[bst];
-            w->pb[bst] = sj;
-            w->pa[np] = sj;
-            w->pb[np] = b;
-            c_a[np] = sj;
-            c_d[bst] = r_d[0];
-            c_j[bst] = r_j[0];
-            w->pd[bst] = r_d[0];
-            w->pj[bst] = r_j[0];
-            ++np;
-        }
-        const int nw = np - 1;  // the new piece (or the first one)
-        c_d[nw] = r_d[np0 == 0 ? 0 : 1];
-        c_j[nw] = r_j[np0 == 0 ? 0 : 1];
-        w->pd[nw] = c_d[nw];
-        w->pj[nw] = c_j[nw];
-        w->np = np;
-        s_np = np;
-    }
-    __syncthreads();
-    if (t >= 64) return;
-    const int np = s_np;
-    bool ok = np < H && t < np && c_j[t] >= 0 && c_d[t] > 0.0;
-    double d = ok ? c_d[t] : 0.0;
-    int64_t a = ok ? c_a[t] : 0;
-    int best = ok ? t : -1;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const double d2 = __shfl_xor(d, off);
-        const int64_t a2 = __shfl_xor(a, off);
-        const int b2 = __shfl_xor(best, off);
-        if (b2 >= 0 && (best < 0 || d2 > d || (d2 == d && a2 < a))) {
-            d = d2;
-            a = a2;
-            best = b2;
-        }
-    }
-    if (t != 0) return;
-    w->best = best;
-    if (best < 0) {
-        w->done = 1;
-    } else {
-        w->ra[0] = c_a[best];
-        w->rb[0] = c_j[best];
-        w->ra[1] = c_j[best];
-        w->rb[1] = w->pb[best];
-    }
-}
-
-// Starts in ascending order (they are distinct: each piece begins where its
-// left neighbour ends), then the last sample index.  One thread per piece
-// (128 threads cover the H + 1 <= 65 outputs).
-__global__ void __launch_bounds__(128) k_knot_finish(int64_t k, int H, const KnotWork* __restrict__ w,
-                                                     int64_t* knots) {
     __shared__ int64_t s_st[NNSORT_MAX_HIDDEN];
-    const int n = w->np;
+    copy_state(&S, &w->s[(H - 1) & 1]);
+    __syncthreads();
+    knot_apply(k, H, S, w->part_d[(H - 1) & 1], w->part_j[(H - 1) & 1], s_d, s_j);
+    const int n = S.np;
     const int t = threadIdx.x;
     if (t < n) {
-        const int64_t v = w->pa[t];
-        int r = 0;
-        for (int i = 0; i < n; ++i) r += w->pa[i] < v ? 1 : 0;
-        s_st[r] = v;
+        const int64_t v = S.pa[t];
+        int rk = 0;
+        for (int i = 0; i < n; ++i) rk += S.pa[i] < v ? 1 : 0;
+        s_st[rk] = v;
     }
     __syncthreads();
     if (t <= H) knots[t] = t < n ? s_st[t] : k - 1;
@@ -832,11 +849,9 @@ hipError_t launch_init(float* d_theta, int H, int init, uint64_t seed, const dou
     if (init == 1) {
         KnotWork* w = (KnotWork*)d_knotws;
         hipLaunchKernelGGL(k_knot_start, dim3(1), dim3(64), 0, st, k, w);
-        for (int it = 0; it < H; ++it) {  // the first piece, then at most H - 1 splits
-            hipLaunchKernelGGL(k_knot_scan, dim3(kKnotBlocks, 2), dim3(kKnotThreads), 0, st, d_x, k, w);
-            hipLaunchKernelGGL(k_knot_update, dim3(1), dim3(kKnotBlocks), 0, st, k, H, w);
-        }
-        hipLaunchKernelGGL(k_knot_finish, dim3(1), dim3(128), 0, st, k, H, (const KnotWork*)w, d_knots);
+        for (int it = 0; it < H; ++it)  // the first piece, then at most H - 1 splits
+            hipLaunchKernelGGL(k_knot_step, dim3(kKnotBlocks, 2), dim3(kKnotThreads), 0, st, d_x, k, H, it, w);
+        hipLaunchKernelGGL(k_knot_finish, dim3(1), dim3(kKnotThreads), 0, st, k, H, w, d_knots);
     } else if (init == 2)
         hipLaunchKernelGGL(k_quantile_knots, dim3(1), dim3(128), 0, st, k, H, d_knots);
     hipLaunchKernelGGL(k_init, dim3(nblk(H * H + 4 * H + 1, 256)), dim3(256), 0, st, d_theta, H, init, seed,
