@@ -25,9 +25,12 @@
  *    takes a caller-provided workspace d_ws of at least the size that
  *    nnsort_workspace_size() reports, aligned to 256 bytes.  Calls on one
  *    workspace must not overlap.  The sorts keep, per host thread and device,
- *    one 256-byte pinned host buffer (hipHostMalloc) and one event for reading
- *    back counters mid-sort, until the process ends; the no-allocation entry
- *    point does not use them.
+ *    until the process ends: a 256-byte pinned host buffer (hipHostMalloc) and
+ *    an event for reading back counters mid-sort, a pinned copy of the device
+ *    model (about 35 KB) and an event for its upload, and twenty timing
+ *    events; and per host thread the last model they prepared (about 52 KB
+ *    of host memory), reused when the next model has the same bytes.  The
+ *    no-allocation entry point uses none of them.
  *  - Every function returns an nnsort_status; no exception crosses the ABI.
  *    nnsort_strerror() describes a status.  On error the output is
  *    unspecified.
