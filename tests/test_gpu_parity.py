@@ -554,6 +554,40 @@ def test_model_fitted_on_other_data(noise):
         assert st[k] == ost[k], (k, st[k], ost[k])
 
 
+def test_models_alternating_on_one_thread():
+    """The library prepares each model's device form on the host and keeps the
+    last one per thread, reusing it when the next model has the same bytes.
+    Sorts that alternate between two models, and one whose weight is changed
+    in place in the same C struct, must each see their own model: every
+    call's round counts equal the oracle's for the model of that call."""
+    x = W.gauss_mix(150_003, seed=4)
+    mA = O.fit(x, H=32, sample_frac=0.02, batch=4096, steps=3)
+    mB = O.fit(x, H=32, sample_frac=0.05, batch=4096, steps=3, seed=7)
+    refs = {}
+    for name, md in (("A", mA), ("B", mB)):
+        ref, ost = O.nnsort(x, md)
+        refs[name] = (ref, ost)
+    assert refs["A"][1]["collided"] != refs["B"][1]["collided"], "the two models must differ in their counts"
+    keys = to_dev(x)
+    sp = nn.sort_params(stats_level=1)
+    cA, cB = nn.model_from_dict(mA), nn.model_from_dict(mB)
+    for name, cm in (("A", cA), ("B", cB), ("A", cA), ("B", cB)):
+        out, st = nn.nnsort_sort_with_model(cm, keys, sp=sp)
+        torch.cuda.synchronize()
+        ref, ost = refs[name]
+        assert_same_bits(to_host(out, x.dtype), ref)
+        assert st["collided"] == ost["collided"], (name, st["collided"], ost["collided"])
+    # one weight changed in place: same struct, new bytes
+    mC = dict(mA, theta=mA["theta"].copy())
+    mC["theta"][5] = np.float32(mC["theta"][5] * 1.5)  # w1 of hidden unit 5
+    cA.w1[5] = float(mC["theta"][5])
+    ref, ost = O.nnsort(x, mC)
+    out, st = nn.nnsort_sort_with_model(cA, keys, sp=sp)
+    torch.cuda.synchronize()
+    assert_same_bits(to_host(out, x.dtype), ref)
+    assert st["collided"] == ost["collided"], (st["collided"], ost["collided"])
+
+
 @pytest.mark.parametrize("batch,delta", [(128, 0.01), (4096, 0.05)])
 def test_huber_fit_tracks_oracle(batch, delta):
     """The paper's training recipe (Sec. 4.1, Eq. (loss)): Huber loss, small
