@@ -366,9 +366,26 @@ __device__ __forceinline__ uint32_t half_of(uint32_t word, uint32_t s) { return 
 // by merge path where its 8 outputs begin in the two runs it merges, merges
 // them into registers, and writes them back after a barrier: 9 rounds for
 // 4096 keys, against 78 barrier-separated stages of a bitonic sort.
+//
+// Between the first and the last write the keys sit in a swizzled layout
+// (key i at swz(i)), so that threads reading or writing 8 consecutive keys
+// start in different LDS banks; the range leaves in the plain layout.
+__device__ __forceinline__ int swz(int i) { return i ^ ((i >> 4) & 15); }
+
+__device__ __forceinline__ int merge_split_swz(const uint64_t* s, int pa, int na, int pb, int nb, int diag) {
+    int lo = diag > nb ? diag - nb : 0;
+    int hi = diag < na ? diag : na;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (s[swz(pa + mid)] <= s[swz(pb + diag - 1 - mid)]) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 template <int CAP, int NT>
 __device__ void sort_range(BucketSmem<CAP, NT>& sm, uint32_t cnt, int tid) {
-    static_assert(CAP == 8 * NT, "8 keys per thread");
+    static_assert(CAP == 8 * NT && CAP > 8 && CAP % 16 == 0, "8 keys per thread, at least one merge round");
     for (int i = (int)cnt + tid; i < CAP; i += NT) sm.keys[i] = ~0ull;
     __syncthreads();
     const int pos = 8 * tid;
@@ -376,24 +393,28 @@ __device__ void sort_range(BucketSmem<CAP, NT>& sm, uint32_t cnt, int tid) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) v[q] = sm.keys[pos + q];
     sort8(v);
+    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sm.keys[pos + q] = v[q];
+    for (int q = 0; q < 8; ++q) sm.keys[swz(pos + q)] = v[q];
     __syncthreads();
     for (int w = 8; w < CAP; w <<= 1) {
         const int base = pos & ~(2 * w - 1);  // the pair of runs [base, base + w), [base + w, base + 2w)
-        const uint64_t* A = sm.keys + base;
-        const uint64_t* B = A + w;
+        const int pb = base + w;
         const int d = pos - base;
-        int i = merge_split(A, w, B, w, d);
+        int i = merge_split_swz(sm.keys, base, w, pb, w, d);
         int j = d - i;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const bool take_a = j >= w || (i < w && A[i] <= B[j]);  // ties to A, as merge_split counts them
-            v[q] = take_a ? A[i++] : B[j++];
+            // ties to A, as merge_split counts them; an exhausted run is not read
+            const bool take_a = j >= w || (i < w && sm.keys[swz(base + i)] <= sm.keys[swz(pb + j)]);
+            v[q] = take_a ? sm.keys[swz(base + i)] : sm.keys[swz(pb + j)];
+            i += take_a ? 1 : 0;
+            j += take_a ? 0 : 1;
         }
         __syncthreads();
+        const bool last = 2 * w >= CAP;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sm.keys[pos + q] = v[q];
+        for (int q = 0; q < 8; ++q) sm.keys[last ? pos + q : swz(pos + q)] = v[q];
         __syncthreads();
     }
 }

@@ -15,9 +15,13 @@
 //     than L = run0 2^r, the sorted runs of length L are merged in pairs
 //     (merge path: each workgroup writes one chunk of output; a wave finds
 //     where the chunk starts in the two runs by a 64-way search, then the
-//     chunk's inputs are staged in LDS and every thread merges 16 outputs).
-//     Round r reads one buffer and writes the other; a segment that takes R
-//     rounds ends in buffer R mod 2 (G for even R).
+//     chunk's inputs are staged in LDS and every thread merges 16 outputs
+//     into registers, which go back through LDS to be written out in
+//     wave-contiguous order).  Round r reads one buffer and writes the other;
+//     a segment that takes R rounds ends in buffer R mod 2 (G for even R).
+// Where every thread reads or writes 8 or 16 consecutive keys in LDS, the
+// index is swizzled (swz) so that neighbouring threads start in different
+// banks.
 #include "nnsort_internal.h"
 
 namespace nns {
@@ -90,6 +94,25 @@ __device__ __forceinline__ void cswap(uint64_t& a, uint64_t& b) {
     a = lo;
 }
 
+// LDS index of key i of a sorted run: the low four bits XORed with bits 4..7,
+// a permutation within each 16-key row.  A thread's 8 consecutive keys
+// (i = 8 t + r) then start in different banks for neighbouring threads, which
+// the plain layout maps onto the same two banks.
+__device__ __forceinline__ int swz(int i) { return i ^ ((i >> 4) & 15); }
+
+// split_lds over runs held in swizzled LDS: A at s[swz(pa + i)], B at
+// s[swz(pq + j)].
+__device__ __forceinline__ int split_lds_swz(const uint64_t* s, int pa, int na, int pq, int nb, int d) {
+    int lo = d > nb ? d - nb : 0;
+    int hi = d < na ? d : na;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s[swz(pa + mid)] <= s[swz(pq + d - mid - 1)]) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 template <int RUN>
 __global__ void __launch_bounds__(RUN / kSortPer) k_seg_sort_chunk(const int64_t* __restrict__ chunk_pref,
                                                                   const int64_t* __restrict__ gpref, int64_t nseg,
@@ -109,12 +132,12 @@ __global__ void __launch_bounds__(RUN / kSortPer) k_seg_sort_chunk(const int64_t
     const int tid = threadIdx.x;
     // padding with the largest order key: a real key of that value is the
     // same bit pattern, so the first cnt outputs are right either way
-    for (int i = tid; i < RUN; i += kThreads) s[i] = i < cnt ? p[i] : ~0ull;
+    for (int i = tid; i < RUN; i += kThreads) s[swz(i)] = i < cnt ? p[i] : ~0ull;
     __syncthreads();
     const int base = tid * kSortPer;
     uint64_t v[kSortPer];
 #pragma unroll
-    for (int r = 0; r < kSortPer; ++r) v[r] = s[base + r];
+    for (int r = 0; r < kSortPer; ++r) v[r] = s[swz(base + r)];
     cswap(v[0], v[2]); cswap(v[1], v[3]); cswap(v[4], v[6]); cswap(v[5], v[7]);
     cswap(v[0], v[4]); cswap(v[1], v[5]); cswap(v[2], v[6]); cswap(v[3], v[7]);
     cswap(v[0], v[1]); cswap(v[2], v[3]); cswap(v[4], v[5]); cswap(v[6], v[7]);
@@ -123,20 +146,19 @@ __global__ void __launch_bounds__(RUN / kSortPer) k_seg_sort_chunk(const int64_t
     cswap(v[1], v[2]); cswap(v[3], v[4]); cswap(v[5], v[6]);
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kSortPer; ++r) s[base + r] = v[r];
+    for (int r = 0; r < kSortPer; ++r) s[swz(base + r)] = v[r];
     __syncthreads();
     for (int run = kSortPer; run < RUN; run <<= 1) {
         const int pb = base & ~(2 * run - 1);  // this thread's pair of runs
-        const uint64_t* A = s + pb;
-        const uint64_t* Bq = A + run;
+        const int pa = pb, pq = pb + run;  // first keys of runs A and B
         const int d = base - pb;
-        int ia = split_lds(A, run, Bq, run, d);
+        int ia = split_lds_swz(s, pa, run, pq, run, d);
         int ib = d - ia;
 #pragma unroll
         for (int r = 0; r < kSortPer; ++r) {
             // both heads read in bounds (an exhausted run's last key, unused)
-            const uint64_t a = A[ia < run ? ia : run - 1];
-            const uint64_t b = Bq[ib < run ? ib : run - 1];
+            const uint64_t a = s[swz(pa + (ia < run ? ia : run - 1))];
+            const uint64_t b = s[swz(pq + (ib < run ? ib : run - 1))];
             const bool takeA = ib >= run || (ia < run && a <= b);
             v[r] = takeA ? a : b;
             ia += takeA ? 1 : 0;
@@ -144,10 +166,10 @@ __global__ void __launch_bounds__(RUN / kSortPer) k_seg_sort_chunk(const int64_t
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < kSortPer; ++r) s[base + r] = v[r];
+        for (int r = 0; r < kSortPer; ++r) s[swz(base + r)] = v[r];
         __syncthreads();
     }
-    for (int i = tid; i < cnt; i += kThreads) p[i] = s[i];
+    for (int i = tid; i < cnt; i += kThreads) p[i] = s[swz(i)];
 }
 
 __global__ void __launch_bounds__(kMergeThreads) k_seg_merge(const int64_t* __restrict__ chunk_pref,
@@ -188,19 +210,34 @@ __global__ void __launch_bounds__(kMergeThreads) k_seg_merge(const int64_t* __re
     const uint64_t* Bw = B + (d0 - i0);
     for (int e = tid; e < la + lb; e += kMergeThreads) s[e] = e < la ? Aw[e] : Bw[e - la];
     __syncthreads();
+    // each thread merges kMergePer outputs into registers; they go back to
+    // LDS (swizzled against bank conflicts) and out in wave-contiguous order
+    const int tot = la + lb;
     const int t0 = tid * kMergePer;
-    if (t0 >= la + lb) return;
-    const uint64_t* sa = s;
-    const uint64_t* sb = s + la;
-    int ia = split_lds(sa, la, sb, lb, t0);
-    int ib = t0 - ia;
-    const int t1 = t0 + kMergePer < la + lb ? t0 + kMergePer : la + lb;
-    for (int t = t0; t < t1; ++t) {
-        const bool takeA = ib >= lb || (ia < la && sa[ia] <= sb[ib]);
-        O[d0 + t] = takeA ? sa[ia] : sb[ib];
-        ia += takeA ? 1 : 0;
-        ib += takeA ? 0 : 1;
+    uint64_t v[kMergePer];
+    if (t0 < tot) {
+        const uint64_t* sa = s;
+        const uint64_t* sb = s + la;
+        int ia = split_lds(sa, la, sb, lb, t0);
+        int ib = t0 - ia;
+#pragma unroll
+        for (int k = 0; k < kMergePer; ++k) {
+            if (t0 + k < tot) {
+                const bool takeA = ib >= lb || (ia < la && sa[ia] <= sb[ib]);
+                v[k] = takeA ? sa[ia] : sb[ib];
+                ia += takeA ? 1 : 0;
+                ib += takeA ? 0 : 1;
+            }
+        }
     }
+    __syncthreads();
+    if (t0 < tot) {
+#pragma unroll
+        for (int k = 0; k < kMergePer; ++k)
+            if (t0 + k < tot) s[swz(t0 + k)] = v[k];
+    }
+    __syncthreads();
+    for (int e = tid; e < tot; e += kMergeThreads) O[d0 + e] = s[swz(e)];
 }
 
 int seg_rounds(int64_t max_len, int64_t run0) {
