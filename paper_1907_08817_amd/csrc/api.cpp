@@ -335,8 +335,12 @@ hipEvent_t* event_pool(int set) {
     EventPool& p = t_event_pool[dev];
     if (!p.ready) {
         hipEvent_t* all = &p.e[0][0];
+        // timing only: no system-scope cache writeback at each record, which
+        // otherwise leaves the GPU idle for several microseconds between the
+        // kernels around it (the host reads these events' times only after
+        // the stream has been synchronised)
         for (int i = 0; i < 2 * kNumEvents; ++i)
-            if (hipEventCreate(&all[i]) != hipSuccess) {
+            if (hipEventCreateWithFlags(&all[i], hipEventDisableSystemFence) != hipSuccess) {
                 for (int j = 0; j < i; ++j) (void)hipEventDestroy(all[j]);
                 return nullptr;
             }
