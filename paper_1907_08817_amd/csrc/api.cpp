@@ -417,11 +417,14 @@ const DevModel* prepared_model(const nnsort_model* m) {
     return &t->dev;
 }
 
-// Per-thread, per-device pinned host copy of the device model, so that its
-// upload is a plain DMA; an event marks the upload's end, which the next
-// call on the thread waits for before it writes the buffer again.
+// Per-thread, per-device pinned host copy of the device model, read into
+// the workspace by a copy kernel on the call's stream (a copy engine's
+// transfer would add tens of microseconds of latency before the map kernel);
+// an event marks the copy's end, which the next call on the thread waits for
+// before it writes the buffer again.
 struct ModelStage {
     DevModel* host = nullptr;
+    const uint64_t* dev_view = nullptr;  // the buffer's device address
     hipEvent_t done = nullptr;
     bool pending = false;
 };
@@ -433,12 +436,15 @@ ModelStage* model_stage() {
     ModelStage& s = t_model_stage[dev];
     if (!s.host) {
         void* p = nullptr;
+        void* dp = nullptr;
         if (hipHostMalloc(&p, sizeof(DevModel), hipHostMallocDefault) != hipSuccess) return nullptr;
-        if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
+        if (hipHostGetDevicePointer(&dp, p, 0) != hipSuccess ||
+            hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
             (void)hipHostFree(p);
             return nullptr;
         }
         s.host = (DevModel*)p;
+        s.dev_view = (const uint64_t*)dp;
     }
     return &s;
 }
@@ -466,7 +472,8 @@ hipError_t upload_model(const nnsort_model* m, DevModel* dmodel, bool allocating
         ms->pending = false;
     }
     std::memcpy(ms->host, dev, sizeof(DevModel));
-    hipError_t e = hipMemcpyAsync(dmodel, ms->host, sizeof(DevModel), hipMemcpyHostToDevice, st);
+    static_assert(sizeof(DevModel) % 8 == 0, "copied in 8-byte words");
+    hipError_t e = launch_copy_u64(ms->dev_view, (uint64_t*)dmodel, (int64_t)(sizeof(DevModel) / 8), st);
     if (e != hipSuccess) return e;
     e = hipEventRecord(ms->done, st);
     ms->pending = e == hipSuccess;
