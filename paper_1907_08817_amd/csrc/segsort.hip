@@ -80,13 +80,16 @@ __device__ __forceinline__ int split_lds(const uint64_t* A, int na, const uint64
 
 // Block merge sort of one run of RUN keys (RUN / kBigChunk chunks, starting at
 // a chunk whose index in its segment is a multiple of that).  Each thread
-// sorts 8 keys in registers
-// with a 19-comparator network (Batcher's odd-even merge sort for 8 inputs);
-// then runs of 8, 16, ..., RUN / 2 keys are merged in pairs in LDS: at every
-// level a thread finds where its 8 outputs start in its pair of runs (merge
-// path, ties from the left run) and merges them in registers.  Global memory
-// is read and written in wave-contiguous order through LDS.
-constexpr int kSortPer = 8;
+// sorts P keys in registers (P = 8: a 19-comparator network, Batcher's
+// odd-even merge sort for 8 inputs; P = 16: that network on both halves, then
+// a bitonic merge of the two); then runs of P, 2P, ..., RUN / 2 keys are
+// merged in pairs in LDS: at every level a thread finds where its P outputs
+// start in its pair of runs (merge path, ties from the left run) and merges
+// them in registers.  Global memory is read and written in wave-contiguous
+// order through LDS.  P = 16 for two-chunk runs (one LDS level fewer, and
+// half as many merge-path searches; the runs are that long only when dense
+// keys fill the GPU), 8 for one-chunk runs (twice the threads for few keys).
+constexpr int kSortPerRun(int run) { return run >= 8192 ? 16 : 8; }
 
 __device__ __forceinline__ void cswap(uint64_t& a, uint64_t& b) {
     const uint64_t lo = a < b ? a : b;
@@ -113,7 +116,7 @@ __device__ __forceinline__ int split_lds_swz(const uint64_t* s, int pa, int na, 
     return lo;
 }
 
-template <int RUN>
+template <int RUN, int kSortPer = kSortPerRun(RUN)>
 __global__ void __launch_bounds__(RUN / kSortPer) k_seg_sort_chunk(const int64_t* __restrict__ chunk_pref,
                                                                   const int64_t* __restrict__ gpref, int64_t nseg,
                                                                   uint64_t* G) {
@@ -138,12 +141,30 @@ __global__ void __launch_bounds__(RUN / kSortPer) k_seg_sort_chunk(const int64_t
     uint64_t v[kSortPer];
 #pragma unroll
     for (int r = 0; r < kSortPer; ++r) v[r] = s[swz(base + r)];
-    cswap(v[0], v[2]); cswap(v[1], v[3]); cswap(v[4], v[6]); cswap(v[5], v[7]);
-    cswap(v[0], v[4]); cswap(v[1], v[5]); cswap(v[2], v[6]); cswap(v[3], v[7]);
-    cswap(v[0], v[1]); cswap(v[2], v[3]); cswap(v[4], v[5]); cswap(v[6], v[7]);
-    cswap(v[2], v[4]); cswap(v[3], v[5]);
-    cswap(v[1], v[4]); cswap(v[3], v[6]);
-    cswap(v[1], v[2]); cswap(v[3], v[4]); cswap(v[5], v[6]);
+#pragma unroll
+    for (int h = 0; h < kSortPer; h += 8) {
+        cswap(v[h + 0], v[h + 2]); cswap(v[h + 1], v[h + 3]); cswap(v[h + 4], v[h + 6]); cswap(v[h + 5], v[h + 7]);
+        cswap(v[h + 0], v[h + 4]); cswap(v[h + 1], v[h + 5]); cswap(v[h + 2], v[h + 6]); cswap(v[h + 3], v[h + 7]);
+        cswap(v[h + 0], v[h + 1]); cswap(v[h + 2], v[h + 3]); cswap(v[h + 4], v[h + 5]); cswap(v[h + 6], v[h + 7]);
+        cswap(v[h + 2], v[h + 4]); cswap(v[h + 3], v[h + 5]);
+        cswap(v[h + 1], v[h + 4]); cswap(v[h + 3], v[h + 6]);
+        cswap(v[h + 1], v[h + 2]); cswap(v[h + 3], v[h + 4]); cswap(v[h + 5], v[h + 6]);
+    }
+    if (kSortPer == 16) {
+        // the two sorted halves as one bitonic sequence (second half
+        // reversed), then half-cleaners at distances 8, 4, 2, 1
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint64_t t = v[8 + i];
+            v[8 + i] = v[15 - i];
+            v[15 - i] = t;
+        }
+#pragma unroll
+        for (int dd = 8; dd > 0; dd >>= 1)
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if ((i & dd) == 0) cswap(v[i], v[i | dd]);
+    }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSortPer; ++r) s[swz(base + r)] = v[r];
@@ -252,10 +273,10 @@ hipError_t seg_sort(const int64_t* d_chunk_pref, const int64_t* d_gpref, int64_t
                     int rounds, int64_t run0, uint64_t* d_G, uint64_t* d_tmp, hipStream_t st) {
     if (nseg <= 0 || nchunks <= 0) return hipSuccess;
     if (run0 == kSortRun)
-        hipLaunchKernelGGL(k_seg_sort_chunk<kSortRun>, dim3((unsigned)nchunks), dim3(kSortRun / kSortPer), 0, st,
+        hipLaunchKernelGGL(k_seg_sort_chunk<kSortRun>, dim3((unsigned)nchunks), dim3(kSortRun / kSortPerRun(kSortRun)), 0, st,
                            d_chunk_pref, d_gpref, nseg, d_G);
     else if (run0 == kBigChunk)
-        hipLaunchKernelGGL(k_seg_sort_chunk<kBigChunk>, dim3((unsigned)nchunks), dim3(kBigChunk / kSortPer), 0, st,
+        hipLaunchKernelGGL(k_seg_sort_chunk<kBigChunk>, dim3((unsigned)nchunks), dim3(kBigChunk / kSortPerRun(kBigChunk)), 0, st,
                            d_chunk_pref, d_gpref, nseg, d_G);
     else
         return hipErrorInvalidValue;
