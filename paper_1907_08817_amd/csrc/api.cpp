@@ -56,11 +56,12 @@ hipError_t launch_big_gather(const int32_t* d_bigbucket, int64_t big_count, int6
                              hipStream_t st);
 hipError_t launch_big_place(const int32_t* d_bigbucket, int64_t big_count, int64_t nchunks,
                             const int64_t* d_chunk_pref, const int64_t* d_gpref, const int64_t* d_start,
-                            const uint64_t* d_Gs, const uint64_t* d_alt, bool seg_mode, int64_t run0, int64_t u_neg,
-                            uint64_t* d_out, bool is_f64, hipStream_t st);
+                            const uint64_t* d_Gs, const uint64_t* d_alt, bool seg_mode, bool in_place, int64_t run0,
+                            int64_t u_neg, uint64_t* d_out, bool is_f64, hipStream_t st);
 int seg_rounds(int64_t max_len, int64_t run0);
 hipError_t seg_sort(const int64_t* d_chunk_pref, const int64_t* d_gpref, int64_t nseg, int64_t nchunks,
-                    int rounds, int64_t run0, uint64_t* d_G, uint64_t* d_tmp, hipStream_t st);
+                    int rounds, int64_t run0, uint64_t* d_G, uint64_t* d_tmp, hipStream_t st,
+                    const int32_t* d_seg_range = nullptr, const int64_t* d_range_start = nullptr);
 hipError_t launch_count_neg(const uint64_t* d_K, const int64_t* d_start, uint32_t NB, int64_t n, uint64_t* d_count,
                             hipStream_t st);
 hipError_t launch_copy_u64(const uint64_t* d_in, uint64_t* d_out, int64_t n, hipStream_t st);
@@ -634,10 +635,22 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     // chunk per range beyond the full ones; the kernels skip chunks past the
     // real count, so no host round trip is needed
     const int64_t nchunks = big_count > 0 ? big_keys / kBucketCap + big_count : 0;
+    // Dense ranges up to run0 << kSegMaxRounds keys are sorted range by range
+    // where the partition left them (chunks in LDS, then merge rounds through
+    // the other partition buffer); larger ones send the whole residue through
+    // one LSD radix sort in G, which then moves fewer bytes than the merge
+    // rounds.  Runs start at two chunks once the dense keys fill the GPU with
+    // such runs (the longer runs save a merge round), at one otherwise.
+    const int64_t run0 = big_keys > kWideRunKeys ? (int64_t)kSortRun : (int64_t)kBigChunk;
+    const int rounds = big_count > 0 ? seg_rounds((int64_t)c[kCntBigMax], run0) : 0;
+    const bool seg_mode = rounds <= kSegMaxRounds;
+    uint64_t* const Kw = which ? K1 : K0;   // Ks, written by the range-by-range sort
+    uint64_t* const alt = which ? K0 : K1;  // the partition buffer that Ks is not in
     if (big_count > 0) {
         NNS_HIP(fill_u32(big_hist, big_count * (int64_t)kBucketSlots, 0u, st));
         NNS_HIP(launch_big_chunks(bigbucket, big_count, start, chunk_pref, gpref, st));
-        NNS_HIP(launch_big_gather(bigbucket, big_count, nchunks, chunk_pref, gpref, start, Ks, Ss, big_hist, G, st));
+        NNS_HIP(launch_big_gather(bigbucket, big_count, nchunks, chunk_pref, gpref, start, Ks, Ss, big_hist,
+                                  seg_mode ? nullptr : G, st));
         NNS_HIP(launch_big_counts(big_hist, big_count, eps, counters, st));
     }
     if (unm > 0) NNS_HIP(launch_copy_u64(Ks + first_unmapped, G + big_keys, unm, st));
@@ -650,25 +663,17 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     ev.mark(3);
 
     // ---- dense ranges and keys without a slot: conventional sort, placed ----
-    // Dense ranges up to run0 << kSegMaxRounds keys: sorted range by
-    // range (chunks in LDS, then merge rounds), the keys without a slot by
-    // radix on their own.  Larger ones: one LSD radix sort of all of G, which
-    // then moves fewer bytes than the merge rounds.
+    // (the keys without a slot by radix on their own in G, after the dense
+    // keys' place there)
     if (G_size > 0) {
-        // sorted runs of two chunks once the dense keys fill the GPU with
-        // such runs (the longer runs save a merge round), of one otherwise
-        const int64_t run0 = big_keys > kWideRunKeys ? (int64_t)kSortRun : (int64_t)kBigChunk;
-        const int rounds = seg_rounds((int64_t)c[kCntBigMax], run0);
-        const bool seg_mode = rounds <= kSegMaxRounds;
-        uint64_t* alt = which ? K0 : K1;  // the partition buffer that Ks is not in
         if (seg_mode) {
-            NNS_HIP(seg_sort(chunk_pref, gpref, big_count, nchunks, rounds, run0, G, alt, st));
+            NNS_HIP(seg_sort(chunk_pref, gpref, big_count, nchunks, rounds, run0, Kw, alt, st, bigbucket, start));
             if (unm > 0) NNS_HIP(radix_sort(G + big_keys, G + big_keys, unm, 0, 0, radix_ws, P.radix_bytes, st));
         } else {
             NNS_HIP(radix_sort(G, G, G_size, 0, 0, radix_ws, P.radix_bytes, st));
         }
-        NNS_HIP(launch_big_place(bigbucket, big_count, nchunks, chunk_pref, gpref, start, G, alt, seg_mode, run0, u_neg,
-                                 out, is_f64, st));
+        NNS_HIP(launch_big_place(bigbucket, big_count, nchunks, chunk_pref, gpref, start, seg_mode ? Kw : G, alt,
+                                 seg_mode, seg_mode, run0, u_neg, out, is_f64, st));
         // sorted keys without a slot: those with the order key's top bit clear
         // first (below every mapped key), the rest last
         const int64_t u_pos = unm - u_neg;

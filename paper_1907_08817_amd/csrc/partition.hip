@@ -41,8 +41,10 @@ __global__ void __launch_bounds__(256) k_check_slots(const uint32_t* __restrict_
 }
 
 // ---- dense ranges (more keys than one LDS tile holds) and keys without a
-// slot: copied to G; a dense range's slot multiplicities are counted in LDS
-// per chunk and added to its histogram, for the round counts.
+// slot: a dense range's slot multiplicities are counted in LDS per chunk and
+// added to its histogram, for the round counts; its keys are copied to G when
+// the whole residue is radix-sorted there (ranges sorted one by one stay in
+// the partition output).
 
 // chunk_pref[i] = number of chunks of big ranges 0..i-1, gpref[i] = keys of
 // big ranges 0..i-1 (i = 0..big_count): one workgroup, 256 ranges at a time.
@@ -108,7 +110,7 @@ __global__ void __launch_bounds__(256) k_big_gather(const int32_t* __restrict__ 
     for (int i = threadIdx.x; i < (int)kBucketSlots; i += blockDim.x) h[i] = 0;
     __syncthreads();
     for (int64_t e = c0 + threadIdx.x; e < c1; e += blockDim.x) {
-        G[gpref[id] + e] = K[s0 + e];
+        if (G) G[gpref[id] + e] = K[s0 + e];  // no G: the range is sorted where it is
         atomicAdd(&h[Sl[s0 + e] & (kBucketSlots - 1)], 1u);
     }
     __syncthreads();
@@ -124,15 +126,17 @@ __global__ void __launch_bounds__(256) k_big_gather(const int32_t* __restrict__ 
 //    ranges the middle part is the dense ranges one after another, so range
 //    id's slice is G[u_neg + gpref[id] ...];
 //  - range by range (seg_mode 1): range id's own keys, sorted in place in its
-//    segment G[gpref[id] ...] or, after an odd number of merge rounds, at the
-//    same offset of the other buffer alt.
+//    segment G[gpref[id] ...] (in_place: in its slice of the partition output,
+//    G[start[b] ...]) or, after an odd number of merge rounds, at the same
+//    offset of the other buffer alt.
 // The boundary check that follows catches any overlap.
 __global__ void __launch_bounds__(256) k_big_place(const int32_t* __restrict__ bigbucket, int64_t big_count,
                                                    const int64_t* __restrict__ chunk_pref,
                                                    const int64_t* __restrict__ gpref,
                                                    const int64_t* __restrict__ start, const uint64_t* __restrict__ Gs,
-                                                   const uint64_t* __restrict__ alt, int seg_mode, int64_t run0,
-                                                   int64_t u_neg, uint64_t* __restrict__ out, int is_f64) {
+                                                   const uint64_t* __restrict__ alt, int seg_mode, int in_place,
+                                                   int64_t run0, int64_t u_neg, uint64_t* __restrict__ out,
+                                                   int is_f64) {
     const int64_t chunk = blockIdx.x;
     if (chunk >= chunk_pref[big_count]) return;  // the grid is an upper bound
     int64_t lo = 0, hi = big_count - 1;
@@ -150,7 +154,7 @@ __global__ void __launch_bounds__(256) k_big_place(const int32_t* __restrict__ b
     if (seg_mode) {
         int rounds = 0;
         for (int64_t L = run0; L < len; L <<= 1) ++rounds;  // run0: the chunk sort's run length
-        src = ((rounds & 1) ? alt : Gs) + gpref[id];
+        src = ((rounds & 1) ? alt : Gs) + (in_place ? start[b] : gpref[id]);
     } else {
         src = Gs + u_neg + gpref[id];
     }
@@ -264,11 +268,12 @@ hipError_t launch_big_gather(const int32_t* d_bigbucket, int64_t big_count, int6
 
 hipError_t launch_big_place(const int32_t* d_bigbucket, int64_t big_count, int64_t nchunks,
                             const int64_t* d_chunk_pref, const int64_t* d_gpref, const int64_t* d_start,
-                            const uint64_t* d_Gs, const uint64_t* d_alt, bool seg_mode, int64_t run0,
+                            const uint64_t* d_Gs, const uint64_t* d_alt, bool seg_mode, bool in_place, int64_t run0,
                             int64_t u_neg, uint64_t* d_out, bool is_f64, hipStream_t st) {
     if (nchunks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_big_place, dim3((unsigned)nchunks), dim3(256), 0, st, d_bigbucket, big_count, d_chunk_pref,
-                       d_gpref, d_start, d_Gs, d_alt, seg_mode ? 1 : 0, run0, u_neg, d_out, is_f64 ? 1 : 0);
+                       d_gpref, d_start, d_Gs, d_alt, seg_mode ? 1 : 0, in_place ? 1 : 0, run0, u_neg, d_out,
+                       is_f64 ? 1 : 0);
     return hipGetLastError();
 }
 

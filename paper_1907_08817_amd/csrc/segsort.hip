@@ -1,9 +1,11 @@
 // Sort of the dense ranges' keys, range by range (the conventional sort of
 // the keys the LDS polish cannot hold; Sec. 2 sorts the last conflict array
 // conventionally, and the dense ranges' keys are the part of it that this
-// design routes here).  After the gather, G holds each dense range's order
-// keys contiguously: range id occupies G[gpref[id], gpref[id + 1]), cut into
-// chunks of kBigChunk keys (chunk_pref[id] = its first chunk).  Sorting each
+// design routes here).  Segment id holds gpref[id + 1] - gpref[id] order keys
+// starting at G[gpref[id]] (a compact buffer), or, when seg_range is given,
+// at G[range_start[seg_range[id]]] (the range's own slice of the partition
+// output, sorted in place); it is cut into chunks of kBigChunk keys
+// (chunk_pref[id] = its first chunk).  Sorting each
 // segment on its own gives every range exactly its own keys in order, the
 // same state a small range reaches in LDS; the boundary check that follows
 // treats both alike.
@@ -116,9 +118,17 @@ __device__ __forceinline__ int split_lds_swz(const uint64_t* s, int pa, int na, 
     return lo;
 }
 
+// First key of segment id in G.
+__device__ __forceinline__ int64_t seg_base(const int64_t* __restrict__ gpref, const int32_t* __restrict__ seg_range,
+                                            const int64_t* __restrict__ range_start, int64_t id) {
+    return seg_range ? range_start[seg_range[id]] : gpref[id];
+}
+
 template <int RUN, int kSortPer = kSortPerRun(RUN)>
 __global__ void __launch_bounds__(RUN / kSortPer) k_seg_sort_chunk(const int64_t* __restrict__ chunk_pref,
                                                                   const int64_t* __restrict__ gpref, int64_t nseg,
+                                                                  const int32_t* __restrict__ seg_range,
+                                                                  const int64_t* __restrict__ range_start,
                                                                   uint64_t* G) {
     constexpr int kThreads = RUN / kSortPer;
     constexpr int kChunksPerRun = RUN / kBigChunk;
@@ -128,7 +138,7 @@ __global__ void __launch_bounds__(RUN / kSortPer) k_seg_sort_chunk(const int64_t
     if (chunk >= chunk_pref[nseg]) return;  // the grid is an upper bound
     const int64_t id = seg_of_chunk(chunk_pref, nseg, chunk);
     if ((chunk - chunk_pref[id]) % kChunksPerRun) return;  // sorted with the chunk before it
-    const int64_t g0 = gpref[id], len = gpref[id + 1] - g0;
+    const int64_t g0 = seg_base(gpref, seg_range, range_start, id), len = gpref[id + 1] - gpref[id];
     const int64_t c0 = (chunk - chunk_pref[id]) * kBigChunk;
     const int cnt = (int)(len - c0 < RUN ? len - c0 : RUN);
     uint64_t* p = G + g0 + c0;
@@ -195,6 +205,8 @@ __global__ void __launch_bounds__(RUN / kSortPer) k_seg_sort_chunk(const int64_t
 
 __global__ void __launch_bounds__(kMergeThreads) k_seg_merge(const int64_t* __restrict__ chunk_pref,
                                                              const int64_t* __restrict__ gpref, int64_t nseg,
+                                                             const int32_t* __restrict__ seg_range,
+                                                             const int64_t* __restrict__ range_start,
                                                              int64_t L, const uint64_t* __restrict__ src,
                                                              uint64_t* __restrict__ dst) {
     __shared__ uint64_t s[kBigChunk];
@@ -202,7 +214,7 @@ __global__ void __launch_bounds__(kMergeThreads) k_seg_merge(const int64_t* __re
     const int64_t chunk = blockIdx.x;
     if (chunk >= chunk_pref[nseg]) return;  // the grid is an upper bound
     const int64_t id = seg_of_chunk(chunk_pref, nseg, chunk);
-    const int64_t g0 = gpref[id], len = gpref[id + 1] - g0;
+    const int64_t g0 = seg_base(gpref, seg_range, range_start, id), len = gpref[id + 1] - gpref[id];
     if (len <= L) return;  // one run already: this segment is done
     const int64_t c0 = (chunk - chunk_pref[id]) * kBigChunk;
     const int64_t c1 = c0 + kBigChunk < len ? c0 + kBigChunk : len;
@@ -267,17 +279,19 @@ int seg_rounds(int64_t max_len, int64_t run0) {
     return r;
 }
 
-// Sorts every segment of G; tmp holds as many keys as G.  A segment of len
-// keys ends in (seg_rounds(len, run0) odd ? tmp : G).
+// Sorts every segment of G; tmp holds as many keys as G, and a segment uses
+// the same offsets in it.  A segment of len keys ends in
+// (seg_rounds(len, run0) odd ? tmp : G).
 hipError_t seg_sort(const int64_t* d_chunk_pref, const int64_t* d_gpref, int64_t nseg, int64_t nchunks,
-                    int rounds, int64_t run0, uint64_t* d_G, uint64_t* d_tmp, hipStream_t st) {
+                    int rounds, int64_t run0, uint64_t* d_G, uint64_t* d_tmp, hipStream_t st,
+                    const int32_t* d_seg_range, const int64_t* d_range_start) {
     if (nseg <= 0 || nchunks <= 0) return hipSuccess;
     if (run0 == kSortRun)
         hipLaunchKernelGGL(k_seg_sort_chunk<kSortRun>, dim3((unsigned)nchunks), dim3(kSortRun / kSortPerRun(kSortRun)), 0, st,
-                           d_chunk_pref, d_gpref, nseg, d_G);
+                           d_chunk_pref, d_gpref, nseg, d_seg_range, d_range_start, d_G);
     else if (run0 == kBigChunk)
         hipLaunchKernelGGL(k_seg_sort_chunk<kBigChunk>, dim3((unsigned)nchunks), dim3(kBigChunk / kSortPerRun(kBigChunk)), 0, st,
-                           d_chunk_pref, d_gpref, nseg, d_G);
+                           d_chunk_pref, d_gpref, nseg, d_seg_range, d_range_start, d_G);
     else
         return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
@@ -285,7 +299,7 @@ hipError_t seg_sort(const int64_t* d_chunk_pref, const int64_t* d_gpref, int64_t
     uint64_t* buf[2] = {d_G, d_tmp};
     for (int r = 0; r < rounds; ++r) {
         hipLaunchKernelGGL(k_seg_merge, dim3((unsigned)nchunks), dim3(kMergeThreads), 0, st, d_chunk_pref, d_gpref,
-                           nseg, run0 << r, buf[r & 1], buf[(r + 1) & 1]);
+                           nseg, d_seg_range, d_range_start, run0 << r, buf[r & 1], buf[(r + 1) & 1]);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
