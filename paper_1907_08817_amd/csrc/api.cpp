@@ -56,12 +56,12 @@ hipError_t launch_big_gather(const int32_t* d_bigbucket, int64_t big_count, int6
                              hipStream_t st);
 hipError_t launch_big_place(const int32_t* d_bigbucket, int64_t big_count, int64_t nchunks,
                             const int64_t* d_chunk_pref, const int64_t* d_gpref, const int64_t* d_start,
-                            const uint64_t* d_Gs, const uint64_t* d_alt, bool seg_mode, bool in_place, int64_t run0,
-                            int64_t u_neg, uint64_t* d_out, bool is_f64, hipStream_t st);
+                            const uint64_t* d_Gs, int64_t u_neg, uint64_t* d_out, bool is_f64, hipStream_t st);
 int seg_rounds(int64_t max_len, int64_t run0);
 hipError_t seg_sort(const int64_t* d_chunk_pref, const int64_t* d_gpref, int64_t nseg, int64_t nchunks,
                     int rounds, int64_t run0, uint64_t* d_G, uint64_t* d_tmp, hipStream_t st,
-                    const int32_t* d_seg_range = nullptr, const int64_t* d_range_start = nullptr);
+                    const int32_t* d_seg_range = nullptr, const int64_t* d_range_start = nullptr,
+                    SegOut fo = SegOut{nullptr, 0, 0});
 hipError_t launch_count_neg(const uint64_t* d_K, const int64_t* d_start, uint32_t NB, int64_t n, uint64_t* d_count,
                             hipStream_t st);
 hipError_t launch_copy_u64(const uint64_t* d_in, uint64_t* d_out, int64_t n, hipStream_t st);
@@ -667,13 +667,16 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     // keys' place there)
     if (G_size > 0) {
         if (seg_mode) {
-            NNS_HIP(seg_sort(chunk_pref, gpref, big_count, nchunks, rounds, run0, Kw, alt, st, bigbucket, start));
+            // each dense range's last sorting step writes it to its place in
+            // the output
+            NNS_HIP(seg_sort(chunk_pref, gpref, big_count, nchunks, rounds, run0, Kw, alt, st, bigbucket, start,
+                             SegOut{out, u_neg, is_f64 ? 1 : 0}));
             if (unm > 0) NNS_HIP(radix_sort(G + big_keys, G + big_keys, unm, 0, 0, radix_ws, P.radix_bytes, st));
         } else {
             NNS_HIP(radix_sort(G, G, G_size, 0, 0, radix_ws, P.radix_bytes, st));
+            NNS_HIP(launch_big_place(bigbucket, big_count, nchunks, chunk_pref, gpref, start, G, u_neg, out, is_f64,
+                                     st));
         }
-        NNS_HIP(launch_big_place(bigbucket, big_count, nchunks, chunk_pref, gpref, start, seg_mode ? Kw : G, alt,
-                                 seg_mode, seg_mode, run0, u_neg, out, is_f64, st));
         // sorted keys without a slot: those with the order key's top bit clear
         // first (below every mapped key), the rest last
         const int64_t u_pos = unm - u_neg;

@@ -155,6 +155,16 @@ struct InferArgs {
     int bf16_scaled;      // the host copy's DevModel::bf16_scaled (BF16 form)
 };
 
+// Where the range-by-range sort of dense ranges leaves each range's final
+// sorted keys: out[base + range_start[range] + i] as the caller's bit
+// patterns (is_f64: binary64, else uint64).  A null out keeps them in the
+// sort's own buffers.
+struct SegOut {
+    uint64_t* out;
+    int64_t base;
+    int is_f64;
+};
+
 // H is the padded model width (32 or 64).
 hipError_t launch_infer(const InferArgs& a, int H, int form, int bf16_terms, hipStream_t st);
 

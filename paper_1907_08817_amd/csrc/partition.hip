@@ -118,25 +118,19 @@ __global__ void __launch_bounds__(256) k_big_gather(const int32_t* __restrict__ 
         if (h[i]) atomicAdd(&hist[id * kBucketSlots + i], h[i]);
 }
 
-// Dense range id's sorted keys go to their place out[u_neg + start[b] ...].
-// Where they are read from depends on how G was sorted:
-//  - whole (seg_mode 0): G in order is the keys without a slot whose order
-//    key has the top bit clear (negative NaN, -inf), then the dense ranges'
-//    keys, then the other keys without a slot.  Where f is monotone across
-//    ranges the middle part is the dense ranges one after another, so range
-//    id's slice is G[u_neg + gpref[id] ...];
-//  - range by range (seg_mode 1): range id's own keys, sorted in place in its
-//    segment G[gpref[id] ...] (in_place: in its slice of the partition output,
-//    G[start[b] ...]) or, after an odd number of merge rounds, at the same
-//    offset of the other buffer alt.
-// The boundary check that follows catches any overlap.
+// Dense range id's sorted keys go to their place out[u_neg + start[b] ...]
+// after the radix sort of the whole residue in G (ranges sorted one by one
+// write their output themselves).  G in order is the keys without a slot
+// whose order key has the top bit clear (negative NaN, -inf), then the dense
+// ranges' keys, then the other keys without a slot.  Where f is monotone
+// across ranges the middle part is the dense ranges one after another, so
+// range id's slice is G[u_neg + gpref[id] ...]; the boundary check that
+// follows catches any overlap.
 __global__ void __launch_bounds__(256) k_big_place(const int32_t* __restrict__ bigbucket, int64_t big_count,
                                                    const int64_t* __restrict__ chunk_pref,
                                                    const int64_t* __restrict__ gpref,
                                                    const int64_t* __restrict__ start, const uint64_t* __restrict__ Gs,
-                                                   const uint64_t* __restrict__ alt, int seg_mode, int in_place,
-                                                   int64_t run0, int64_t u_neg, uint64_t* __restrict__ out,
-                                                   int is_f64) {
+                                                   int64_t u_neg, uint64_t* __restrict__ out, int is_f64) {
     const int64_t chunk = blockIdx.x;
     if (chunk >= chunk_pref[big_count]) return;  // the grid is an upper bound
     int64_t lo = 0, hi = big_count - 1;
@@ -150,14 +144,7 @@ __global__ void __launch_bounds__(256) k_big_place(const int32_t* __restrict__ b
     const int64_t len = start[b + 1] - start[b];
     const int64_t c0 = (chunk - chunk_pref[id]) * kBigChunk;
     const int64_t c1 = c0 + kBigChunk < len ? c0 + kBigChunk : len;
-    const uint64_t* src;
-    if (seg_mode) {
-        int rounds = 0;
-        for (int64_t L = run0; L < len; L <<= 1) ++rounds;  // run0: the chunk sort's run length
-        src = ((rounds & 1) ? alt : Gs) + (in_place ? start[b] : gpref[id]);
-    } else {
-        src = Gs + u_neg + gpref[id];
-    }
+    const uint64_t* src = Gs + u_neg + gpref[id];
     uint64_t* dst = out + u_neg + start[b];
     for (int64_t e = c0 + threadIdx.x; e < c1; e += blockDim.x) dst[e] = order_key_inverse(src[e], is_f64);
 }
@@ -268,12 +255,10 @@ hipError_t launch_big_gather(const int32_t* d_bigbucket, int64_t big_count, int6
 
 hipError_t launch_big_place(const int32_t* d_bigbucket, int64_t big_count, int64_t nchunks,
                             const int64_t* d_chunk_pref, const int64_t* d_gpref, const int64_t* d_start,
-                            const uint64_t* d_Gs, const uint64_t* d_alt, bool seg_mode, bool in_place, int64_t run0,
-                            int64_t u_neg, uint64_t* d_out, bool is_f64, hipStream_t st) {
+                            const uint64_t* d_Gs, int64_t u_neg, uint64_t* d_out, bool is_f64, hipStream_t st) {
     if (nchunks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_big_place, dim3((unsigned)nchunks), dim3(256), 0, st, d_bigbucket, big_count, d_chunk_pref,
-                       d_gpref, d_start, d_Gs, d_alt, seg_mode ? 1 : 0, in_place ? 1 : 0, run0, u_neg, d_out,
-                       is_f64 ? 1 : 0);
+                       d_gpref, d_start, d_Gs, u_neg, d_out, is_f64 ? 1 : 0);
     return hipGetLastError();
 }
 

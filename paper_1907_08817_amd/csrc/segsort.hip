@@ -23,7 +23,9 @@
 //     a segment that takes R rounds ends in buffer R mod 2 (G for even R).
 // Where every thread reads or writes 8 or 16 consecutive keys in LDS, the
 // index is swizzled (swz) so that neighbouring threads start in different
-// banks.
+// banks.  Given an output (SegOut), the step that completes a segment (the
+// run sort of a segment of at most one run, else its last merge round) writes
+// it there as bit patterns instead of to the sort's buffers.
 #include "nnsort_internal.h"
 
 namespace nns {
@@ -129,7 +131,7 @@ __global__ void __launch_bounds__(RUN / kSortPer) k_seg_sort_chunk(const int64_t
                                                                   const int64_t* __restrict__ gpref, int64_t nseg,
                                                                   const int32_t* __restrict__ seg_range,
                                                                   const int64_t* __restrict__ range_start,
-                                                                  uint64_t* G) {
+                                                                  uint64_t* G, SegOut fo) {
     constexpr int kThreads = RUN / kSortPer;
     constexpr int kChunksPerRun = RUN / kBigChunk;
     static_assert(RUN % kBigChunk == 0 && RUN <= 8192, "a run of whole chunks, in at most 64 KB of LDS");
@@ -200,7 +202,12 @@ __global__ void __launch_bounds__(RUN / kSortPer) k_seg_sort_chunk(const int64_t
         for (int r = 0; r < kSortPer; ++r) s[swz(base + r)] = v[r];
         __syncthreads();
     }
-    for (int i = tid; i < cnt; i += kThreads) p[i] = s[swz(i)];
+    if (fo.out && len <= RUN) {  // the whole segment: straight to its place in the output
+        uint64_t* o = fo.out + fo.base + range_start[seg_range[id]];
+        for (int i = tid; i < cnt; i += kThreads) o[i] = order_key_inverse(s[swz(i)], fo.is_f64 != 0);
+    } else {
+        for (int i = tid; i < cnt; i += kThreads) p[i] = s[swz(i)];
+    }
 }
 
 __global__ void __launch_bounds__(kMergeThreads) k_seg_merge(const int64_t* __restrict__ chunk_pref,
@@ -208,7 +215,7 @@ __global__ void __launch_bounds__(kMergeThreads) k_seg_merge(const int64_t* __re
                                                              const int32_t* __restrict__ seg_range,
                                                              const int64_t* __restrict__ range_start,
                                                              int64_t L, const uint64_t* __restrict__ src,
-                                                             uint64_t* __restrict__ dst) {
+                                                             uint64_t* __restrict__ dst, SegOut fo) {
     __shared__ uint64_t s[kBigChunk];
     __shared__ int64_t s_split[2];
     const int64_t chunk = blockIdx.x;
@@ -224,11 +231,14 @@ __global__ void __launch_bounds__(kMergeThreads) k_seg_merge(const int64_t* __re
     const uint64_t* B = A + L;
     int64_t nb = len - pb - L;
     nb = nb < 0 ? 0 : (nb > L ? L : nb);
-    uint64_t* O = dst + g0 + pb;
+    // the round that completes the segment writes it to its place in the output
+    const bool fin = fo.out != nullptr && len <= 2 * L;
+    uint64_t* O = fin ? fo.out + fo.base + range_start[seg_range[id]] + pb : dst + g0 + pb;
+    const bool f64 = fo.is_f64 != 0;
     const int64_t d0 = c0 - pb, d1 = c1 - pb;
     const int tid = threadIdx.x;
     if (nb == 0) {  // the segment's last run has no partner: carried over
-        for (int64_t e = d0 + tid; e < d1; e += kMergeThreads) O[e] = A[e];
+        for (int64_t e = d0 + tid; e < d1; e += kMergeThreads) O[e] = fin ? order_key_inverse(A[e], f64) : A[e];
         return;
     }
     const int wv = tid >> 6, lane = tid & 63;
@@ -270,7 +280,10 @@ __global__ void __launch_bounds__(kMergeThreads) k_seg_merge(const int64_t* __re
             if (t0 + k < tot) s[swz(t0 + k)] = v[k];
     }
     __syncthreads();
-    for (int e = tid; e < tot; e += kMergeThreads) O[d0 + e] = s[swz(e)];
+    for (int e = tid; e < tot; e += kMergeThreads) {
+        const uint64_t k = s[swz(e)];
+        O[d0 + e] = fin ? order_key_inverse(k, f64) : k;
+    }
 }
 
 int seg_rounds(int64_t max_len, int64_t run0) {
@@ -284,14 +297,15 @@ int seg_rounds(int64_t max_len, int64_t run0) {
 // (seg_rounds(len, run0) odd ? tmp : G).
 hipError_t seg_sort(const int64_t* d_chunk_pref, const int64_t* d_gpref, int64_t nseg, int64_t nchunks,
                     int rounds, int64_t run0, uint64_t* d_G, uint64_t* d_tmp, hipStream_t st,
-                    const int32_t* d_seg_range, const int64_t* d_range_start) {
+                    const int32_t* d_seg_range, const int64_t* d_range_start, SegOut fo) {
+    if (fo.out && !(d_seg_range && d_range_start)) return hipErrorInvalidValue;
     if (nseg <= 0 || nchunks <= 0) return hipSuccess;
     if (run0 == kSortRun)
         hipLaunchKernelGGL(k_seg_sort_chunk<kSortRun>, dim3((unsigned)nchunks), dim3(kSortRun / kSortPerRun(kSortRun)), 0, st,
-                           d_chunk_pref, d_gpref, nseg, d_seg_range, d_range_start, d_G);
+                           d_chunk_pref, d_gpref, nseg, d_seg_range, d_range_start, d_G, fo);
     else if (run0 == kBigChunk)
         hipLaunchKernelGGL(k_seg_sort_chunk<kBigChunk>, dim3((unsigned)nchunks), dim3(kBigChunk / kSortPerRun(kBigChunk)), 0, st,
-                           d_chunk_pref, d_gpref, nseg, d_seg_range, d_range_start, d_G);
+                           d_chunk_pref, d_gpref, nseg, d_seg_range, d_range_start, d_G, fo);
     else
         return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
@@ -299,7 +313,7 @@ hipError_t seg_sort(const int64_t* d_chunk_pref, const int64_t* d_gpref, int64_t
     uint64_t* buf[2] = {d_G, d_tmp};
     for (int r = 0; r < rounds; ++r) {
         hipLaunchKernelGGL(k_seg_merge, dim3((unsigned)nchunks), dim3(kMergeThreads), 0, st, d_chunk_pref, d_gpref,
-                           nseg, d_seg_range, d_range_start, run0 << r, buf[r & 1], buf[(r + 1) & 1]);
+                           nseg, d_seg_range, d_range_start, run0 << r, buf[r & 1], buf[(r + 1) & 1], fo);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
