@@ -86,6 +86,12 @@ __global__ void __launch_bounds__(256) k_big_chunks(const int32_t* __restrict__ 
     }
 }
 
+// One workgroup per kGatherChunks consecutive chunks: the LDS histogram of a
+// range's slots is added to the range's global histogram once per range met,
+// not once per chunk (a chunk holds 4096 keys over 2048 slots, so a flush per
+// chunk costs about as many global atomics as it has keys).
+constexpr int kGatherChunks = 8;
+
 __global__ void __launch_bounds__(256) k_big_gather(const int32_t* __restrict__ bigbucket, int64_t big_count,
                                                     const int64_t* __restrict__ chunk_pref,
                                                     const int64_t* __restrict__ gpref,
@@ -93,25 +99,39 @@ __global__ void __launch_bounds__(256) k_big_gather(const int32_t* __restrict__ 
                                                     const uint64_t* __restrict__ K, const uint32_t* __restrict__ Sl,
                                                     uint32_t* hist, uint64_t* G) {
     __shared__ uint32_t h[kBucketSlots];
-    const int64_t chunk = blockIdx.x;
-    if (chunk >= chunk_pref[big_count]) return;  // the grid is an upper bound
-    // big range of this chunk: last i with chunk_pref[i] <= chunk
+    const int64_t total = chunk_pref[big_count];
+    const int64_t first = (int64_t)blockIdx.x * kGatherChunks;
+    if (first >= total) return;  // the grid is an upper bound
+    const int64_t last = first + kGatherChunks < total ? first + kGatherChunks : total;
+    // big range of the first chunk: last i with chunk_pref[i] <= first
     int64_t lo = 0, hi = big_count - 1;
     while (lo < hi) {
         int64_t mid = (lo + hi + 1) >> 1;
-        if (chunk_pref[mid] <= chunk) lo = mid;
+        if (chunk_pref[mid] <= first) lo = mid;
         else hi = mid - 1;
     }
-    const int64_t id = lo;
-    const int32_t b = bigbucket[id];
-    const int64_t s0 = start[b], len = start[b + 1] - s0;
-    const int64_t c0 = (chunk - chunk_pref[id]) * kBigChunk;
-    const int64_t c1 = c0 + kBigChunk < len ? c0 + kBigChunk : len;
+    int64_t id = lo;
     for (int i = threadIdx.x; i < (int)kBucketSlots; i += blockDim.x) h[i] = 0;
     __syncthreads();
-    for (int64_t e = c0 + threadIdx.x; e < c1; e += blockDim.x) {
-        if (G) G[gpref[id] + e] = K[s0 + e];  // no G: the range is sorted where it is
-        atomicAdd(&h[Sl[s0 + e] & (kBucketSlots - 1)], 1u);
+    for (int64_t chunk = first; chunk < last; ++chunk) {
+        if (chunk >= chunk_pref[id + 1]) {  // a new range: flush the last one's counts (uniform branch)
+            __syncthreads();
+            for (int i = threadIdx.x; i < (int)kBucketSlots; i += blockDim.x)
+                if (h[i]) {
+                    atomicAdd(&hist[id * kBucketSlots + i], h[i]);
+                    h[i] = 0;
+                }
+            __syncthreads();
+            while (chunk >= chunk_pref[id + 1]) ++id;
+        }
+        const int32_t b = bigbucket[id];
+        const int64_t s0 = start[b], len = start[b + 1] - s0;
+        const int64_t c0 = (chunk - chunk_pref[id]) * kBigChunk;
+        const int64_t c1 = c0 + kBigChunk < len ? c0 + kBigChunk : len;
+        for (int64_t e = c0 + threadIdx.x; e < c1; e += blockDim.x) {
+            if (G) G[gpref[id] + e] = K[s0 + e];  // no G: the range is sorted where it is
+            atomicAdd(&h[Sl[s0 + e] & (kBucketSlots - 1)], 1u);
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < (int)kBucketSlots; i += blockDim.x)
@@ -248,8 +268,8 @@ hipError_t launch_big_gather(const int32_t* d_bigbucket, int64_t big_count, int6
                              const uint64_t* d_K, const uint32_t* d_S, uint32_t* d_hist, uint64_t* d_G,
                              hipStream_t st) {
     if (nchunks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_big_gather, dim3((unsigned)nchunks), dim3(256), 0, st, d_bigbucket, big_count, d_chunk_pref,
-                       d_gpref, d_start, d_K, d_S, d_hist, d_G);
+    hipLaunchKernelGGL(k_big_gather, dim3((unsigned)((nchunks + kGatherChunks - 1) / kGatherChunks)), dim3(256), 0,
+                       st, d_bigbucket, big_count, d_chunk_pref, d_gpref, d_start, d_K, d_S, d_hist, d_G);
     return hipGetLastError();
 }
 
