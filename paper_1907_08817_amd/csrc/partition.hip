@@ -86,10 +86,12 @@ __global__ void __launch_bounds__(256) k_big_chunks(const int32_t* __restrict__ 
     }
 }
 
-// One workgroup per kGatherChunks consecutive chunks: the LDS histogram of a
+// One workgroup per `per` consecutive chunks: the LDS histogram of a
 // range's slots is added to the range's global histogram once per range met,
 // not once per chunk (a chunk holds 4096 keys over 2048 slots, so a flush per
-// chunk costs about as many global atomics as it has keys).
+// chunk costs about as many global atomics as it has keys).  `per` stays 1
+// until there are enough chunks for 2048 workgroups, and is at most
+// kGatherChunks.
 constexpr int kGatherChunks = 8;
 
 __global__ void __launch_bounds__(256) k_big_gather(const int32_t* __restrict__ bigbucket, int64_t big_count,
@@ -97,12 +99,12 @@ __global__ void __launch_bounds__(256) k_big_gather(const int32_t* __restrict__ 
                                                     const int64_t* __restrict__ gpref,
                                                     const int64_t* __restrict__ start,
                                                     const uint64_t* __restrict__ K, const uint32_t* __restrict__ Sl,
-                                                    uint32_t* hist, uint64_t* G) {
+                                                    uint32_t* hist, uint64_t* G, int per) {
     __shared__ uint32_t h[kBucketSlots];
     const int64_t total = chunk_pref[big_count];
-    const int64_t first = (int64_t)blockIdx.x * kGatherChunks;
+    const int64_t first = (int64_t)blockIdx.x * per;
     if (first >= total) return;  // the grid is an upper bound
-    const int64_t last = first + kGatherChunks < total ? first + kGatherChunks : total;
+    const int64_t last = first + per < total ? first + per : total;
     // big range of the first chunk: last i with chunk_pref[i] <= first
     int64_t lo = 0, hi = big_count - 1;
     while (lo < hi) {
@@ -268,8 +270,9 @@ hipError_t launch_big_gather(const int32_t* d_bigbucket, int64_t big_count, int6
                              const uint64_t* d_K, const uint32_t* d_S, uint32_t* d_hist, uint64_t* d_G,
                              hipStream_t st) {
     if (nchunks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_big_gather, dim3((unsigned)((nchunks + kGatherChunks - 1) / kGatherChunks)), dim3(256), 0,
-                       st, d_bigbucket, big_count, d_chunk_pref, d_gpref, d_start, d_K, d_S, d_hist, d_G);
+    const int64_t per = std::min<int64_t>(kGatherChunks, std::max<int64_t>(1, nchunks / 2048));
+    hipLaunchKernelGGL(k_big_gather, dim3((unsigned)((nchunks + per - 1) / per)), dim3(256), 0, st, d_bigbucket,
+                       big_count, d_chunk_pref, d_gpref, d_start, d_K, d_S, d_hist, d_G, (int)per);
     return hipGetLastError();
 }
 
