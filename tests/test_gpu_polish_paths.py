@@ -296,3 +296,25 @@ def test_many_dense_keys_range_too_long_for_wide_runs():
     st = sort_slots(x, s)
     assert st["big_buckets"] == 3 and st["big_bucket_keys"] == 4_305_000
     assert st["fallback"] == 0
+
+
+def test_many_dense_ranges_counted_several_chunks_per_workgroup():
+    """3,000 dense ranges of 4,097 to 6,000 keys (15.2M keys): with more than
+    4,096 chunks of 4,096 dense keys, each workgroup of the slot count takes
+    several consecutive chunks, and most of them cross from one range into the
+    next; the round counts must still equal the oracle's."""
+    x = W.uniform(15_500_000, seed=33)
+    rng = np.random.default_rng(7)
+    sizes = rng.integers(4097, 6001, 3000)
+    edges = np.concatenate([[0], np.cumsum(sizes)])
+    r = ranks(x)
+    b = np.searchsorted(edges, r, side="right") - 1
+    dense = b < sizes.size
+    s = np.empty(x.size, np.int64)
+    s[dense] = b[dense] * RANGE_SLOTS + rng.integers(0, RANGE_SLOTS, int(dense.sum()))
+    s[~dense] = sizes.size * RANGE_SLOTS + (r[~dense] - edges[-1])
+    assert s.max() < O.num_slots(x.size)
+    assert int(sizes.sum()) // 4096 + sizes.size >= 2 * 2048  # at least two chunks per workgroup
+    st = sort_slots(x, s)
+    assert st["big_buckets"] == sizes.size and st["big_bucket_keys"] == int(sizes.sum())
+    assert st["fallback"] == 0
