@@ -44,7 +44,8 @@ size_t zone_bytes();
 size_t partition_hist_words(int64_t n);
 hipError_t partition_by_range(const uint64_t* in_keys, const uint32_t* in_slots, int64_t n, uint32_t NB, bool is_f64,
                               uint64_t* K0, uint32_t* S0, uint64_t* K1, uint32_t* S1, uint32_t* blockhist,
-                              int* which, hipStream_t st);
+                              int* which, hipStream_t st, bool first_counted = false);
+int range_passes(uint32_t NB, int* shifts, uint32_t* masks, int* widths);
 hipError_t launch_range_bounds(const uint32_t* d_sorted_slots, int64_t n, uint32_t NB, int64_t* d_start,
                                hipStream_t st);
 hipError_t launch_check_slots(const uint32_t* d_slots, int64_t n, int64_t S, uint64_t* d_bad, hipStream_t st);
@@ -578,6 +579,15 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     } else if (!model_is_finite(model)) {
         NNS_HIP(fill_u32(slots0, n, kUnmapped, st));
     } else {
+        if (prm->form == NNSORT_FORM_BF16) {
+            // the BF16 map kernel also counts the partition's first digits
+            int shifts[4], widths[4];
+            uint32_t masks[4];
+            range_passes((uint32_t)P.NB, shifts, masks, widths);
+            ia.tile_hist = phist;
+            ia.NB = (uint32_t)P.NB;
+            ia.dmask = masks[0];
+        }
         NNS_HIP(launch_infer(ia, HP, prm->form, prm->bf16_terms, st));
     }
     ev.mark(1);
@@ -586,7 +596,7 @@ int sort_impl(const nnsort_model* model, const uint32_t* given_slots, const void
     const uint32_t NB = (uint32_t)P.NB;
     int which = 0;
     NNS_HIP(partition_by_range((const uint64_t*)d_in, slots_src, n, NB, is_f64, K0, S0, K1, slots0, phist, &which,
-                               st));
+                               st, ia.tile_hist != nullptr));
     const uint64_t* Ks = which ? K1 : K0;
     const uint32_t* Ss = which ? slots0 : S0;
     NNS_HIP(launch_range_bounds(Ss, n, NB, start, st));

@@ -169,7 +169,7 @@ __device__ __forceinline__ void pair_half_sums(float xa, float xla, float xb, fl
 }
 
 template <int H, int T, bool SCALED>
-__global__ void __launch_bounds__(256, 3) k_infer_bf16(InferArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) k_infer_bf16(InferArgs a) {
     constexpr int RB = H / 32;
     constexpr int KS = H / 16;
     const DevModel* __restrict__ m = a.model;
@@ -217,10 +217,10 @@ __global__ void __launch_bounds__(256, 3) k_infer_bf16(InferArgs a) {
     const double lo = m->lo, inv = m->inv_range;
     const TileOps op{s_w1 + 8 * g, s_b1 + 8 * g, s_b2[g], s_w3[g]};
 
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int64_t nblocks = (a.n + 63) >> 6;
-    for (int64_t blk = wave; blk < nblocks; blk += nwaves) {
+    // Maps block blk (keys 64 blk .. 64 blk + 63; the whole wave calls it
+    // with the same blk) and returns the slot of the lane's key.
+    auto map_block = [&](int64_t blk) -> uint32_t {
         // keeps the compiler from hoisting the LDS vectors into registers
         __asm__ volatile("" ::: "memory");
         const int64_t i = blk * 64 + lane;
@@ -240,19 +240,48 @@ __global__ void __launch_bounds__(256, 3) k_infer_bf16(InferArgs a) {
         // half 0's sum of tile B (the same two terms a sum over both halves
         // of one tile adds)
         const double F = (g ? sB : sA) + other_half(g ? sA : sB);
+        uint32_t slot = kUnmapped;
         if (active) {
-            if (a.slots_out) a.slots_out[i] = mapped ? slot_of(F, a.M) : kUnmapped;
+            slot = mapped ? slot_of(F, a.M) : kUnmapped;
+            if (a.slots_out) a.slots_out[i] = slot;
             if (a.F_out) a.F_out[i] = mapped ? F : __longlong_as_double(0x7FF8000000000000ll);
+        }
+        return slot;
+    };
+
+    // Tiles of kPartTile keys, one per workgroup at a time: wave w maps
+    // blocks 8w .. 8w + 7 of the tile.  With tile_hist, the keys' first-pass
+    // digits are counted in LDS and the tile's histogram stored as the
+    // partition's count kernel would store it.
+    static_assert(kPartTile == 4 * 8 * 64, "a tile is 8 blocks per wave of a 256-thread workgroup");
+    __shared__ uint32_t s_h[256];
+    const int wv = threadIdx.x >> 6;
+    const int64_t ntiles = (a.n + kPartTile - 1) / kPartTile;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        if (a.tile_hist) {
+            s_h[threadIdx.x] = 0;
+            __syncthreads();
+        }
+#pragma unroll 1
+        for (int k = 0; k < 8; ++k) {
+            const int64_t blk = t * 32 + wv * 8 + k;
+            if (blk < nblocks) {
+                const uint32_t sl = map_block(blk);
+                if (a.tile_hist && blk * 64 + lane < a.n) atomicAdd(&s_h[range_of(sl, a.NB) & a.dmask], 1u);
+            }
+        }
+        if (a.tile_hist) {
+            __syncthreads();
+            a.tile_hist[t * 256 + threadIdx.x] = s_h[threadIdx.x];
         }
     }
 }
 
 hipError_t launch_bf16_infer(const InferArgs& a, int H, int bf16_terms, bool scaled, hipStream_t st) {
-    int64_t blocks64 = (a.n + 63) / 64;
-    // grid-stride over 64-key blocks; 64 workgroups per CU (about ten times
+    // grid-stride over tiles; up to 64 workgroups per CU (about ten times
     // what is resident at once) balances the waves' finishing times better
     // than fewer, longer-lived workgroups
-    int64_t blocks = (blocks64 + 3) / 4;
+    int64_t blocks = (a.n + kPartTile - 1) / kPartTile;
     if (blocks > 256 * 64) blocks = 256 * 64;
     if (blocks < 1) blocks = 1;
     dim3 grid((unsigned)blocks), block(256);

@@ -153,6 +153,12 @@ struct InferArgs {
     uint32_t* slots_out;  // optional per-key slot
     double* F_out;        // optional per-key F
     int bf16_scaled;      // the host copy's DevModel::bf16_scaled (BF16 form)
+    // BF16 form, optional: the first partition pass's digit histogram of
+    // every kPartTile-key tile, hist[tile][256], counted as the slots are
+    // written (digit = range_of(slot, NB) & dmask)
+    uint32_t* tile_hist;
+    uint32_t NB;
+    uint32_t dmask;
 };
 
 // Where the range-by-range sort of dense ranges leaves each range's final

@@ -209,7 +209,7 @@ size_t partition_hist_words(int64_t n) { return lsd_hist_words(n); }
 // result in (K[res], S[res]) as order keys; returns res via *which.
 hipError_t partition_by_range(const uint64_t* in_keys, const uint32_t* in_slots, int64_t n, uint32_t NB, bool is_f64,
                               uint64_t* K0, uint32_t* S0, uint64_t* K1, uint32_t* S1, uint32_t* blockhist,
-                              int* which, hipStream_t st) {
+                              int* which, hipStream_t st, bool first_counted) {
     int shifts[4], widths[4];
     uint32_t masks[4];
     int passes = range_passes(NB, shifts, masks, widths);
@@ -225,8 +225,9 @@ hipError_t partition_by_range(const uint64_t* in_keys, const uint32_t* in_slots,
         uint32_t* so = Sb[p & 1];
         const RangeDigit dig{NB, shifts[p], masks[p]};
         const int im = p == 0 ? (is_f64 ? 1 : 2) : 0;
-        hipLaunchKernelGGL((k_lsd_upsweep<true, RangeDigit>), dim3((unsigned)ntiles), dim3(kLsdThreads), 0, st,
-                           kin, sin, n, im, dig, blockhist);
+        if (p > 0 || !first_counted)  // else the map kernel counted the first pass's digits
+            hipLaunchKernelGGL((k_lsd_upsweep<true, RangeDigit>), dim3((unsigned)ntiles), dim3(kLsdThreads), 0, st,
+                               kin, sin, n, im, dig, blockhist);
         if ((e = launch_lsd_scan(blockhist, ntiles, st)) != hipSuccess) return e;
         if (p == 0)
             hipLaunchKernelGGL((k_lsd_downsweep<false, true, RangeDigit>), dim3((unsigned)ntiles), dim3(kLsdThreads),
