@@ -23,7 +23,13 @@
 // of its own key l; translate, slot and store run once per key.  The two
 // tiles go through each k-step together: one read of the k-step's layer-1
 // weights and W2 operands from LDS serves both (half the LDS traffic of
-// mapping them one after the other, 125 VGPRs at H = 64, 4 waves per SIMD).
+// mapping them one after the other).  Held to 4 waves per SIMD: 128 VGPRs at
+// H = 64, one value spilled outside the block loop.
+//
+// A workgroup maps one partition tile (2048 keys, 8 blocks per wave) at a
+// time; in a sort it also counts the tile's keys by the first partition
+// pass's range digit in LDS and stores the tile's histogram, so the
+// partition does not read the slots back to count them.
 //
 // Scaled operands (the host's bf16_operands()): with every pre-activation of
 // the power-of-two-scaled network at most 1, relu(z) equals clamp(z, 0, 1),
