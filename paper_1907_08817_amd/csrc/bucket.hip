@@ -211,16 +211,26 @@ __global__ void __launch_bounds__(256) k_big_counts(const uint32_t* __restrict__
                                                     unsigned long long* counters) {
     __shared__ unsigned long long s_w[4][2 * NNSORT_MAX_EPS];
     unsigned long long col[NNSORT_MAX_EPS] = {0}, pl[NNSORT_MAX_EPS] = {0};
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-        uint32_t k = hist[i];
+    auto add = [&](uint32_t k) {
 #pragma unroll
         for (int r = 1; r <= NNSORT_MAX_EPS; ++r) {
             if (r > eps) break;
             col[r - 1] += k > (uint32_t)r ? k - r : 0;
             pl[r - 1] += k >= (uint32_t)r ? 1 : 0;
         }
+    };
+    // eight independent loads in flight per thread: few workgroups, so few
+    // atomics on the 2 eps shared counters at the end
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 7 * stride < total; i += 8 * stride) {
+        uint32_t k[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) k[q] = hist[i + q * stride];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) add(k[q]);
     }
+    for (; i < total; i += stride) add(hist[i]);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int r = 0; r < NNSORT_MAX_EPS; ++r) {
@@ -245,7 +255,7 @@ __global__ void __launch_bounds__(256) k_big_counts(const uint32_t* __restrict__
 hipError_t launch_big_counts(const uint32_t* d_hist, int64_t big_count, int eps, uint64_t* d_counters,
                              hipStream_t st) {
     if (big_count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_big_counts, dim3(blocks_for(big_count * kBucketSlots, 256, 2048)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_big_counts, dim3(blocks_for(big_count * kBucketSlots, 256 * 8, 2048)), dim3(256), 0, st,
                        d_hist, big_count * (int64_t)kBucketSlots, eps, (unsigned long long*)d_counters);
     return hipGetLastError();
 }
