@@ -277,6 +277,27 @@ def test_bf16_sort_exact_and_counts(terms):
     assert st["collided"] == [int(np.maximum(0, k - r).sum()) for r in range(1, 4)]
 
 
+@pytest.mark.parametrize("n", [2, 63, 64, 65, 2047, 2048, 2049, 6143, 6145])
+def test_bf16_sort_tile_edges(n):
+    """The BF16 map kernel counts the first partition pass's digits per
+    2048-key tile itself: sizes around a 64-key block and a tile, with the
+    round-count shortcut off (tau 0), sort exactly with the oracle's counts."""
+    x = W.gauss_mix(n, seed=40 + n % 7)
+    model = O.fit(W.gauss_mix(20_000, seed=5), H=64, sample_frac=0.05, batch=512, steps=2)
+    m = nn.model_from_dict(model)
+    sp = nn.sort_params(form=nn.FORM_BF16, tau=0, stats_level=1)
+    xd = to_dev(x)
+    out, st = nn.nnsort_sort_with_model(m, xd, sp=sp)
+    assert_same_bits(to_host(out, x.dtype), O.sort_reference(x))
+    slots, _ = nn.nnsort_predict(m, xd, sp)
+    s = slots.cpu().numpy().astype(np.int64)
+    k = np.bincount(s[s != 0xFFFFFFFF])
+    want = [int(np.maximum(0, k - r).sum()) for r in range(1, 4)]
+    # with tau 0 the rounds stop after the first one that leaves no conflict
+    rounds = next((i + 1 for i, c in enumerate(want) if c == 0), 3)
+    assert st["rounds"] == rounds and st["collided"] == want[:rounds]
+
+
 # ---------------------------------------------------------------------------
 # determinism, radix sort, fit, gradients, errors
 # ---------------------------------------------------------------------------
