@@ -47,38 +47,68 @@ __global__ void __launch_bounds__(256) k_check_slots(const uint32_t* __restrict_
 // the partition output).
 
 // chunk_pref[i] = number of chunks of big ranges 0..i-1, gpref[i] = keys of
-// big ranges 0..i-1 (i = 0..big_count): one workgroup, 256 ranges at a time.
-__global__ void __launch_bounds__(256) k_big_chunks(const int32_t* __restrict__ bigbucket, int64_t big_count,
-                                                    const int64_t* __restrict__ start, int64_t* chunk_pref,
-                                                    int64_t* gpref) {
-    __shared__ int64_t s_c[256], s_g[256];
+// big ranges 0..i-1 (i = 0..big_count): one workgroup of NT threads, each
+// summing PER consecutive ranges, then a scan of the threads' totals by wave
+// shuffles (one barrier per NT * PER ranges).  One range per thread of 256
+// while that covers them all, eight per thread of 1024 beyond.
+template <int NT, int PER>
+__global__ void __launch_bounds__(NT) k_big_chunks(const int32_t* __restrict__ bigbucket, int64_t big_count,
+                                                   const int64_t* __restrict__ start, int64_t* chunk_pref,
+                                                   int64_t* gpref) {
+    constexpr int kWaves = NT / 64;
+    __shared__ int64_t s_c[kWaves], s_g[kWaves];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int64_t cbase = 0, gbase = 0;
-    for (int64_t i0 = 0; i0 < big_count; i0 += 256) {
-        const int64_t i = i0 + threadIdx.x;
-        int64_t len = 0;
-        if (i < big_count) {
-            const int32_t b = bigbucket[i];
-            len = start[b + 1] - start[b];
+    for (int64_t i0 = 0; i0 < big_count; i0 += (int64_t)NT * PER) {
+        const int64_t first = i0 + (int64_t)threadIdx.x * PER;
+        int64_t len[PER];
+        int64_t tc = 0, tg = 0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            len[q] = 0;
+            if (first + q < big_count) {
+                const int32_t b = bigbucket[first + q];
+                len[q] = start[b + 1] - start[b];
+            }
+            tc += (len[q] + kBigChunk - 1) / kBigChunk;
+            tg += len[q];
         }
-        const int64_t nc = (len + kBigChunk - 1) / kBigChunk;
-        s_c[threadIdx.x] = nc;
-        s_g[threadIdx.x] = len;
+        int64_t ic = tc, ig = tg;  // inclusive scan over the wave
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t yc = __shfl_up(ic, o), yg = __shfl_up(ig, o);
+            if (lane >= o) {
+                ic += yc;
+                ig += yg;
+            }
+        }
+        if (lane == 63) {
+            s_c[w] = ic;
+            s_g[w] = ig;
+        }
         __syncthreads();
-        for (int o = 1; o < 256; o <<= 1) {
-            const int64_t yc = threadIdx.x >= (unsigned)o ? s_c[threadIdx.x - o] : 0;
-            const int64_t yg = threadIdx.x >= (unsigned)o ? s_g[threadIdx.x - o] : 0;
-            __syncthreads();
-            s_c[threadIdx.x] += yc;
-            s_g[threadIdx.x] += yg;
-            __syncthreads();
+        int64_t rc = cbase + ic - tc, rg = gbase + ig - tg, allc = 0, allg = 0;
+#pragma unroll
+        for (int ww = 0; ww < kWaves; ++ww) {
+            if (ww < w) {
+                rc += s_c[ww];
+                rg += s_g[ww];
+            }
+            allc += s_c[ww];
+            allg += s_g[ww];
         }
-        if (i < big_count) {
-            chunk_pref[i] = cbase + s_c[threadIdx.x] - nc;
-            gpref[i] = gbase + s_g[threadIdx.x] - len;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            if (first + q < big_count) {
+                chunk_pref[first + q] = rc;
+                gpref[first + q] = rg;
+            }
+            rc += (len[q] + kBigChunk - 1) / kBigChunk;
+            rg += len[q];
         }
-        cbase += s_c[255];
-        gbase += s_g[255];
-        __syncthreads();
+        cbase += allc;
+        gbase += allg;
+        __syncthreads();  // s_c, s_g are rewritten by the next group
     }
     if (threadIdx.x == 0) {
         chunk_pref[big_count] = cbase;
@@ -262,7 +292,12 @@ hipError_t launch_check_slots(const uint32_t* d_slots, int64_t n, int64_t S, uin
 
 hipError_t launch_big_chunks(const int32_t* d_bigbucket, int64_t big_count, const int64_t* d_start,
                              int64_t* d_chunk_pref, int64_t* d_gpref, hipStream_t st) {
-    hipLaunchKernelGGL(k_big_chunks, dim3(1), dim3(256), 0, st, d_bigbucket, big_count, d_start, d_chunk_pref, d_gpref);
+    if (big_count <= 256)
+        hipLaunchKernelGGL((k_big_chunks<256, 1>), dim3(1), dim3(256), 0, st, d_bigbucket, big_count, d_start,
+                           d_chunk_pref, d_gpref);
+    else
+        hipLaunchKernelGGL((k_big_chunks<1024, 8>), dim3(1), dim3(1024), 0, st, d_bigbucket, big_count, d_start,
+                           d_chunk_pref, d_gpref);
     return hipGetLastError();
 }
 
