@@ -160,9 +160,21 @@ __global__ void __launch_bounds__(256) k_big_gather(const int32_t* __restrict__ 
         const int64_t s0 = start[b], len = start[b + 1] - s0;
         const int64_t c0 = (chunk - chunk_pref[id]) * kBigChunk;
         const int64_t c1 = c0 + kBigChunk < len ? c0 + kBigChunk : len;
-        for (int64_t e = c0 + threadIdx.x; e < c1; e += blockDim.x) {
-            if (G) G[gpref[id] + e] = K[s0 + e];  // no G: the range is sorted where it is
-            atomicAdd(&h[Sl[s0 + e] & (kBucketSlots - 1)], 1u);
+        int64_t e = c0 + threadIdx.x;
+        if (G) {
+            for (; e < c1; e += blockDim.x) {
+                G[gpref[id] + e] = K[s0 + e];
+                atomicAdd(&h[Sl[s0 + e] & (kBucketSlots - 1)], 1u);
+            }
+        } else {  // the range is sorted where it is: slots only, four loads in flight
+            for (; e + 3 * (int64_t)blockDim.x < c1; e += 4 * (int64_t)blockDim.x) {
+                uint32_t v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = Sl[s0 + e + q * (int64_t)blockDim.x];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) atomicAdd(&h[v[q] & (kBucketSlots - 1)], 1u);
+            }
+            for (; e < c1; e += blockDim.x) atomicAdd(&h[Sl[s0 + e] & (kBucketSlots - 1)], 1u);
         }
     }
     __syncthreads();
