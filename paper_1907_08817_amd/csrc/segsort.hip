@@ -145,14 +145,14 @@ __global__ void __launch_bounds__(RUN / kSortPer) k_seg_sort_chunk(const int64_t
     const int cnt = (int)(len - c0 < RUN ? len - c0 : RUN);
     uint64_t* p = G + g0 + c0;
     const int tid = threadIdx.x;
-    // padding with the largest order key: a real key of that value is the
-    // same bit pattern, so the first cnt outputs are right either way
-    for (int i = tid; i < RUN; i += kThreads) s[swz(i)] = i < cnt ? p[i] : ~0ull;
-    __syncthreads();
+    // each thread loads its kSortPer consecutive keys straight into registers
+    // (all loads in flight at once), padded with the largest order key: a
+    // real key of that value is the same bit pattern, so the first cnt
+    // outputs are right either way
     const int base = tid * kSortPer;
     uint64_t v[kSortPer];
 #pragma unroll
-    for (int r = 0; r < kSortPer; ++r) v[r] = s[swz(base + r)];
+    for (int r = 0; r < kSortPer; ++r) v[r] = base + r < cnt ? p[base + r] : ~0ull;
 #pragma unroll
     for (int h = 0; h < kSortPer; h += 8) {
         cswap(v[h + 0], v[h + 2]); cswap(v[h + 1], v[h + 3]); cswap(v[h + 4], v[h + 6]); cswap(v[h + 5], v[h + 7]);
@@ -251,7 +251,19 @@ __global__ void __launch_bounds__(kMergeThreads) k_seg_merge(const int64_t* __re
     const int la = (int)(i1 - i0), lb = (int)((d1 - i1) - (d0 - i0));
     const uint64_t* Aw = A + i0;
     const uint64_t* Bw = B + (d0 - i0);
-    for (int e = tid; e < la + lb; e += kMergeThreads) s[e] = e < la ? Aw[e] : Bw[e - la];
+    {  // all of a thread's loads in flight before its LDS writes
+        uint64_t t[kMergePer];
+#pragma unroll
+        for (int q = 0; q < kMergePer; ++q) {
+            const int e = tid + q * kMergeThreads;
+            t[q] = e < la ? Aw[e] : (e < la + lb ? Bw[e - la] : 0);
+        }
+#pragma unroll
+        for (int q = 0; q < kMergePer; ++q) {
+            const int e = tid + q * kMergeThreads;
+            if (e < la + lb) s[e] = t[q];
+        }
+    }
     __syncthreads();
     // each thread merges kMergePer outputs into registers; they go back to
     // LDS (swizzled against bank conflicts) and out in wave-contiguous order
