@@ -505,17 +505,17 @@ __global__ void __launch_bounds__(NT, CAP <= 2048 ? 7 : 4) k_bucket_polish(
     uint64_t key[kItems];
     uint32_t sl[kItems];
     uint32_t rank[kItems];
+    // every load issued before any is used: no branches between them (items
+    // past cnt read the range's last key again and are never used)
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        if (k * NT >= (int)cnt) break;
         const uint32_t e = tid + k * NT;
-        key[k] = 0;
-        sl[k] = 0;
-        if (e < cnt) {
-            key[k] = rk[e];
-            sl[k] = rs[e] & (kBucketSlots - 1);
-        }
+        const uint32_t ec = e < cnt ? e : cnt - 1;
+        key[k] = rk[ec];
+        sl[k] = rs[ec];
     }
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) sl[k] &= kBucketSlots - 1;
     for (int i = tid; i < (int)kBucketSlots / 2; i += NT) sm.off[i] = 0;
     if (tid == 0) sm.flag = 0;
     __syncthreads();
