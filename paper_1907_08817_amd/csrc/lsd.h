@@ -111,7 +111,13 @@ __global__ void __launch_bounds__(kLsdThreads) k_lsd_upsweep(const uint64_t* __r
 // Scatter of one pass.  hist / chunk: the scanned offsets (a tile's output
 // offset for digit d is hist[t][d] + chunk[t / kScanTiles][d]).  Keys are
 // converted by in_mode on load and by out_mode on store.
-template <bool STABLE, bool PAYLOAD, class D>
+//
+// BATCH: a thread's kLsdItems loads are all issued before the first is
+// ranked, instead of each after the previous item's ranking.  Measured per
+// pass: the stable passes of a three-pass partition (1e9 keys) run 0.6 ms
+// faster each that way, while the two passes at 1e8 keys and the first pass
+// at 1e9 run 4-5% slower, so the partition asks for it only there.
+template <bool STABLE, bool PAYLOAD, class D, bool BATCH = false>
 __global__ void __launch_bounds__(kLsdThreads) k_lsd_downsweep(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ sin, uint64_t* __restrict__ kout,
     uint32_t* __restrict__ sout, int64_t n, int in_mode, int out_mode, D dig, int nbits,
@@ -141,12 +147,26 @@ __global__ void __launch_bounds__(kLsdThreads) k_lsd_downsweep(
     uint64_t key[kLsdItems];
     uint32_t slot[kLsdItems];
     uint32_t rank[kLsdItems];
+    if (BATCH) {  // no branch between the loads: items past the tile's end read its last key again
+#pragma unroll
+        for (int k = 0; k < kLsdItems; ++k) {
+            const int idx = w * (kLsdItems * 64) + k * 64 + lane;
+            const int ic = idx < lim ? idx : lim - 1;
+            key[k] = kb[ic];
+            slot[k] = PAYLOAD ? sb[ic] : 0;
+        }
+    }
 #pragma unroll
     for (int k = 0; k < kLsdItems; ++k) {
         const int idx = w * (kLsdItems * 64) + k * 64 + lane;
         const bool valid = idx < lim;
-        key[k] = to_order_key(valid ? kb[idx] : 0, in_mode);
-        slot[k] = PAYLOAD && valid ? sb[idx] : 0;
+        if (BATCH) {
+            key[k] = to_order_key(valid ? key[k] : 0, in_mode);
+            slot[k] = valid ? slot[k] : 0;
+        } else {
+            key[k] = to_order_key(valid ? kb[idx] : 0, in_mode);
+            slot[k] = PAYLOAD && valid ? sb[idx] : 0;
+        }
         const uint32_t d = dig(key[k], slot[k]);
         if (STABLE) {
             unsigned long long peers = __ballot(valid);

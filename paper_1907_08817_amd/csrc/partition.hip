@@ -274,6 +274,10 @@ hipError_t partition_by_range(const uint64_t* in_keys, const uint32_t* in_slots,
         if (p == 0)
             hipLaunchKernelGGL((k_lsd_downsweep<false, true, RangeDigit>), dim3((unsigned)ntiles), dim3(kLsdThreads),
                                0, st, kin, sin, ko, so, n, im, 0, dig, widths[p], blockhist, chunk, ntiles);
+        else if (passes >= 3)
+            hipLaunchKernelGGL((k_lsd_downsweep<true, true, RangeDigit, true>), dim3((unsigned)ntiles),
+                               dim3(kLsdThreads), 0, st, kin, sin, ko, so, n, im, 0, dig, widths[p], blockhist, chunk,
+                               ntiles);
         else
             hipLaunchKernelGGL((k_lsd_downsweep<true, true, RangeDigit>), dim3((unsigned)ntiles), dim3(kLsdThreads),
                                0, st, kin, sin, ko, so, n, im, 0, dig, widths[p], blockhist, chunk, ntiles);
