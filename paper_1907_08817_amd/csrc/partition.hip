@@ -236,11 +236,16 @@ int range_passes(uint32_t NB, int* shifts, uint32_t* masks, int* widths) {
     while (bits < 32 && ((uint64_t)NB >> bits) != 0) ++bits;  // range ids 0..NB
     int passes = (bits + 7) / 8;
     int per = (bits + passes - 1) / passes;
+    // the first passes take one bit fewer where the bits do not divide
+    // evenly: fewer digits, longer runs per tile for the unstable first pass
+    const int fewer = per * passes - bits;
+    int shift = 0;
     for (int p = 0; p < passes; ++p) {
-        shifts[p] = p * per;
-        int w = bits - p * per < per ? bits - p * per : per;
+        const int w = per - (p < fewer ? 1 : 0);
+        shifts[p] = shift;
         masks[p] = (1u << w) - 1u;
         widths[p] = w;
+        shift += w;
     }
     return passes;
 }
